@@ -1,0 +1,210 @@
+"""Seeded synthetic inputs for the P-SWA wavefront context model.
+
+This module is shared by the FP64 oracle, the tests and the benchmark. It
+holds shapes, seeds and random draws only: none of the context model's
+arithmetic lives here, so the oracle and the HIP path stay independent.
+
+Everything is drawn with NumPy's PCG64 generator in float64 and rounded once
+(to int32 for symbols, to float32 for weights).
+
+Data recipe (a stand-in for the 1080p test sequences the paper evaluates on,
+which are not available):
+  * latent y[i, j, c] = rint(mu[i, j, c] + b[c] * Laplace(0, 1)), with mu a
+    per-channel smooth Gaussian random field (white N(0, 1) noise filtered
+    by a periodic Gaussian kernel of std 2 latent pixels, scaled to std 3)
+    and b[c] log-uniform in [0.2, 4];
+  * hyperprior z[u, v, c] = rint(N(0, 2)), std 2;
+  * previous frames (P-frames): y_tau = y + rint(N(0, 1)), independent for
+    tau = 1 (most recent) and tau = 2.
+
+Weight recipe ("random-init weights from the seed"): linear weights
+N(0, 1/fan_in); norm gains 1; input scale 1/3; sub-position embedding and
+null key/value N(0, 1); relative-position biases N(0, 0.1^2); mean gain 1,
+mean offset 0, scale gain 0.25, scale offset ln 3.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+__all__ = [
+    "ModelCfg", "FrameCfg", "TINY", "FULL", "STUDENT",
+    "bias_sizes", "weight_shapes", "model_weights",
+    "latent_frame", "hyper_frame", "prev_frames", "frame_inputs",
+    "BATCH_MIX", "CONFIG_SEEDS",
+]
+
+
+@dataclasses.dataclass(frozen=True)
+class ModelCfg:
+    """Shape of a context model: L layers of width d with `heads` heads,
+    causal window k x k, SwiGLU hidden width mlp_ratio * d, C latent
+    channels and Ch hyperprior channels."""
+    L: int
+    d: int
+    heads: int
+    window: int
+    mlp_ratio: int
+    C: int
+    Ch: int
+
+    @property
+    def dh(self) -> int:
+        return self.d // self.heads
+
+    @property
+    def F(self) -> int:
+        return self.mlp_ratio * self.d
+
+    @property
+    def r(self) -> int:
+        return (self.window - 1) // 2
+
+
+@dataclasses.dataclass(frozen=True)
+class FrameCfg:
+    """Latent grid H x W (C channels come from the model) and hyperprior grid
+    Hh x Wh; n_prev = 0 for an I-frame, 2 for a P-frame."""
+    H: int
+    W: int
+    n_prev: int = 0
+
+    @property
+    def Hh(self) -> int:
+        return -(-self.H // 4)
+
+    @property
+    def Wh(self) -> int:
+        return -(-self.W // 4)
+
+
+# Tiny intra model: 2 layers, d = 64, 4 heads, causal 5x5 window.
+TINY = ModelCfg(L=2, d=64, heads=4, window=5, mlp_ratio=4, C=32, Ch=16)
+# 1080p model: 6 layers, d = 384, 8 heads of 48, causal 9x9 window.
+FULL = ModelCfg(L=6, d=384, heads=8, window=9, mlp_ratio=4, C=192, Ch=128)
+# Distilled student: 2 layers, d = 128, 4 heads, causal 9x9 window.
+STUDENT = ModelCfg(L=2, d=128, heads=4, window=9, mlp_ratio=4, C=192, Ch=128)
+
+# Batched decode mix: 8 frames of each grid size, I and P alternating.
+BATCH_MIX = [(15, 20), (34, 60), (45, 80), (68, 120)]
+
+# (data seed, weight seed) of each workload.
+CONFIG_SEEDS = {
+    "tiny": (0, 1),
+    "1080p_I": (10, 11),
+    "1080p_P": (20, 11),
+    "batch": (30, 11),
+    "4k_student": (40, 11),
+}
+
+
+def bias_sizes(cfg: ModelCfg) -> tuple[int, int, int]:
+    """Number of relative-bias slots: (accumulator, spatial layer, temporal
+    layer). The causal window holds r rows of 2r+1 above and r to the left
+    (2r(r+1) cells); the layer window adds the query itself; the temporal
+    window is (2r+1)^2 cells in each of two previous frames."""
+    r = cfg.r
+    n_acc = 2 * r * (r + 1)
+    return n_acc, n_acc + 1, 2 * (2 * r + 1) ** 2
+
+
+def weight_shapes(cfg: ModelCfg) -> list[tuple[str, tuple[int, ...]]]:
+    """Ordered (name, shape) list of every parameter. Linear weights are
+    stored [out_features, in_features]."""
+    d, C, Ch, F, h = cfg.d, cfg.C, cfg.Ch, cfg.F, cfg.heads
+    n_acc, n_sp, n_tm = bias_sizes(cfg)
+    out = [
+        ("hyper.W", (d, Ch)), ("hyper.P4", (16, d)),
+        ("in.g", (C,)), ("in.W", (d, C)),
+        ("acc.gq", (d,)), ("acc.Wq", (d, d)),
+        ("acc.gkv", (d,)), ("acc.Wkv", (2 * d, d)),
+        ("acc.knull", (d,)), ("acc.vnull", (d,)),
+        ("acc.bias", (h, n_acc)), ("acc.Wo", (d, d)),
+    ]
+    for l in range(cfg.L):
+        p = f"layer{l}."
+        out += [
+            (p + "g1", (d,)), (p + "Wqkv", (3 * d, d)),
+            (p + "bias", (h, n_sp + n_tm)), (p + "Wo", (d, d)),
+            (p + "g2", (d,)), (p + "Wgate", (F, d)), (p + "Wup", (F, d)),
+            (p + "Wdown", (d, F)),
+        ]
+    out += [
+        ("head.g", (d,)), ("head.W1", (d, d)), ("head.W2", (2 * C, d)),
+        ("head.gmu", (C,)), ("head.bmu", (C,)),
+        ("head.gsig", (C,)), ("head.bsig", (C,)),
+    ]
+    return out
+
+
+def model_weights(cfg: ModelCfg, seed: int) -> dict[str, np.ndarray]:
+    """Random-init float32 weights, drawn in float64 and rounded once."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    w: dict[str, np.ndarray] = {}
+    for name, shape in weight_shapes(cfg):
+        leaf = name.split(".")[-1]
+        if leaf.startswith("W"):
+            a = rng.standard_normal(shape) / math.sqrt(shape[1])
+        elif leaf in ("g", "gq", "gkv", "g1", "g2", "gmu"):
+            a = np.ones(shape)
+        elif leaf == "bias":
+            a = 0.1 * rng.standard_normal(shape)
+        elif leaf in ("P4", "knull", "vnull"):
+            a = rng.standard_normal(shape)
+        elif leaf == "bmu":
+            a = np.zeros(shape)
+        elif leaf == "gsig":
+            a = np.full(shape, 0.25)
+        elif leaf == "bsig":
+            a = np.full(shape, math.log(3.0))
+        else:
+            raise KeyError(name)
+        if name == "in.g":
+            a = np.full(shape, 1.0 / 3.0)
+        w[name] = np.ascontiguousarray(a, dtype=np.float32)
+    return w
+
+
+def _smooth_field(rng, H, W, C, std_px=2.0, target_std=3.0):
+    white = rng.standard_normal((C, H, W))
+    fy = np.fft.fftfreq(H)[:, None]
+    fx = np.fft.fftfreq(W)[None, :]
+    # Fourier transform of a periodic Gaussian kernel of std `std_px`.
+    kern = np.exp(-2.0 * (math.pi * std_px) ** 2 * (fy ** 2 + fx ** 2))
+    f = np.fft.ifft2(np.fft.fft2(white, axes=(1, 2)) * kern, axes=(1, 2)).real
+    sd = f.reshape(C, -1).std(axis=1)
+    f = f * (target_std / np.maximum(sd, 1e-12))[:, None, None]
+    return np.transpose(f, (1, 2, 0))
+
+
+def latent_frame(H: int, W: int, C: int, seed: int) -> np.ndarray:
+    """int32 [H, W, C] latent symbols (see the module recipe)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mu = _smooth_field(rng, H, W, C)
+    b = np.exp(rng.uniform(math.log(0.2), math.log(4.0), size=C))
+    lap = rng.laplace(0.0, 1.0, size=(H, W, C))
+    return np.rint(mu + b[None, None, :] * lap).astype(np.int32)
+
+
+def hyper_frame(Hh: int, Wh: int, Ch: int, seed: int) -> np.ndarray:
+    """int32 [Hh, Wh, Ch] hyperprior symbols, rint(N(0, 2))."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.rint(2.0 * rng.standard_normal((Hh, Wh, Ch))).astype(np.int32)
+
+
+def prev_frames(y: np.ndarray, seed: int) -> np.ndarray:
+    """int32 [2, H, W, C]: y plus independent rint(N(0, 1)) drift per frame."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    drift = np.rint(rng.standard_normal((2,) + y.shape)).astype(np.int32)
+    return (y[None] + drift).astype(np.int32)
+
+
+def frame_inputs(mcfg: ModelCfg, fcfg: FrameCfg, seed: int):
+    """(y, z, prev-or-None) for one frame, all from one data seed: the latent
+    uses `seed`, the hyperprior `seed + 1`, the previous frames `seed + 2`."""
+    y = latent_frame(fcfg.H, fcfg.W, mcfg.C, seed)
+    z = hyper_frame(fcfg.Hh, fcfg.Wh, mcfg.Ch, seed + 1)
+    prev = prev_frames(y, seed + 2) if fcfg.n_prev else None
+    return y, z, prev
