@@ -1,0 +1,222 @@
+/*
+ * pswa.h -- C ABI of the MI355X (gfx950) P-SWA wavefront context model.
+ *
+ * Paper: Kopte and Kaup, "Parallel Context Modeling for Sliding Window
+ * Attention in Neural Video Coding" (arXiv 2605.20977).
+ *
+ * The library predicts, for every symbol of a quantized latent y (H x W x C,
+ * int32), the mean and scale of a Gaussian that drives an arithmetic coder
+ * (Sec. 3.1 and Fig. 1: the prediction heads output mu and sigma), from
+ *   - a hyperprior token per position (Sec. 3.1: the decoded hyperprior is
+ *     the accumulator's query and residual),
+ *   - an accumulator: cross-attention from that token to the already
+ *     decoded neighbours (strictly past positions, Sec. 3.1 and Fig. 2b),
+ *   - L causal sliding-window attention + SwiGLU layers (Sec. 3.1, Llama-2
+ *     style blocks), joined for P-frames by a window over two previous frames,
+ *   - a two-layer head with channel-wise output scales (Sec. 3.1).
+ * Decoding walks a diagonal wavefront (Sec. 2, WPP; Sec. 3.2): position
+ * (i, j) is decoded at step t = j + s*i with s = r + 1 for a k x k causal
+ * window (r = (k-1)/2): the window holds all 2r+1 columns of the r rows above
+ * and the r cells to the left, and every such cell lies on an earlier
+ * diagonal. A frame takes T = (W-1) + s*(H-1) + 1 steps.
+ *
+ * Conventions shared by every call:
+ *   - "d_" pointers are device pointers (HIP global memory), "h_" pointers
+ *     are host pointers. Arrays are C-contiguous, raster order: a latent
+ *     array [H][W][C] holds symbol (i, j, c) at (i*W + j)*C + c.
+ *   - The caller owns all device memory (the model's weights region, the
+ *     encode workspace, the decode state) and passes pointer + size; the
+ *     library never calls hipMalloc/hipFree. Opaque handles are host objects
+ *     owned by the library and freed by the matching *_destroy call.
+ *   - `stream` is a hipStream_t (NULL = the null stream). All device work of
+ *     a call is enqueued on it. A call returns before that work finishes
+ *     unless it documents a wait.
+ *   - Every call returns a pswa_status; no C++ exception crosses the ABI.
+ *     pswa_last_error() returns the calling thread's last message. Argument
+ *     and shape checks run before any HIP call.
+ *   - Determinism: for one model and precision, pswa_encode_params and the
+ *     pswa_decode_step sequence produce bit-identical mean, scale, bits,
+ *     centre and table index (every kernel is shared and each row's
+ *     reduction order does not depend on how many rows run together).
+ */
+#ifndef PSWA_H
+#define PSWA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PSWA_OK = 0,
+  PSWA_E_ARG = -1,         /* null pointer, bad enum, buffer too small   */
+  PSWA_E_SHAPE = -2,       /* inconsistent sizes (e.g. Hh != ceil(H/4))  */
+  PSWA_E_ORDER = -3,       /* decode_step called out of order            */
+  PSWA_E_HIP = -4,         /* a HIP runtime call failed                  */
+  PSWA_E_UNSUPPORTED = -5, /* valid request this build does not serve    */
+  PSWA_E_CORRUPT = -6,     /* bitstream truncated or inconsistent        */
+  PSWA_E_NUMERIC = -7      /* a non-finite mean/scale was produced       */
+} pswa_status;
+
+typedef enum { PSWA_FP32 = 0, PSWA_BF16 = 1, PSWA_FP8_E4M3 = 2 } pswa_precision;
+
+enum { PSWA_SRC_DEVICE = 0, PSWA_SRC_BITSTREAM = 1 };
+
+/* Model shape. window is odd (3..9); d a multiple of 64, <= 1024; head dim
+ * d / heads in {16, 32, 48, 64}; mlp_ratio * d <= 2048; C a multiple of 4,
+ * <= 256; Ch <= 512. Other shapes are rejected with PSWA_E_ARG. */
+typedef struct {
+  int32_t L, d, heads, window, mlp_ratio, C, Ch;
+  int32_t prec; /* pswa_precision */
+} pswa_model_desc;
+
+/* Frame shape. Hh = ceil(H/4), Wh = ceil(W/4) (the hyperprior is at a
+ * quarter of the latent resolution, Fig. 1); n_prev = 0 (I-frame) or 2
+ * (P-frame with the two previous latents). */
+typedef struct {
+  int32_t H, W, Hh, Wh, n_prev;
+} pswa_frame_desc;
+
+typedef struct pswa_model pswa_model;
+typedef struct pswa_state pswa_state;
+
+/* ---------------------------------------------------------------- model */
+
+/* Number of float32 values in a weight blob for `desc`. The blob is the
+ * concatenation, in this order, of (linear weights are [out][in]):
+ *   hyper.W [d][Ch], hyper.P4 [16][d], in.g [C], in.W [d][C],
+ *   acc.gq [d], acc.Wq [d][d], acc.gkv [d], acc.Wkv [2d][d], acc.knull [d],
+ *   acc.vnull [d], acc.bias [heads][2r(r+1)], acc.Wo [d][d],
+ *   per layer l = 0..L-1: g1 [d], Wqkv [3d][d], bias [heads][nS + nT],
+ *     Wo [d][d], g2 [d], Wgate [F][d], Wup [F][d], Wdown [d][F],
+ *   head.g [d], head.W1 [d][d], head.W2 [2C][d], head.gmu [C], head.bmu [C],
+ *   head.gsig [C], head.bsig [C];
+ * with r = (window-1)/2, F = mlp_ratio*d, nS = 2r(r+1)+1 spatial bias slots
+ * (the causal window in row-major order, then the query itself) and
+ * nT = 2(2r+1)^2 temporal slots (previous frame 1 then 2, each its full
+ * window in row-major order). Returns 0 for an invalid desc. */
+size_t pswa_model_blob_floats(const pswa_model_desc* desc);
+
+/* Device bytes the model needs (weights plus their low-precision copies). */
+size_t pswa_model_device_bytes(const pswa_model_desc* desc);
+
+/* Upload a blob into caller-owned device memory d_mem (>= device_bytes,
+ * 256-byte aligned). Waits for the upload (the blob may be freed on return).
+ * For PSWA_BF16 / PSWA_FP8_E4M3 the projection and MLP weights are rounded
+ * once (RNE; FP8 saturating, one static scale per tensor). */
+pswa_status pswa_model_create(const pswa_model_desc* desc, const float* h_blob,
+                              size_t blob_floats, void* d_mem, size_t d_bytes,
+                              void* stream, pswa_model** out);
+void pswa_model_destroy(pswa_model* model);
+
+/* ------------------------------------------------- encode (parallel form) */
+
+size_t pswa_encode_workspace_bytes(const pswa_model* model,
+                                   const pswa_frame_desc* frame);
+
+/* Every position at once (the decoder's arithmetic, row for row).
+ *   d_latents [H][W][C] int32, d_hyper [Hh][Wh][Ch] int32,
+ *   d_prev [2][H][W][C] int32 (frame 1 = most recent) or NULL for I-frames;
+ *   outputs [H][W][C]: d_mean, d_scale (float), d_bits (float, -log2 of the
+ *   discretized-Gaussian mass, floored at 1e-9), d_cdf_center (int32) and
+ *   d_cdf_index (uint16: table scale*16 + phase, see pswa_cdf_tables).
+ *   h_total_bits: if non-NULL, waits and stores the sum of d_bits; the wait
+ *   also reports PSWA_E_NUMERIC if any mean/scale was non-finite.
+ *   d_ws: workspace of pswa_encode_workspace_bytes, 256-byte aligned. */
+pswa_status pswa_encode_params(const pswa_model* model, const pswa_frame_desc* frame,
+                               const int32_t* d_latents, const int32_t* d_hyper,
+                               const int32_t* d_prev, float* d_mean, float* d_scale,
+                               float* d_bits, int32_t* d_cdf_center,
+                               uint16_t* d_cdf_index, double* h_total_bits,
+                               void* d_ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- decode */
+
+size_t pswa_state_bytes(const pswa_model* model, const pswa_frame_desc* frame);
+
+/* Start decoding one frame: builds the hyperprior tokens and, for P-frames,
+ * the per-layer keys/values of the two previous latents.
+ *   symbol_source = PSWA_SRC_DEVICE: src is d_latents [H][W][C] int32 on the
+ *     device; each step copies the symbols of its diagonal from there (the
+ *     model-limited mode used for throughput and encode-by-decode checks).
+ *   symbol_source = PSWA_SRC_BITSTREAM: src is a host byte array of
+ *     src_bytes written by pswa_range_encode; each step waits for its CDF
+ *     selections, range-decodes the diagonal on the CPU and uploads it.
+ *   d_state_mem: pswa_state_bytes, 256-byte aligned, owned by the caller and
+ *   untouched by anyone else until pswa_state_destroy. */
+pswa_status pswa_decode_begin(const pswa_model* model, const pswa_frame_desc* frame,
+                              const int32_t* d_hyper, const int32_t* d_prev,
+                              int symbol_source, const void* src, size_t src_bytes,
+                              void* d_state_mem, size_t state_bytes, void* stream,
+                              pswa_state** out);
+
+/* Number of wavefront steps T of the frame. */
+int pswa_num_steps(const pswa_state* state);
+
+/* Decode diagonal t = {(i, t - s*i)}: accumulator, L layers and head for
+ * its positions, then the symbols (from the chosen source) and the
+ * accumulator keys/values of the decoded positions. Steps must be called
+ * for t = 0, 1, ..., T-1 in order, else PSWA_E_ORDER. */
+pswa_status pswa_decode_step(pswa_state* state, int t, void* stream);
+
+/* After the last step: copy out the decoded latents and (each optional,
+ * NULL to skip) the per-symbol outputs, laid out as in pswa_encode_params.
+ * h_total_bits waits as in pswa_encode_params. */
+pswa_status pswa_decode_end(pswa_state* state, int32_t* d_latents_out, float* d_mean,
+                            float* d_scale, float* d_bits, int32_t* d_cdf_center,
+                            uint16_t* d_cdf_index, double* h_total_bits, void* stream);
+void pswa_state_destroy(pswa_state* state);
+
+/* ---------------------------------------------------------- entropy side */
+
+/* Table selection of n symbols from their mean and log-scale (float32
+ * decision, one rounding per operation):
+ *   centre c = floor(mu + 0.5); phase m = min(15, floor((mu - c + 0.5)*16));
+ *   scale s = clamp(floor((ln_sigma - ln 0.11) * (63 / ln(64/0.11)) + 0.5), 0, 63);
+ *   index = s*16 + m. */
+pswa_status pswa_cdf_select(const float* d_mean, const float* d_log_scale, size_t n,
+                            int32_t* d_center, uint16_t* d_index, void* stream);
+
+/* The 1024 integer CDF tables (16-bit precision) on the host. Table
+ * x = s*16 + m covers offsets -R..R from the centre plus an escape bin:
+ * h_radius[x] = R, and its 2R+2 frequencies sit at h_freq[h_offset[x] ..].
+ * Each frequency is max(1, floor(pmf * (65536 - n_bins))) of the float64
+ * Gaussian mass with scale 0.11*exp(s*Delta), Delta = ln(64/0.11)/63, and
+ * mean offset (m + 0.5)/16 - 0.5 (escape bin: both tails), and the rest of
+ * 65536 goes to the largest bin (lowest index on ties).
+ * h_offset holds 1025 entries; freq_cap is the capacity of h_freq in
+ * entries (pass 0 with h_freq NULL to query the needed size in *h_offset[1024]). */
+pswa_status pswa_cdf_tables(uint32_t* h_radius, uint32_t* h_offset, uint16_t* h_freq,
+                            size_t freq_cap);
+
+/* Range-code a frame's symbols in decode order (steps t = 0..T-1, rows i
+ * ascending within a step, channels 0..C-1), each with its table: symbol
+ * v is coded as bin v - c + R when |v - c| <= R, else as the escape bin
+ * followed by the sign and an order-0 Exp-Golomb code of |v - c| - R - 1
+ * in equiprobable bits. All arrays are host [H][W][C]. window is the
+ * model's window (it fixes the slope s). Writes at most cap bytes to out. */
+pswa_status pswa_range_encode(const pswa_frame_desc* frame, int32_t C, int32_t window,
+                              const int32_t* h_symbols, const int32_t* h_center,
+                              const uint16_t* h_index, uint8_t* out, size_t cap,
+                              size_t* out_bytes);
+
+/* Decode n symbols coded with the given centres/indices (same coding as
+ * above, in the given order); a host-only check of the coder. */
+pswa_status pswa_range_decode_seq(const uint8_t* in, size_t in_bytes, size_t n,
+                                  const int32_t* h_center, const uint16_t* h_index,
+                                  int32_t* h_symbols_out);
+
+/* Encode n symbols in the given order (the counterpart of the above). */
+pswa_status pswa_range_encode_seq(size_t n, const int32_t* h_symbols,
+                                  const int32_t* h_center, const uint16_t* h_index,
+                                  uint8_t* out, size_t cap, size_t* out_bytes);
+
+const char* pswa_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSWA_H */

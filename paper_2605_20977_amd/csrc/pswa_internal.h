@@ -1,0 +1,153 @@
+// Internal interfaces between the C ABI / runtime (pswa_capi.cpp), the HIP
+// kernels (kernels_*.hip) and the host entropy coder (coder.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace pswa {
+
+// ------------------------------------------------------------------ GEMM
+// Y[m][n] = epilogue( sum_k A[m][k] * W[n][k] ), accumulated k = 0..K-1 in
+// order by one thread per output, so a row's value never depends on how many
+// rows are in the launch or how they are tiled.
+enum AKind { A_FLOAT = 0, A_INT = 1 };
+enum Epi {
+  EPI_STORE = 0,   // Y[yrow(m)][n] = acc
+  EPI_RESID = 1,   // Y[yrow(m)][n] = R[rrow(m)][n] + acc
+  EPI_QKV = 2,     // n < nsplit: Y[m][n] = acc; else Y2[y2row(m)][n - nsplit] = acc
+  EPI_SILU = 3,    // Y[yrow(m)][n] = silu(acc)
+  EPI_SWIGLU = 4,  // Y[yrow(m)][n] = silu(acc(W)) * acc(W2)
+  EPI_HEAD = 5     // mean/scale/centre/index from acc(W) (mean) and acc(W2) (scale)
+};
+
+struct HeadOut {
+  const float *gmu, *bmu, *gsig, *bsig;  // [C]
+  float ln_smin, ln_smax, inv_delta;
+  float *mean, *scale;                   // [HW][C] rows yrow(m)
+  int32_t* center;                       // [HW][C]
+  uint16_t* index;                       // [HW][C]
+  int32_t* center_c;                     // compact [M][C] copies (or null)
+  uint16_t* index_c;
+  int* flag;                             // set to 1 on a non-finite mean/scale
+};
+
+struct GemmArgs {
+  int M, N, K;
+  const float* X = nullptr;              // A_FLOAT: row m at X + xrow(m)*ldx
+  const int32_t* Xi = nullptr;           // A_INT:   row m at Xi + xrow(m)*ldx, times xscale[k]
+  const float* xscale = nullptr;
+  int ldx = 0;
+  const int* xrow = nullptr;             // null: identity
+  const float* gain = nullptr;           // RMSNorm prologue gain (null: none)
+  const float* W = nullptr;              // [N][K]
+  const float* W2 = nullptr;             // paired epilogues: second [N][K]
+  float* Y = nullptr;
+  int ldy = 0;
+  const int* yrow = nullptr;
+  const float* R = nullptr;
+  int ldr = 0;
+  const int* rrow = nullptr;
+  float* Y2 = nullptr;
+  int ldy2 = 0;
+  const int* y2row = nullptr;
+  int nsplit = 0;
+  HeadOut head{};
+};
+
+void gemm_f32(AKind ak, bool rms, Epi epi, const GemmArgs& a, hipStream_t s);
+
+// ------------------------------------------------------------- attention
+struct AttnArgs {
+  int M;                       // query rows
+  const int* pos;              // flat position i*W + j of row m (null: m)
+  int H, W, r, heads, dh, d;
+  const float* q; int ldq;     // [M][d]
+  const float* kv;             // [HW][2d]: K then V per position
+  const float* tkv;            // [2][HW][2d] temporal K/V (or null)
+  const float* bias; int nbias;  // [heads][nbias]
+  const float* knull;          // accumulator null slot (null in layer mode)
+  const float* vnull;
+  int include_self;            // layer mode: the query's own key
+  float* out; int ldo;         // [M][d]
+};
+void attention_f32(const AttnArgs& a, hipStream_t s);
+
+// ----------------------------------------------------------------- misc
+void hyper_embed(const int32_t* z, int Hh, int Wh, int Ch, const float* Wh_, const float* P4,
+                 int H, int W, int d, float* h, hipStream_t s);
+// ydec[pos(m)][c] = src[(compact ? m : pos(m))][c]
+void gather_symbols(const int32_t* src, int compact, const int* pos, int M, int C,
+                    int32_t* ydec, hipStream_t s);
+// bits[pos(m)][c] = -log2(max(P, 1e-9)) of ydec under N(mean, scale)
+void symbol_bits(const int* pos, int M, int C, const int32_t* ydec, const float* mean,
+                 const float* scale, float* bits, hipStream_t s);
+// out[0] = sum of v[0..n) (fixed order, float32 with compensation)
+void sum_f32(const float* v, size_t n, float* out, hipStream_t s);
+void cdf_select(const float* mean, const float* lsig, size_t n, float ln_smin,
+                float inv_delta, int32_t* center, uint16_t* index, hipStream_t s);
+void fill_positions(int H, int W, int s, int* pos_all, hipStream_t st);
+
+// -------------------------------------------------------- entropy coder
+constexpr int kScales = 64;
+constexpr int kPhases = 16;
+constexpr int kTables = kScales * kPhases;
+constexpr int kPrecBits = 16;
+constexpr double kSigmaMin = 0.11;
+constexpr double kSigmaMax = 64.0;
+
+struct CdfTables {
+  std::vector<uint32_t> radius;  // [kTables]
+  std::vector<uint32_t> offset;  // [kTables + 1] into freq / cum (cum has +1 per table)
+  std::vector<uint16_t> freq;    // frequencies
+  std::vector<uint32_t> cum_off; // [kTables] offset into cum
+  std::vector<uint32_t> cum;     // cumulative, 2R+3 entries per table
+};
+const CdfTables& cdf_tables();
+float ln_sigma_min_f32();
+float inv_delta_f32();
+
+class RangeEncoder {
+ public:
+  RangeEncoder(uint8_t* out, size_t cap) : out_(out), cap_(cap) {}
+  void encode(uint32_t start, uint32_t size);
+  void bit(uint32_t b);
+  void symbol(int32_t v, int32_t center, uint16_t index);
+  void finish();
+  size_t bytes() const { return n_; }
+  bool overflow() const { return overflow_; }
+
+ private:
+  void shift_low();
+  void put(uint8_t b);
+  uint8_t* out_;
+  size_t cap_, n_ = 0;
+  bool overflow_ = false;
+  uint64_t low_ = 0;
+  uint32_t range_ = 0xFFFFFFFFu;
+  uint8_t cache_ = 0;
+  uint64_t cache_size_ = 1;
+};
+
+class RangeDecoder {
+ public:
+  RangeDecoder(const uint8_t* in, size_t n);
+  // false on a corrupt or truncated stream
+  bool symbol(int32_t center, uint16_t index, int32_t* v);
+  bool ok() const { return ok_; }
+
+ private:
+  uint32_t next();
+  bool bit(uint32_t* b);
+  const uint8_t* in_;
+  size_t n_, p_ = 0;
+  uint32_t range_ = 0xFFFFFFFFu, code_ = 0;
+  bool ok_ = true;
+  size_t overrun_ = 0;
+};
+
+}  // namespace pswa

@@ -1,0 +1,379 @@
+"""Thin Python binding of libpswa.so (the C ABI in include/pswa.h).
+
+Argument marshalling only: every step of the context model runs in the HIP
+library. PyTorch provides device memory (tensors) and the current stream.
+The functions keep the C names; each raises PswaError on a non-OK status.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+# torch first: the library must bind to the HIP runtime torch already loaded
+# (same soname), so that tensors, streams and kernels share one runtime.
+import torch  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpswa.so")
+
+PSWA_FP32, PSWA_BF16, PSWA_FP8_E4M3 = 0, 1, 2
+PSWA_SRC_DEVICE, PSWA_SRC_BITSTREAM = 0, 1
+STATUS = {0: "OK", -1: "E_ARG", -2: "E_SHAPE", -3: "E_ORDER", -4: "E_HIP",
+          -5: "E_UNSUPPORTED", -6: "E_CORRUPT", -7: "E_NUMERIC"}
+PRECISIONS = {"fp32": PSWA_FP32, "bf16": PSWA_BF16, "fp8": PSWA_FP8_E4M3}
+
+
+class PswaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"pswa {STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class ModelDesc(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in
+                ("L", "d", "heads", "window", "mlp_ratio", "C", "Ch", "prec")]
+
+
+class FrameDesc(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("H", "W", "Hh", "Wh", "n_prev")]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is not built: run `python -m paper_2605_20977_amd.build` "
+            "(there is no CPU fallback)")
+    lib = C.CDLL(LIB_PATH)
+    vp, sz, i32 = C.c_void_p, C.c_size_t, C.c_int
+    P = C.POINTER
+    sig = {
+        "pswa_model_blob_floats": (sz, [P(ModelDesc)]),
+        "pswa_model_device_bytes": (sz, [P(ModelDesc)]),
+        "pswa_model_create": (i32, [P(ModelDesc), vp, sz, vp, sz, vp, P(vp)]),
+        "pswa_model_destroy": (None, [vp]),
+        "pswa_encode_workspace_bytes": (sz, [vp, P(FrameDesc)]),
+        "pswa_encode_params": (i32, [vp, P(FrameDesc), vp, vp, vp, vp, vp, vp, vp, vp,
+                                     P(C.c_double), vp, sz, vp]),
+        "pswa_state_bytes": (sz, [vp, P(FrameDesc)]),
+        "pswa_decode_begin": (i32, [vp, P(FrameDesc), vp, vp, i32, vp, sz, vp, sz, vp, P(vp)]),
+        "pswa_num_steps": (i32, [vp]),
+        "pswa_decode_step": (i32, [vp, i32, vp]),
+        "pswa_decode_end": (i32, [vp, vp, vp, vp, vp, vp, vp, P(C.c_double), vp]),
+        "pswa_state_destroy": (None, [vp]),
+        "pswa_cdf_select": (i32, [vp, vp, sz, vp, vp, vp]),
+        "pswa_cdf_tables": (i32, [vp, vp, vp, sz]),
+        "pswa_range_encode": (i32, [P(FrameDesc), C.c_int32, C.c_int32, vp, vp, vp, vp, sz,
+                                    P(sz)]),
+        "pswa_range_encode_seq": (i32, [sz, vp, vp, vp, vp, sz, P(sz)]),
+        "pswa_range_decode_seq": (i32, [vp, sz, sz, vp, vp, vp]),
+        "pswa_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+EXPORTED = ("pswa_model_blob_floats", "pswa_model_device_bytes", "pswa_model_create",
+            "pswa_model_destroy", "pswa_encode_workspace_bytes", "pswa_encode_params",
+            "pswa_state_bytes", "pswa_decode_begin", "pswa_num_steps", "pswa_decode_step",
+            "pswa_decode_end", "pswa_state_destroy", "pswa_cdf_select", "pswa_cdf_tables",
+            "pswa_range_encode", "pswa_range_encode_seq", "pswa_range_decode_seq",
+            "pswa_last_error")
+
+
+def lib():
+    return _lib
+
+
+def _check(st):
+    if st != 0:
+        raise PswaError(st, _lib.pswa_last_error().decode())
+
+
+def _ptr(t):
+    """Device/host address of a tensor or numpy array (None -> NULL)."""
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ------------------------------------------------------------------ shapes
+
+def model_desc(cfg, prec="fp32") -> ModelDesc:
+    return ModelDesc(cfg.L, cfg.d, cfg.heads, cfg.window, cfg.mlp_ratio, cfg.C, cfg.Ch,
+                     PRECISIONS[prec] if isinstance(prec, str) else int(prec))
+
+
+def frame_desc(H, W, n_prev=0) -> FrameDesc:
+    return FrameDesc(H, W, -(-H // 4), -(-W // 4), n_prev)
+
+
+def blob_order(cfg) -> list[str]:
+    """Parameter names in the blob order the header documents."""
+    names = ["hyper.W", "hyper.P4", "in.g", "in.W", "acc.gq", "acc.Wq", "acc.gkv",
+             "acc.Wkv", "acc.knull", "acc.vnull", "acc.bias", "acc.Wo"]
+    for l in range(cfg.L):
+        names += [f"layer{l}.{n}" for n in
+                  ("g1", "Wqkv", "bias", "Wo", "g2", "Wgate", "Wup", "Wdown")]
+    names += ["head.g", "head.W1", "head.W2", "head.gmu", "head.bmu", "head.gsig",
+              "head.bsig"]
+    return names
+
+
+def pack_blob(cfg, weights) -> np.ndarray:
+    return np.concatenate([np.asarray(weights[n], dtype=np.float32).ravel()
+                           for n in blob_order(cfg)])
+
+
+# ------------------------------------------------------------------- model
+
+class Model:
+    """A model uploaded into a torch-owned device region."""
+
+    def __init__(self, cfg, weights, prec="fp32", device="cuda"):
+        import torch
+        self.cfg = cfg
+        self.desc = model_desc(cfg, prec)
+        blob = pack_blob(cfg, weights)
+        need = _lib.pswa_model_blob_floats(C.byref(self.desc))
+        if need != blob.size:
+            raise PswaError(-2, f"blob has {blob.size} floats, library expects {need}")
+        nbytes = _lib.pswa_model_device_bytes(C.byref(self.desc))
+        self.mem = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        h = C.c_void_p()
+        _check(_lib.pswa_model_create(C.byref(self.desc), blob.ctypes.data, blob.size,
+                                      _ptr(self.mem), nbytes, _stream(), C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.pswa_model_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+
+def _i32(t, device):
+    import torch
+    if isinstance(t, np.ndarray):
+        t = torch.from_numpy(np.ascontiguousarray(t, dtype=np.int32))
+    return t.to(device=device, dtype=torch.int32).contiguous()
+
+
+def _shape_check(model, y=None, z=None, prev=None, H=None, W=None):
+    """Refuse mis-shaped tensors before any pointer reaches the library."""
+    cfg = model.cfg
+    if y is not None:
+        if y.dim() != 3 or y.shape[2] != cfg.C:
+            raise PswaError(-2, f"latents must be [H][W][{cfg.C}], got {tuple(y.shape)}")
+        H, W = y.shape[0], y.shape[1]
+    if z is not None and tuple(z.shape) != (-(-H // 4), -(-W // 4), cfg.Ch):
+        raise PswaError(-2, f"hyperprior must be [{-(-H // 4)}][{-(-W // 4)}][{cfg.Ch}], "
+                            f"got {tuple(z.shape)}")
+    if prev is not None and tuple(prev.shape) != (2, H, W, cfg.C):
+        raise PswaError(-2, f"previous latents must be [2][{H}][{W}][{cfg.C}], "
+                            f"got {tuple(prev.shape)}")
+
+
+def _outputs(H, W, Cc, device):
+    import torch
+    n = (H, W, Cc)
+    return {
+        "mean": torch.empty(n, dtype=torch.float32, device=device),
+        "scale": torch.empty(n, dtype=torch.float32, device=device),
+        "bits": torch.empty(n, dtype=torch.float32, device=device),
+        "center": torch.empty(n, dtype=torch.int32, device=device),
+        "index": torch.empty(n, dtype=torch.int16, device=device),  # holds uint16 bits
+    }
+
+
+def pswa_encode_params(model: Model, latents, hyper, prev=None, total_bits=True, ws=None):
+    """Parallel encode form. Returns dict of device tensors (index holds the
+    uint16 table index in an int16 tensor; use index_u16()) and 'total_bits'."""
+    import torch
+    dev = model.mem.device
+    y = _i32(latents, dev)
+    z = _i32(hyper, dev)
+    H, W, Cc = y.shape
+    pv = _i32(prev, dev) if prev is not None else None
+    _shape_check(model, y, z, pv)
+    fd = frame_desc(H, W, 2 if pv is not None else 0)
+    nws = _lib.pswa_encode_workspace_bytes(model.handle, C.byref(fd))
+    if nws == 0:
+        raise PswaError(-2, "invalid frame for this model")
+    if ws is None or ws.numel() < nws:
+        ws = torch.empty(nws, dtype=torch.uint8, device=dev)
+    out = _outputs(H, W, Cc, dev)
+    tot = C.c_double(0.0)
+    _check(_lib.pswa_encode_params(
+        model.handle, C.byref(fd), _ptr(y), _ptr(z), _ptr(pv), _ptr(out["mean"]),
+        _ptr(out["scale"]), _ptr(out["bits"]), _ptr(out["center"]), _ptr(out["index"]),
+        C.byref(tot) if total_bits else None, _ptr(ws), ws.numel(), _stream()))
+    if total_bits:
+        out["total_bits"] = tot.value
+    return out
+
+
+class State:
+    def __init__(self, handle, mem, keep):
+        self.handle = handle
+        self.mem = mem
+        self._keep = keep
+        self.T = _lib.pswa_num_steps(handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.pswa_state_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+
+def pswa_state_bytes(model: Model, H, W, n_prev=0):
+    fd = frame_desc(H, W, n_prev)
+    return _lib.pswa_state_bytes(model.handle, C.byref(fd))
+
+
+def pswa_decode_begin(model: Model, H, W, hyper, prev=None, source="device", src=None,
+                      mem=None):
+    """src: device latents (source='device') or bytes (source='bitstream')."""
+    import torch
+    dev = model.mem.device
+    z = _i32(hyper, dev)
+    pv = _i32(prev, dev) if prev is not None else None
+    _shape_check(model, None, z, pv, H, W)
+    fd = frame_desc(H, W, 2 if pv is not None else 0)
+    nb = _lib.pswa_state_bytes(model.handle, C.byref(fd))
+    if nb == 0:
+        raise PswaError(-2, "invalid frame for this model")
+    if mem is None or mem.numel() < nb:
+        mem = torch.empty(nb, dtype=torch.uint8, device=dev)
+    keep = [z, pv]
+    if source == "device":
+        s = _i32(src, dev)
+        if tuple(s.shape) != (H, W, model.cfg.C):
+            raise PswaError(-2, f"device symbol source must be [{H}][{W}][{model.cfg.C}]")
+        keep.append(s)
+        kind, sp, sn = PSWA_SRC_DEVICE, _ptr(s), s.numel() * 4
+    elif source == "bitstream":
+        buf = np.frombuffer(bytes(src), dtype=np.uint8).copy()
+        keep.append(buf)
+        kind, sp, sn = PSWA_SRC_BITSTREAM, buf.ctypes.data, buf.size
+    else:
+        raise ValueError(source)
+    h = C.c_void_p()
+    _check(_lib.pswa_decode_begin(model.handle, C.byref(fd), _ptr(z), _ptr(pv), kind, sp, sn,
+                                  _ptr(mem), mem.numel(), _stream(), C.byref(h)))
+    return State(h, mem, keep)
+
+
+def pswa_num_steps(state: State) -> int:
+    return _lib.pswa_num_steps(state.handle)
+
+
+def pswa_decode_step(state: State, t: int):
+    _check(_lib.pswa_decode_step(state.handle, t, _stream()))
+
+
+def pswa_decode_end(state: State, H, W, Cc, total_bits=True):
+    import torch
+    dev = state.mem.device
+    out = _outputs(H, W, Cc, dev)
+    out["latents"] = torch.empty((H, W, Cc), dtype=torch.int32, device=dev)
+    tot = C.c_double(0.0)
+    _check(_lib.pswa_decode_end(state.handle, _ptr(out["latents"]), _ptr(out["mean"]),
+                                _ptr(out["scale"]), _ptr(out["bits"]), _ptr(out["center"]),
+                                _ptr(out["index"]), C.byref(tot) if total_bits else None,
+                                _stream()))
+    if total_bits:
+        out["total_bits"] = tot.value
+    return out
+
+
+def decode_frame(model: Model, H, W, hyper, prev=None, source="device", src=None, mem=None):
+    st = pswa_decode_begin(model, H, W, hyper, prev, source, src, mem)
+    for t in range(st.T):
+        pswa_decode_step(st, t)
+    out = pswa_decode_end(st, H, W, model.cfg.C)
+    st.close()
+    return out
+
+
+def index_u16(t):
+    """uint16 numpy view of an index tensor."""
+    return t.cpu().numpy().view(np.uint16)
+
+
+# ------------------------------------------------------------ entropy side
+
+def pswa_cdf_select(mean, log_scale):
+    import torch
+    n = mean.numel()
+    c = torch.empty(n, dtype=torch.int32, device=mean.device)
+    i = torch.empty(n, dtype=torch.int16, device=mean.device)
+    _check(_lib.pswa_cdf_select(_ptr(mean), _ptr(log_scale), n, _ptr(c), _ptr(i), _stream()))
+    return c, i
+
+
+def pswa_cdf_tables():
+    """(radius uint32 [1024], offset uint32 [1025], freq uint16 [..]) on the host."""
+    off = np.zeros(1025, np.uint32)
+    rad = np.zeros(1024, np.uint32)
+    _check(_lib.pswa_cdf_tables(rad.ctypes.data, off.ctypes.data, None, 0))
+    freq = np.zeros(int(off[1024]), np.uint16)
+    _check(_lib.pswa_cdf_tables(rad.ctypes.data, off.ctypes.data, freq.ctypes.data, freq.size))
+    return rad, off, freq
+
+
+def _u8cap(n_symbols):
+    return 64 + 8 * n_symbols
+
+
+def pswa_range_encode(H, W, Cc, window, symbols, center, index) -> bytes:
+    fd = frame_desc(H, W, 0)
+    sy = np.ascontiguousarray(symbols, dtype=np.int32)
+    ce = np.ascontiguousarray(center, dtype=np.int32)
+    ix = np.ascontiguousarray(index).view(np.uint16)
+    cap = _u8cap(sy.size)
+    out = np.empty(cap, np.uint8)
+    nb = C.c_size_t(0)
+    _check(_lib.pswa_range_encode(C.byref(fd), Cc, window, sy.ctypes.data, ce.ctypes.data,
+                                  ix.ctypes.data, out.ctypes.data, cap, C.byref(nb)))
+    return out[:nb.value].tobytes()
+
+
+def pswa_range_encode_seq(symbols, center, index) -> bytes:
+    sy = np.ascontiguousarray(symbols, dtype=np.int32).ravel()
+    ce = np.ascontiguousarray(center, dtype=np.int32).ravel()
+    ix = np.ascontiguousarray(index).view(np.uint16).ravel()
+    cap = _u8cap(sy.size)
+    out = np.empty(cap, np.uint8)
+    nb = C.c_size_t(0)
+    _check(_lib.pswa_range_encode_seq(sy.size, sy.ctypes.data, ce.ctypes.data, ix.ctypes.data,
+                                      out.ctypes.data, cap, C.byref(nb)))
+    return out[:nb.value].tobytes()
+
+
+def pswa_range_decode_seq(data: bytes, center, index):
+    ce = np.ascontiguousarray(center, dtype=np.int32).ravel()
+    ix = np.ascontiguousarray(index).view(np.uint16).ravel()
+    buf = np.frombuffer(data, dtype=np.uint8).copy()
+    out = np.empty(ce.size, np.int32)
+    _check(_lib.pswa_range_decode_seq(buf.ctypes.data if buf.size else None, buf.size,
+                                      ce.size, ce.ctypes.data, ix.ctypes.data,
+                                      out.ctypes.data))
+    return out

@@ -175,7 +175,10 @@ def _smooth_field(rng, H, W, C, std_px=2.0, target_std=3.0):
     kern = np.exp(-2.0 * (math.pi * std_px) ** 2 * (fy ** 2 + fx ** 2))
     f = np.fft.ifft2(np.fft.fft2(white, axes=(1, 2)) * kern, axes=(1, 2)).real
     sd = f.reshape(C, -1).std(axis=1)
-    f = f * (target_std / np.maximum(sd, 1e-12))[:, None, None]
+    # a one-pixel grid has no spread: its field is the constant 0
+    gain = np.where(sd > 1e-9, target_std / np.maximum(sd, 1e-9), 0.0)
+    f = (f - f.reshape(C, -1).mean(axis=1)[:, None, None] * (sd <= 1e-9)[:, None, None]) \
+        * gain[:, None, None]
     return np.transpose(f, (1, 2, 0))
 
 

@@ -1,0 +1,215 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Bar (FP32 path): mean |d mu| / max(|mu|, 1) <= 1e-4, scale relative error
+<= 1e-4, total bits relative error <= 1e-3; centres/table indices equal to
+the oracle's float32 decision except on ties within the mean/scale error
+budget; encode and every decode mode bit-identical.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import entropy as oe
+from oracle import model as om
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+MU_TOL = 1e-4
+SIG_TOL = 1e-4
+BITS_TOL = 1e-3
+
+
+def _pswa():
+    from paper_2605_20977_amd import pswa
+    return pswa
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return _pswa()
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def assert_matches_oracle(out, ref, y, label=""):
+    mu, sig = _np(out["mean"]).astype(np.float64), _np(out["scale"]).astype(np.float64)
+    emu = np.abs(mu - ref["mu"]) / np.maximum(np.abs(ref["mu"]), 1.0)
+    esig = np.abs(sig - ref["sigma"]) / ref["sigma"]
+    print(f"[{label}] max mu err {emu.max():.3e}  max sigma err {esig.max():.3e}", flush=True)
+    assert emu.max() <= MU_TOL, label
+    assert esig.max() <= SIG_TOL, label
+    ref_bits = oe.bits(y, ref["mu"], ref["sigma"]).sum()
+    if "total_bits" in out:
+        eb = abs(out["total_bits"] - ref_bits) / ref_bits
+        print(f"[{label}] total bits {out['total_bits']:.1f} vs {ref_bits:.1f} (rel {eb:.2e})",
+              flush=True)
+        assert eb <= BITS_TOL, label
+    # table selection: the oracle decision in float32, ties excepted
+    c_ref, i_ref = oe.cdf_select_f32(ref["mu"], ref["lsig"])
+    c, ix = _np(out["center"]), _np(out["index"]).view(np.uint16)
+    bad = (c != c_ref) | (ix != i_ref)
+    tie = oe.decision_margin(ref["mu"], ref["lsig"]) < 4 * MU_TOL * np.maximum(1, np.abs(ref["mu"]))
+    assert not (bad & ~tie).any(), f"{label}: {int((bad & ~tie).sum())} selections differ"
+
+
+def assert_bitwise(a, b, keys=("mean", "scale", "bits", "center", "index")):
+    for k in keys:
+        assert torch.equal(a[k], b[k]), k
+
+
+# -------------------------------------------------------- table selection
+
+def test_cdf_select_bit_exact(P):
+    rng = np.random.Generator(np.random.PCG64(123))
+    n = 1 << 20
+    mu = rng.uniform(-300, 300, n).astype(np.float32)
+    mu[: n // 4] = np.round(mu[: n // 4] * 16) / 16  # exact phase boundaries
+    lsig = rng.uniform(math.log(0.05), math.log(100), n).astype(np.float32)
+    c, i = P.pswa_cdf_select(torch.from_numpy(mu).cuda(), torch.from_numpy(lsig).cuda())
+    c_ref, i_ref = oe.cdf_select_f32(mu, lsig)
+    assert np.array_equal(_np(c), c_ref)
+    assert np.array_equal(_np(i).view(np.uint16), i_ref)
+
+
+# ------------------------------------------------------------------- tiny
+
+@pytest.fixture(scope="module")
+def tiny(P):
+    cfg = synth.TINY
+    W = synth.model_weights(cfg, synth.CONFIG_SEEDS["tiny"][1])
+    model = P.Model(cfg, W)
+    return cfg, W, model
+
+
+@pytest.mark.parametrize("H,W", [(16, 16), (13, 21), (1, 1), (1, 7), (7, 1), (3, 2), (5, 33)])
+def test_tiny_iframe_encode_decode(P, tiny, H, W):
+    cfg, Wt, model = tiny
+    print(f"case tiny I {H}x{W}", flush=True)
+    y, z, _ = synth.frame_inputs(cfg, synth.FrameCfg(H, W), synth.CONFIG_SEEDS["tiny"][0] + H * 100 + W)
+    ref = om.forward(cfg, Wt, y, z)
+    enc = P.pswa_encode_params(model, y, z)
+    assert_matches_oracle(enc, ref, y, f"tiny-enc {H}x{W}")
+    dec = P.decode_frame(model, H, W, z, source="device", src=y)
+    assert_bitwise(enc, dec)
+    assert np.array_equal(_np(dec["latents"]), y)
+    assert dec["total_bits"] == enc["total_bits"]
+
+
+def test_tiny_pframe_encode_decode(P, tiny):
+    cfg, Wt, model = tiny
+    H, W = 16, 16
+    y, z, prev = synth.frame_inputs(cfg, synth.FrameCfg(H, W, 2), 5)
+    ref = om.forward(cfg, Wt, y, z, prev)
+    enc = P.pswa_encode_params(model, y, z, prev)
+    assert_matches_oracle(enc, ref, y, "tiny-P-enc")
+    dec = P.decode_frame(model, H, W, z, prev=prev, source="device", src=y)
+    assert_bitwise(enc, dec)
+
+
+def test_tiny_bitstream_round_trip(P, tiny):
+    cfg, Wt, model = tiny
+    H, W = 16, 16
+    y, z, _ = synth.frame_inputs(cfg, synth.FrameCfg(H, W), 0)
+    enc = P.pswa_encode_params(model, y, z)
+    data = P.pswa_range_encode(H, W, cfg.C, cfg.window, y, _np(enc["center"]),
+                               _np(enc["index"]))
+    dec = P.decode_frame(model, H, W, z, source="bitstream", src=data)
+    assert np.array_equal(_np(dec["latents"]), y)
+    assert_bitwise(enc, dec)
+    ideal = enc["total_bits"]
+    print(f"bitstream {len(data)} bytes = {8 * len(data)} bits vs ideal {ideal:.0f}", flush=True)
+    assert 8 * len(data) < 1.02 * ideal + 64
+
+
+def test_bitstream_corrupt_is_reported(P, tiny):
+    cfg, Wt, model = tiny
+    H, W = 8, 8
+    y, z, _ = synth.frame_inputs(cfg, synth.FrameCfg(H, W), 3)
+    enc = P.pswa_encode_params(model, y, z)
+    data = P.pswa_range_encode(H, W, cfg.C, cfg.window, y, _np(enc["center"]), _np(enc["index"]))
+    st = P.pswa_decode_begin(model, H, W, z, source="bitstream", src=data[: len(data) // 3])
+    with pytest.raises(P.PswaError) as e:
+        for t in range(st.T):
+            P.pswa_decode_step(st, t)
+    assert e.value.name == "E_CORRUPT"
+    st.close()
+    torch.cuda.synchronize()
+
+
+def test_decode_order_errors(P, tiny):
+    cfg, Wt, model = tiny
+    H, W = 6, 6
+    y, z, _ = synth.frame_inputs(cfg, synth.FrameCfg(H, W), 4)
+    st = P.pswa_decode_begin(model, H, W, z, source="device", src=y)
+    with pytest.raises(P.PswaError) as e:
+        P.pswa_decode_step(st, 1)
+    assert e.value.name == "E_ORDER"
+    P.pswa_decode_step(st, 0)
+    with pytest.raises(P.PswaError) as e:
+        P.pswa_decode_end(st, H, W, cfg.C)
+    assert e.value.name == "E_ORDER"
+    for t in range(1, st.T):
+        P.pswa_decode_step(st, t)
+    with pytest.raises(P.PswaError):
+        P.pswa_decode_step(st, st.T)
+    P.pswa_decode_end(st, H, W, cfg.C)
+    st.close()
+
+
+def test_nan_poisoned_state_and_repeatability(P, tiny):
+    """State memory pre-filled with NaN: any read-before-write would show."""
+    cfg, Wt, model = tiny
+    H, W = 12, 10
+    y, z, _ = synth.frame_inputs(cfg, synth.FrameCfg(H, W), 6)
+    nb = P.pswa_state_bytes(model, H, W)
+    mem = torch.full((nb // 4,), float("nan"), dtype=torch.float32, device="cuda").view(torch.uint8)
+    a = P.decode_frame(model, H, W, z, source="device", src=y, mem=mem)
+    b = P.decode_frame(model, H, W, z, source="device", src=y)
+    assert_bitwise(a, b)
+    assert torch.isfinite(a["mean"]).all() and torch.isfinite(a["scale"]).all()
+
+
+def test_hyper_shape_error(P, tiny):
+    cfg, Wt, model = tiny
+    y, z, _ = synth.frame_inputs(cfg, synth.FrameCfg(8, 8), 1)
+    with pytest.raises(P.PswaError) as e:
+        P.pswa_encode_params(model, y[:, :5], z[:1])  # 8x5 needs a 2x2 hyperprior
+    assert e.value.name in ("E_SHAPE", "E_ARG")
+
+
+# ------------------------------------------------------------------ 1080p
+
+@pytest.fixture(scope="module")
+def full(P):
+    cfg = synth.FULL
+    W = synth.model_weights(cfg, synth.CONFIG_SEEDS["1080p_I"][1])
+    return cfg, W, P.Model(cfg, W)
+
+
+def test_1080p_iframe_decode_matches_oracle(P, full):
+    cfg, Wt, model = full
+    H, W = 68, 120
+    print("case 1080p I decode vs oracle", flush=True)
+    y, z, _ = synth.frame_inputs(cfg, synth.FrameCfg(H, W), synth.CONFIG_SEEDS["1080p_I"][0])
+    dec = P.decode_frame(model, H, W, z, source="device", src=y)
+    ref = om.forward(cfg, Wt, y, z)
+    assert_matches_oracle(dec, ref, y, "1080p-I-dec")
+    enc = P.pswa_encode_params(model, y, z)
+    assert_bitwise(enc, dec)
+
+
+def test_1080p_pframe_encode_matches_oracle(P, full):
+    cfg, Wt, model = full
+    H, W = 68, 120
+    print("case 1080p P encode vs oracle", flush=True)
+    y, z, prev = synth.frame_inputs(cfg, synth.FrameCfg(H, W, 2), synth.CONFIG_SEEDS["1080p_P"][0])
+    enc = P.pswa_encode_params(model, y, z, prev)
+    ref = om.forward(cfg, Wt, y, z, prev)
+    assert_matches_oracle(enc, ref, y, "1080p-P-enc")
