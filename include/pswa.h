@@ -169,6 +169,64 @@ pswa_status pswa_decode_end(pswa_state* state, int32_t* d_latents_out, float* d_
                             uint16_t* d_cdf_index, double* h_total_bits, void* stream);
 void pswa_state_destroy(pswa_state* state);
 
+/* ---------------------------------------------------- batched decode */
+
+/* Persistent decode of many frames (any sizes, I and P mixed) in one launch:
+ * one kernel walks the global steps t = 0 .. max_f T_f - 1, each step
+ * holding the diagonal t of every frame that has one, with grid barriers
+ * between the dependent phases of the network (Sec. 3.2: every position of
+ * a diagonal is predicted in one step; the frames of a batch are
+ * independent). Per-row arithmetic is the same as in pswa_decode_step and
+ * pswa_encode_params, so the outputs are bit-identical to theirs. Symbols
+ * come from device memory (one d_latents per frame). */
+typedef struct {
+  pswa_frame_desc frame;
+  const int32_t* d_hyper;   /* [Hh][Wh][Ch] */
+  const int32_t* d_prev;    /* [2][H][W][C] for P-frames, else NULL */
+  const int32_t* d_latents; /* symbol source [H][W][C] */
+} pswa_batch_frame;
+
+typedef struct pswa_batch pswa_batch;
+
+/* Workspace bytes for the batch (0 for invalid frames). The workspace holds
+ * every frame's caches and outputs plus the step tables. */
+size_t pswa_batch_workspace_bytes(const pswa_model* model, int n, const pswa_batch_frame* frames);
+
+/* Plan a batch in caller-owned workspace (256-byte aligned): builds and
+ * uploads the per-step row tables and waits for the upload. grid = number of
+ * persistent workgroups (0: default; clamped to what can be co-resident).
+ * The frames' device buffers must stay valid until pswa_batch_destroy. */
+pswa_status pswa_batch_create(const pswa_model* model, int n, const pswa_batch_frame* frames,
+                              int grid, void* d_ws, size_t ws_bytes, void* stream,
+                              pswa_batch** out);
+
+/* Enqueue one full decode of the batch: hyperprior tokens and previous-frame
+ * keys of every frame, then the persistent launch. Does not wait; may be
+ * called again to decode the same inputs again, and may be captured in a
+ * HIP graph. */
+pswa_status pswa_batch_run(pswa_batch* batch, void* stream);
+
+/* Waits for the stream and reports a barrier-timeout abort (PSWA_E_HIP) or a
+ * non-finite mean/scale (PSWA_E_NUMERIC) of the last run. */
+pswa_status pswa_batch_check(pswa_batch* batch, void* stream);
+
+/* Copy frame f's outputs (each optional) laid out as in pswa_encode_params;
+ * h_total_bits waits (and checks, as pswa_batch_check). */
+pswa_status pswa_batch_outputs(pswa_batch* batch, int f, int32_t* d_latents_out, float* d_mean,
+                               float* d_scale, float* d_bits, int32_t* d_cdf_center,
+                               uint16_t* d_cdf_index, double* h_total_bits, void* stream);
+
+int pswa_batch_num_steps(const pswa_batch* batch);  /* global steps */
+int pswa_batch_max_rows(const pswa_batch* batch);   /* largest step */
+int pswa_batch_grid(const pswa_batch* batch);       /* current grid */
+int pswa_batch_max_grid(const pswa_batch* batch);   /* co-resident limit */
+/* Choose the persistent grid (the autotuner's knob); 1 <= grid <= max. */
+pswa_status pswa_batch_set_grid(pswa_batch* batch, int grid);
+/* Bound on the spin count of one grid-barrier wait before the launch aborts
+ * (default about a second of waiting). Lowering it forces the abort path. */
+pswa_status pswa_batch_set_spin_limit(pswa_batch* batch, int64_t spins);
+void pswa_batch_destroy(pswa_batch* batch);
+
 /* ---------------------------------------------------------- entropy side */
 
 /* Table selection of n symbols from their mean and log-scale (float32
@@ -214,6 +272,24 @@ pswa_status pswa_range_encode_seq(size_t n, const int32_t* h_symbols,
                                   uint8_t* out, size_t cap, size_t* out_bytes);
 
 const char* pswa_last_error(void);
+
+/* ------------------------------------------------------------ profiling */
+
+/* Live kernel timer (a profiling aid, off by default). While enabled, every
+ * kernel the library launches is bracketed by two HIP events recorded on the
+ * stream it is launched on, and its algorithmic bytes and flops (weights
+ * once, activations in and out; 2 flops per multiply-add) are recorded under
+ * the kernel's role. Enabling clears earlier records. Timing adds event
+ * records between launches, so timed runs should not be the ones measured. */
+pswa_status pswa_profile_enable(int on);
+
+/* Number of roles (kernel kinds) the timer distinguishes. */
+int pswa_profile_roles(void);
+
+/* Totals of one role since the timer was enabled: waits for its events.
+ * name (optional) receives the role's name. */
+pswa_status pswa_profile_read(int role, char* name, size_t name_cap, double* total_ms,
+                              int64_t* launches, double* alg_bytes, double* alg_flops);
 
 #ifdef __cplusplus
 }

@@ -1,6 +1,7 @@
 """Build the HIP library libpswa.so in-tree with hipcc for gfx950.
 
-Usage: python -m paper_2605_20977_amd.build   (or call build()).
+Usage: python paper_2605_20977_amd/build.py   (or __graft_entry__.build()).
+It does not import the package, so it works with no library built.
 """
 from __future__ import annotations
 
@@ -13,10 +14,14 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpswa.so")
 
-SOURCES = ["kernels_f32.hip", "pswa_capi.cpp", "coder.cpp"]
+SOURCES = ["kernels_f32.hip", "persistent.hip", "pswa_capi.cpp", "batch.cpp", "coder.cpp",
+           "profile.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # no implicit multiply-add contraction: identical source gives identical
+    # arithmetic in every kernel and translation unit
+    "-ffp-contract=off",
     # packed FP32 instructions stay off: plain scalar FP32 only
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result", "-Wno-unused-function",

@@ -1,0 +1,304 @@
+// Batched persistent decode (C ABI in include/pswa.h): many frames of any
+// sizes, I and P mixed, decoded in one persistent launch.
+//
+// All frames live in one global position space: frame f owns positions
+// [off_f, off_f + H_f W_f). At global step t the launch processes the union
+// of every frame's diagonal t (frames start together; a frame with fewer
+// steps simply has no rows at later steps). The per-step row tables (global
+// position and frame of each row) are built on the host once per batch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <memory>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/pswa.h"
+#include "persistent.h"
+#include "runtime.h"
+
+using namespace pswa;
+
+struct pswa_batch {
+  const pswa_model* model = nullptr;
+  std::vector<pswa_batch_frame> frames;
+  std::vector<FrameInfo> finfo;
+  int HWt = 0, T = 0, Mmax = 0, grid = 0, max_grid = 0;
+  long spin_limit = 1L << 21;  // barrier wait bound (about a second)
+  bool any_p = false;
+  // device (inside the caller's workspace)
+  FrameInfo* d_frames = nullptr;
+  int *row_start = nullptr, *gpos_all = nullptr, *fid_all = nullptr;
+  float *h = nullptr, *acc_kv = nullptr, *kv = nullptr, *tkv = nullptr, *e_prev = nullptr;
+  int32_t *ysrc = nullptr, *ydec = nullptr;
+  float *mean = nullptr, *scale = nullptr, *bits = nullptr;
+  int32_t* center = nullptr;
+  uint16_t* index = nullptr;
+  Acts a{};
+  int* ctl = nullptr;  // [0] barrier arrivals, [1] abort, [2] numeric flag
+  float* sum = nullptr;
+  size_t bytes = 0;
+};
+
+namespace {
+
+
+struct Plan {
+  std::vector<FrameInfo> finfo;
+  int HWt = 0, T = 0, Mmax = 0;
+  bool any_p = false;
+  std::vector<int> row_start, gpos, fid;
+};
+
+Plan make_plan(const NetDims& x, int n, const pswa_batch_frame* fr, bool tables) {
+  Plan p;
+  int off = 0;
+  for (int f = 0; f < n; ++f) {
+    const pswa_frame_desc& d = fr[f].frame;
+    p.finfo.push_back(FrameInfo{d.H, d.W, off, d.n_prev});
+    off += d.H * d.W;
+    p.T = std::max(p.T, steps_of(d.H, d.W, x.s));
+    p.any_p = p.any_p || d.n_prev > 0;
+  }
+  p.HWt = off;
+  p.row_start.assign(p.T + 1, 0);
+  for (int t = 0; t < p.T; ++t) {
+    int cnt = 0;
+    for (int f = 0; f < n; ++f) {
+      const FrameInfo& fi = p.finfo[f];
+      for (int i = 0; i < fi.H; ++i) {
+        const int j = t - x.s * i;
+        if (j < 0 || j >= fi.W) continue;
+        ++cnt;
+        if (tables) {
+          p.gpos.push_back(fi.off + i * fi.W + j);
+          p.fid.push_back(f);
+        }
+      }
+    }
+    p.row_start[t + 1] = p.row_start[t] + cnt;
+    p.Mmax = std::max(p.Mmax, cnt);
+  }
+  return p;
+}
+
+void lay_out(const NetDims& x, const Plan& p, int n, void* base, pswa_batch* b) {
+  Layout L(base);
+  const size_t HWt = p.HWt;
+  b->d_frames = L.take<FrameInfo>(n);
+  b->row_start = L.take<int>(p.T + 1);
+  b->gpos_all = L.take<int>(HWt);
+  b->fid_all = L.take<int>(HWt);
+  b->h = L.take<float>(HWt * x.d);
+  b->acc_kv = L.take<float>(HWt * 2 * x.d);
+  b->kv = L.take<float>((size_t)x.L * HWt * 2 * x.d);
+  b->tkv = p.any_p ? L.take<float>((size_t)x.L * 2 * HWt * 2 * x.d) : nullptr;
+  b->e_prev = p.any_p ? L.take<float>(2 * HWt * x.d) : nullptr;
+  b->ysrc = L.take<int32_t>(HWt * x.C);
+  b->ydec = L.take<int32_t>(HWt * x.C);
+  b->mean = L.take<float>(HWt * x.C);
+  b->scale = L.take<float>(HWt * x.C);
+  b->bits = L.take<float>(HWt * x.C);
+  b->center = L.take<int32_t>(HWt * x.C);
+  b->index = L.take<uint16_t>(HWt * x.C);
+  b->a = take_acts(L, x, std::max(p.Mmax, 1));
+  b->ctl = L.take<int>(64);
+  b->sum = L.take<float>(64);
+  b->bytes = L.used;
+}
+
+pswa_status check_frames(const pswa_model* m, int n, const pswa_batch_frame* fr) {
+  if (!m) return fail(PSWA_E_ARG, "model is null");
+  if (n < 1 || !fr) return fail(PSWA_E_ARG, "need at least one frame");
+  for (int f = 0; f < n; ++f) {
+    std::string why;
+    if (!valid_frame(&fr[f].frame, &why))
+      return fail(PSWA_E_SHAPE, "frame %d: %s", f, why.c_str());
+    if (!fr[f].d_hyper || !fr[f].d_latents) return fail(PSWA_E_ARG, "frame %d: null pointer", f);
+    if ((fr[f].frame.n_prev != 0) != (fr[f].d_prev != nullptr))
+      return fail(PSWA_E_ARG, "frame %d: d_prev must be given exactly for P-frames", f);
+  }
+  int64_t tot = 0;
+  for (int f = 0; f < n; ++f) tot += (int64_t)fr[f].frame.H * fr[f].frame.W;
+  if (tot > (1 << 24)) return fail(PSWA_E_SHAPE, "batch holds more than 2^24 positions");
+  return PSWA_OK;
+}
+
+PersistArgs persist_args(const pswa_batch* b) {
+  const NetDims& x = b->model->x;
+  PersistArgs P{};
+  P.x = x;
+  P.w = b->model->w;
+  PassCtx& c = P.c;
+  c.frames = b->d_frames;
+  c.frame0 = b->finfo[0];
+  c.HWt = b->HWt;
+  c.h = b->h;
+  c.acc_kv = b->acc_kv;
+  c.kv = b->kv;
+  c.kv_stride = (size_t)b->HWt * 2 * x.d;
+  c.tkv = b->tkv;
+  c.tkv_stride = (size_t)2 * b->HWt * 2 * x.d;
+  c.x = b->a.x; c.q = b->a.q; c.att = b->a.att; c.e = b->a.e; c.t1 = b->a.t1; c.hmid = b->a.hmid;
+  c.mean = b->mean; c.scale = b->scale; c.bits = b->bits;
+  c.center = b->center; c.index = b->index;
+  c.center_c = nullptr; c.index_c = nullptr;
+  c.flag = b->ctl + 2;
+  c.ysrc = b->ysrc;
+  c.src_compact = 0;
+  c.ydec = b->ydec;
+  P.row_start = b->row_start;
+  P.gpos_all = b->gpos_all;
+  P.fid_all = b->fid_all;
+  P.T = b->T;
+  P.bar = reinterpret_cast<unsigned*>(b->ctl);
+  P.abort_flag = b->ctl + 1;
+  P.spin_limit = b->spin_limit;
+  return P;
+}
+
+pswa_status run(pswa_batch* b, hipStream_t st) {
+  const pswa_model* m = b->model;
+  const NetDims& x = m->x;
+  zero_ints(b->ctl, 3, st);
+  for (size_t f = 0; f < b->frames.size(); ++f) {
+    const pswa_batch_frame& fr = b->frames[f];
+    const FrameInfo& fi = b->finfo[f];
+    const int HW = fi.H * fi.W;
+    hyper_embed(fr.d_hyper, fr.frame.Hh, fr.frame.Wh, x.Ch, m->w.hyperW, m->w.P4, fi.H, fi.W,
+                x.d, b->h + (size_t)fi.off * x.d, st);
+    PSWA_HIP_TRY(hipMemcpyAsync(b->ysrc + (size_t)fi.off * x.C, fr.d_latents,
+                                (size_t)HW * x.C * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    if (fi.n_prev) {
+      embed_prev(m, HW, b->HWt, fi.off, fr.d_prev, b->e_prev, st);
+      for (int l = 0; l < x.L; ++l)
+        temporal_kv_layer(m, HW, b->HWt, fi.off, b->e_prev, l,
+                          b->tkv + (size_t)l * 2 * b->HWt * 2 * x.d, st);
+    }
+  }
+  launch_persistent(persist_args(b), b->grid, st);
+  PSWA_HIP_TRY(hipGetLastError());
+  return PSWA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pswa_batch_workspace_bytes(const pswa_model* model, int n, const pswa_batch_frame* frames) {
+  if (check_frames(model, n, frames) != PSWA_OK) return 0;
+  Plan p = make_plan(model->x, n, frames, false);
+  pswa_batch tmp;
+  lay_out(model->x, p, n, nullptr, &tmp);
+  return tmp.bytes;
+}
+
+pswa_status pswa_batch_create(const pswa_model* model, int n, const pswa_batch_frame* frames,
+                              int grid, void* d_ws, size_t ws_bytes, void* stream,
+                              pswa_batch** out) {
+  if (!out) return fail(PSWA_E_ARG, "out is null");
+  *out = nullptr;
+  const pswa_status cs = check_frames(model, n, frames);
+  if (cs != PSWA_OK) return cs;
+  if (!d_ws || (reinterpret_cast<uintptr_t>(d_ws) % kAlign) != 0)
+    return fail(PSWA_E_ARG, "workspace must be non-null and 256-byte aligned");
+  if (model->desc.prec != PSWA_FP32)
+    return fail(PSWA_E_UNSUPPORTED, "batched decode of precision %d is not built", model->desc.prec);
+  Plan p = make_plan(model->x, n, frames, true);
+  std::unique_ptr<pswa_batch> b(new pswa_batch);
+  lay_out(model->x, p, n, d_ws, b.get());
+  if (ws_bytes < b->bytes) return fail(PSWA_E_ARG, "workspace %zu bytes < %zu", ws_bytes, b->bytes);
+  b->model = model;
+  b->frames.assign(frames, frames + n);
+  b->finfo = p.finfo;
+  b->HWt = p.HWt;
+  b->T = p.T;
+  b->Mmax = p.Mmax;
+  b->any_p = p.any_p;
+  b->max_grid = persistent_max_grid(model->x);
+  if (b->max_grid <= 0) return fail(PSWA_E_HIP, "cannot size the persistent grid");
+  b->grid = grid > 0 ? std::min(grid, b->max_grid) : std::min(b->max_grid, 256);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  PSWA_HIP_TRY(hipMemcpyAsync(b->d_frames, p.finfo.data(), n * sizeof(FrameInfo),
+                              hipMemcpyHostToDevice, st));
+  PSWA_HIP_TRY(hipMemcpyAsync(b->row_start, p.row_start.data(), (p.T + 1) * sizeof(int),
+                              hipMemcpyHostToDevice, st));
+  PSWA_HIP_TRY(hipMemcpyAsync(b->gpos_all, p.gpos.data(), p.gpos.size() * sizeof(int),
+                              hipMemcpyHostToDevice, st));
+  PSWA_HIP_TRY(hipMemcpyAsync(b->fid_all, p.fid.data(), p.fid.size() * sizeof(int),
+                              hipMemcpyHostToDevice, st));
+  PSWA_HIP_TRY(hipStreamSynchronize(st));
+  *out = b.release();
+  return PSWA_OK;
+}
+
+int pswa_batch_num_steps(const pswa_batch* b) { return b ? b->T : -1; }
+int pswa_batch_max_rows(const pswa_batch* b) { return b ? b->Mmax : -1; }
+int pswa_batch_grid(const pswa_batch* b) { return b ? b->grid : -1; }
+int pswa_batch_max_grid(const pswa_batch* b) { return b ? b->max_grid : -1; }
+
+pswa_status pswa_batch_set_grid(pswa_batch* b, int grid) {
+  if (!b) return fail(PSWA_E_ARG, "batch is null");
+  if (grid < 1 || grid > b->max_grid)
+    return fail(PSWA_E_ARG, "grid %d outside [1, %d]", grid, b->max_grid);
+  b->grid = grid;
+  return PSWA_OK;
+}
+
+pswa_status pswa_batch_run(pswa_batch* b, void* stream) {
+  if (!b) return fail(PSWA_E_ARG, "batch is null");
+  return run(b, static_cast<hipStream_t>(stream));
+}
+
+pswa_status pswa_batch_check(pswa_batch* b, void* stream) {
+  if (!b) return fail(PSWA_E_ARG, "batch is null");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int ctl[3] = {0, 0, 0};
+  PSWA_HIP_TRY(hipMemcpyAsync(ctl, b->ctl, sizeof ctl, hipMemcpyDeviceToHost, st));
+  PSWA_HIP_TRY(hipStreamSynchronize(st));
+  if (ctl[1]) return fail(PSWA_E_HIP, "persistent decode aborted: a grid barrier wait timed out");
+  if (ctl[2]) return fail(PSWA_E_NUMERIC, "non-finite mean or scale produced");
+  return PSWA_OK;
+}
+
+pswa_status pswa_batch_outputs(pswa_batch* b, int f, int32_t* d_latents_out, float* d_mean,
+                               float* d_scale, float* d_bits, int32_t* d_cdf_center,
+                               uint16_t* d_cdf_index, double* h_total_bits, void* stream) {
+  if (!b) return fail(PSWA_E_ARG, "batch is null");
+  if (f < 0 || f >= (int)b->finfo.size()) return fail(PSWA_E_ARG, "frame %d out of range", f);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t C = b->model->x.C;
+  const size_t o = (size_t)b->finfo[f].off * C;
+  const size_t n = (size_t)b->finfo[f].H * b->finfo[f].W * C;
+  auto cp = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    return dst ? hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st) : hipSuccess;
+  };
+  PSWA_HIP_TRY(cp(d_latents_out, b->ydec + o, n * sizeof(int32_t)));
+  PSWA_HIP_TRY(cp(d_mean, b->mean + o, n * sizeof(float)));
+  PSWA_HIP_TRY(cp(d_scale, b->scale + o, n * sizeof(float)));
+  PSWA_HIP_TRY(cp(d_bits, b->bits + o, n * sizeof(float)));
+  PSWA_HIP_TRY(cp(d_cdf_center, b->center + o, n * sizeof(int32_t)));
+  PSWA_HIP_TRY(cp(d_cdf_index, b->index + o, n * sizeof(uint16_t)));
+  if (h_total_bits) {
+    const pswa_status s = pswa_batch_check(b, stream);
+    if (s != PSWA_OK) return s;
+    return finish_sum(b->bits + o, n, b->sum, b->ctl + 2, h_total_bits, st);
+  }
+  return PSWA_OK;
+}
+
+pswa_status pswa_batch_set_spin_limit(pswa_batch* b, int64_t spins) {
+  if (!b) return fail(PSWA_E_ARG, "batch is null");
+  if (spins < 0) return fail(PSWA_E_ARG, "spin limit must be >= 0");
+  b->spin_limit = long(spins);
+  return PSWA_OK;
+}
+
+void pswa_batch_destroy(pswa_batch* b) { delete b; }
+
+}  // extern "C"

@@ -1,0 +1,420 @@
+// Device building blocks shared by the per-launch kernels (kernels_f32.hip)
+// and the persistent decode kernel (persistent.hip). Every output is computed
+// by the same code whatever launch runs it, and the library is built with
+// -ffp-contract=off, so a row's values are bit-identical across the parallel
+// encode form, the per-diagonal decode and the persistent multi-frame decode.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cmath>
+
+#include "pswa_internal.h"
+
+namespace pswa {
+namespace dev {
+
+constexpr float kEps = 1e-5f;
+constexpr int kRowsW = 4;   // weight rows per wave in a GEMM tile
+constexpr int kWaves = 4;   // waves per 256-thread block
+constexpr int kMB = 16;     // A rows per GEMM tile
+constexpr int kMaxKeys = 256;
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ int map_row(const int* idx, int m) { return idx ? idx[m] : m; }
+
+__device__ __forceinline__ float silu(float v) { return v / (1.0f + expf(-v)); }
+
+__device__ __forceinline__ float dot4(float4 x, float4 w, float acc) {
+  acc = fmaf(x.x, w.x, acc);
+  acc = fmaf(x.y, w.y, acc);
+  acc = fmaf(x.z, w.z, acc);
+  return fmaf(x.w, w.w, acc);
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Centre and table index of one symbol, one rounding per operation, so the
+// decision equals the documented float32 formula.
+__device__ __forceinline__ void select_table(float mu, float lsig, float ln_smin, float inv_delta,
+                                             int32_t* c_out, uint16_t* i_out) {
+  const float c = floorf(mu + 0.5f);
+  const float ph = (mu - c) + 0.5f;
+  const float m = fminf(15.0f, floorf(ph * 16.0f));
+  const float t = (lsig - ln_smin) * inv_delta;
+  const float s = fminf(63.0f, fmaxf(0.0f, floorf(t + 0.5f)));
+  *c_out = int32_t(c);
+  *i_out = uint16_t(int(s) * 16 + int(m));
+}
+
+// Number of float4 chunks per lane a GEMM with reduction length K needs
+// (a compile-time count per instantiation; chunks past K are skipped).
+__host__ __device__ inline int kc_for(int K) {
+  const int K4 = K / 4;
+  return K4 <= 64 ? 1 : K4 <= 128 ? 2 : K4 <= 256 ? 4 : 8;
+}
+
+__host__ __device__ inline constexpr bool paired_epi(int epi) {
+  return epi == EPI_SWIGLU || epi == EPI_HEAD;
+}
+
+// Tiles of a GEMM launch: (column tiles, row tiles).
+__host__ __device__ inline int gemm_col_tiles(int N, int epi) {
+  const int per = kWaves * (paired_epi(epi) ? 2 : kRowsW);
+  return (N + per - 1) / per;
+}
+__host__ __device__ inline int gemm_row_tiles(int M) { return (M + kMB - 1) / kMB; }
+
+// LDS a GEMM tile needs: the raw A tile, reused as the lane-transpose buffer.
+__host__ __device__ inline size_t gemm_lds_bytes(int K) {
+  const size_t tile = (size_t)kMB * K * sizeof(float);
+  const size_t red = (size_t)kWaves * 64 * 65 * sizeof(float);
+  return tile > red ? tile : red;
+}
+
+// ---------------------------------------------------------------- GEMM tile
+// Skinny FP32 GEMM tile: 16 weight rows (4 per wave) x up to 16 A rows.
+//   1. each wave loads its 4 weight rows into registers: lane l takes the
+//      float4 chunks l, l + 64, ... (KC of them, all in flight);
+//   2. the block stages the raw A tile [rows][K] in LDS, 8 loads per thread
+//      in flight;
+//   3. RMSNorm rows: lane l sums x^2 over its chunks in order, then a fixed
+//      xor tree gives the row's 1/rms;
+//   4. each lane keeps an fmaf chain per (row, weight row) over its chunks,
+//      and the 64 lane partials are summed lane 0..63 in order.
+// The RMSNorm scale is applied to the finished dot product:
+//   sum_k (x_k * rstd * g_k) w_k  ==  rstd * sum_k (x_k g_k) w_k.
+// An output's arithmetic depends only on K. Paired epilogues (SwiGLU, head):
+// a wave's weight rows are W[n], W[n+1], W2[n], W2[n+1] -> outputs n, n+1.
+template <int AK, bool RMS, int EPI, int KC>
+__device__ void gemm_tile(const GemmArgs& a, int bx, int by, float4* smem4, float* rstd) {
+  constexpr bool PAIRED = paired_epi(EPI);
+  float* smem = reinterpret_cast<float*>(smem4);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n0 = bx * kWaves * (PAIRED ? 2 : kRowsW) + wave * (PAIRED ? 2 : kRowsW);
+  const int m0 = by * kMB;
+  const int K = a.K, K4 = a.K / 4;
+  const int rows = min(kMB, a.M - m0);
+  __syncthreads();  // the previous tile of this block is done with the LDS
+
+  const float* wrow[kRowsW];
+#pragma unroll
+  for (int j = 0; j < kRowsW; ++j) {
+    if (PAIRED) {
+      const int n = min(n0 + (j & 1), a.N - 1);
+      wrow[j] = (j < 2 ? a.W : a.W2) + (size_t)n * K;
+    } else {
+      wrow[j] = a.W + (size_t)min(n0 + j, a.N - 1) * K;
+    }
+  }
+  float4 w[KC][kRowsW];
+  float4 g[KC];
+#pragma unroll
+  for (int it = 0; it < KC; ++it) {
+    const int c = lane + 64 * it;
+    const bool in = c < K4;
+#pragma unroll
+    for (int j = 0; j < kRowsW; ++j)
+      w[it][j] = in ? *reinterpret_cast<const float4*>(wrow[j] + 4 * c) : make_float4(0, 0, 0, 0);
+    g[it] = make_float4(1.f, 1.f, 1.f, 1.f);
+    if (RMS && in) g[it] = *reinterpret_cast<const float4*>(a.gain + 4 * c);
+    if (AK == A_INT && in) g[it] = *reinterpret_cast<const float4*>(a.xscale + 4 * c);
+  }
+
+  {
+    const int total = rows * K4;
+    for (int base = 0; base < total; base += 8 * kThreads) {
+      float4 x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = base + u * kThreads + tid;
+        if (e < total) {
+          const int m = e / K4, c = e % K4;
+          const size_t off = (size_t)map_row(a.xrow, m0 + m) * a.ldx + 4 * c;
+          if (AK == A_INT) {
+            const int4 xi = *reinterpret_cast<const int4*>(a.Xi + off);
+            x[u] = make_float4(float(xi.x), float(xi.y), float(xi.z), float(xi.w));
+          } else {
+            x[u] = *reinterpret_cast<const float4*>(a.X + off);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = base + u * kThreads + tid;
+        if (e < total) smem4[e] = x[u];
+      }
+    }
+  }
+  __syncthreads();
+
+  if (RMS) {
+    for (int m = wave; m < rows; m += kWaves) {
+      float ss = 0.f;
+#pragma unroll
+      for (int it = 0; it < KC; ++it) {
+        const int c = lane + 64 * it;
+        if (c < K4) {
+          const float4 x = smem4[m * K4 + c];
+          ss = dot4(x, x, ss);
+        }
+      }
+      ss = wave_sum(ss);
+      if (lane == 0) rstd[m] = 1.0f / sqrtf(ss / float(K) + kEps);
+    }
+  }
+
+  float acc[kMB][kRowsW];
+#pragma unroll
+  for (int m = 0; m < kMB; ++m)
+#pragma unroll
+    for (int j = 0; j < kRowsW; ++j) acc[m][j] = 0.f;
+#pragma unroll
+  for (int m = 0; m < kMB; ++m) {
+    if (m < rows) {
+#pragma unroll
+      for (int it = 0; it < KC; ++it) {
+        const int c = lane + 64 * it;
+        if (c < K4) {
+          float4 x = smem4[m * K4 + c];
+          x = make_float4(x.x * g[it].x, x.y * g[it].y, x.z * g[it].z, x.w * g[it].w);
+#pragma unroll
+          for (int j = 0; j < kRowsW; ++j) acc[m][j] = dot4(x, w[it][j], acc[m][j]);
+        }
+      }
+    }
+  }
+  __syncthreads();  // the A tile is dead; its LDS becomes the transpose buffer
+
+  float* red = smem + wave * (64 * 65);
+#pragma unroll
+  for (int m = 0; m < kMB; ++m)
+#pragma unroll
+    for (int j = 0; j < kRowsW; ++j) red[(m * kRowsW + j) * 65 + lane] = acc[m][j];
+  __syncthreads();
+  float v = 0.f;
+#pragma unroll
+  for (int l = 0; l < 64; ++l) v += red[lane * 65 + l];
+  const int m = lane / kRowsW, j = lane % kRowsW;
+  if (RMS) v *= rstd[min(m, rows - 1)];
+  const int row = m0 + m;
+  // paired: lanes with j = 2, 3 hold the W2 products of lanes j = 0, 1
+  const float v2 = PAIRED ? __shfl(v, (lane & ~3) | ((j & 1) + 2), 64) : 0.f;
+  if (m >= rows) return;
+  if (PAIRED && j >= 2) return;
+  const int n = n0 + j;
+  if (n >= a.N) return;
+
+  if (EPI == EPI_STORE) {
+    a.Y[(size_t)map_row(a.yrow, row) * a.ldy + n] = v;
+  } else if (EPI == EPI_RESID) {
+    const float r = a.R[(size_t)map_row(a.rrow, row) * a.ldr + n];
+    a.Y[(size_t)map_row(a.yrow, row) * a.ldy + n] = r + v;
+  } else if (EPI == EPI_QKV) {
+    if (n < a.nsplit)
+      a.Y[(size_t)row * a.ldy + n] = v;
+    else
+      a.Y2[(size_t)map_row(a.y2row, row) * a.ldy2 + (n - a.nsplit)] = v;
+  } else if (EPI == EPI_SILU) {
+    a.Y[(size_t)map_row(a.yrow, row) * a.ldy + n] = silu(v);
+  } else if (EPI == EPI_SWIGLU) {
+    a.Y[(size_t)map_row(a.yrow, row) * a.ldy + n] = silu(v) * v2;
+  } else if (EPI == EPI_HEAD) {
+    const HeadOut& h = a.head;
+    const float mu = fmaf(h.gmu[n], v, h.bmu[n]);
+    const float raw = fmaf(h.gsig[n], v2, h.bsig[n]);
+    const float ls = fminf(h.ln_smax, fmaxf(h.ln_smin, raw));
+    const float sg = expf(ls);
+    const size_t o = (size_t)map_row(a.yrow, row) * a.N + n;
+    h.mean[o] = mu;
+    h.scale[o] = sg;
+    int32_t c;
+    uint16_t x;
+    select_table(mu, ls, h.ln_smin, h.inv_delta, &c, &x);
+    h.center[o] = c;
+    h.index[o] = x;
+    if (h.center_c) {
+      h.center_c[(size_t)row * a.N + n] = c;
+      h.index_c[(size_t)row * a.N + n] = x;
+    }
+    if (!(fabsf(mu) <= FLT_MAX) || !(fabsf(raw) <= FLT_MAX)) atomicOr(h.flag, 1);
+  }
+}
+
+// Runtime choice of the chunk count (the same choice everywhere).
+template <int AK, bool RMS, int EPI>
+__device__ __forceinline__ void gemm_tile_any(const GemmArgs& a, int bx, int by, float4* smem4,
+                                              float* rstd) {
+  switch (kc_for(a.K)) {
+    case 1: gemm_tile<AK, RMS, EPI, 1>(a, bx, by, smem4, rstd); break;
+    case 2: gemm_tile<AK, RMS, EPI, 2>(a, bx, by, smem4, rstd); break;
+    case 4: gemm_tile<AK, RMS, EPI, 4>(a, bx, by, smem4, rstd); break;
+    default: gemm_tile<AK, RMS, EPI, 8>(a, bx, by, smem4, rstd); break;
+  }
+}
+
+// ------------------------------------------------------------ attention item
+// One 64-lane wave per (query row, head). Lane l owns keys l, l+64, ... in
+// slot order (spatial window, then the null slot or the temporal windows)
+// and runs an online softmax over them, loading each key's K and V rows
+// together. The lanes are then merged: common max and rescaled exp-sum by
+// wave reductions, the rescaled value vectors summed lane 0..63 in order
+// through LDS. All four waves of the block must call this together (it
+// synchronises the block); `live` marks waves with a real item.
+// Key positions: a row's frame (fid, else the single frame0) gives its grid
+// and its offset in the global position space; temporal K/V of frame
+// position g in previous frame tau is at (tau * HWt + g) * 2d.
+template <int DH>
+__device__ void attn_item(const AttnArgs& a, int item, bool live, float* tr_all) {
+  float* tr = tr_all + (threadIdx.x >> 6) * (DH * 65);
+  const int lane = threadIdx.x & 63;
+  live = live && item < a.M * a.heads;
+  const int m = live ? item / a.heads : 0, hd = live ? item % a.heads : 0;
+  const int gp = map_row(a.pos, m);
+  const FrameInfo fi = a.fid ? a.frames[a.fid[m]] : a.frame0;
+  const int lp = gp - fi.off;
+  const int pi = lp / fi.W, pj = lp % fi.W;
+  const int r = a.r, k1 = 2 * r + 1;
+  const int n_causal = 2 * r * (r + 1);
+  const int n_sp = n_causal + (a.include_self ? 1 : 0);
+  const bool temporal = a.tkv && fi.n_prev > 0;
+  const int n_tm = temporal ? 2 * k1 * k1 : 0;
+  const int n_keys = live ? n_sp + (a.knull ? 1 : 0) + n_tm : 0;
+  const int d = a.d;
+  const float scale = 1.0f / sqrtf(float(DH));
+  __syncthreads();  // the block's previous items are done with the LDS
+
+  float4 q[DH / 4];
+  {
+    const float* qv = a.q + (size_t)m * a.ldq + hd * DH;
+#pragma unroll
+    for (int e = 0; e < DH / 4; ++e) q[e] = *reinterpret_cast<const float4*>(qv + 4 * e);
+  }
+
+  float mx = -INFINITY, sum = 0.f;
+  float o[DH];
+#pragma unroll
+  for (int e = 0; e < DH; ++e) o[e] = 0.f;
+
+#pragma unroll
+  for (int u = 0; u < kMaxKeys / 64; ++u) {
+    const int kk = lane + 64 * u;
+    if (kk >= n_keys) continue;
+    const float* kp = nullptr;
+    const float* vp = nullptr;
+    float b = 0.f;
+    if (kk < n_sp) {
+      int da, db;
+      if (kk < r * k1) {
+        da = kk / k1 - r;
+        db = kk % k1 - r;
+      } else if (kk < n_causal) {
+        da = 0;
+        db = kk - r * k1 - r;
+      } else {
+        da = 0;
+        db = 0;
+      }
+      const int ki = pi + da, kj = pj + db;
+      if (ki < 0 || ki >= fi.H || kj < 0 || kj >= fi.W) continue;
+      kp = a.kv + (size_t)(fi.off + ki * fi.W + kj) * 2 * d + hd * DH;
+      vp = kp + d;
+      b = a.bias[hd * a.nbias + kk];
+    } else if (a.knull && kk == n_sp) {
+      kp = a.knull + hd * DH;
+      vp = a.vnull + hd * DH;
+    } else {
+      const int t = kk - n_sp - (a.knull ? 1 : 0);
+      const int tau = t / (k1 * k1), rem = t % (k1 * k1);
+      const int ki = pi + rem / k1 - r, kj = pj + rem % k1 - r;
+      if (ki < 0 || ki >= fi.H || kj < 0 || kj >= fi.W) continue;
+      kp = a.tkv + ((size_t)tau * a.HWt + (size_t)(fi.off + ki * fi.W + kj)) * 2 * d + hd * DH;
+      vp = kp + d;
+      b = a.bias[hd * a.nbias + n_sp + t];
+    }
+    float4 kr[DH / 4], vr[DH / 4];
+#pragma unroll
+    for (int e = 0; e < DH / 4; ++e) {
+      kr[e] = *reinterpret_cast<const float4*>(kp + 4 * e);
+      vr[e] = *reinterpret_cast<const float4*>(vp + 4 * e);
+    }
+    float dot = 0.f;
+#pragma unroll
+    for (int e = 0; e < DH / 4; ++e) dot = dot4(q[e], kr[e], dot);
+    const float lg = dot * scale + b;
+    const float mn = fmaxf(mx, lg);
+    const float c_old = expf(mx - mn);  // 0 for the first key (mx = -inf)
+    const float pk = expf(lg - mn);
+    sum = sum * c_old + pk;
+#pragma unroll
+    for (int e = 0; e < DH / 4; ++e) {
+      o[4 * e + 0] = fmaf(pk, vr[e].x, o[4 * e + 0] * c_old);
+      o[4 * e + 1] = fmaf(pk, vr[e].y, o[4 * e + 1] * c_old);
+      o[4 * e + 2] = fmaf(pk, vr[e].z, o[4 * e + 2] * c_old);
+      o[4 * e + 3] = fmaf(pk, vr[e].w, o[4 * e + 3] * c_old);
+    }
+    mx = mn;
+  }
+
+  const float gmx = wave_max(mx);
+  const float f = mx == -INFINITY ? 0.f : expf(mx - gmx);
+  const float tot = wave_sum(sum * f);
+#pragma unroll
+  for (int e = 0; e < DH; ++e) tr[e * 65 + lane] = o[e] * f;
+  __syncthreads();
+  if (live && lane < DH) {
+    float v = 0.f;
+#pragma unroll
+    for (int l = 0; l < 64; ++l) v += tr[lane * 65 + l];
+    a.out[(size_t)m * a.ldo + hd * DH + lane] = v / tot;
+  }
+}
+
+__host__ __device__ inline size_t attn_lds_bytes(int dh) {
+  return (size_t)kWaves * dh * 65 * sizeof(float);
+}
+
+template <int DH_dummy = 0>
+__device__ __forceinline__ void attn_item_any(const AttnArgs& a, int item, bool live,
+                                              float* tr_all) {
+  switch (a.dh) {  // other head sizes are rejected when the model is created
+    case 16: attn_item<16>(a, item, live, tr_all); break;
+    case 32: attn_item<32>(a, item, live, tr_all); break;
+    case 48: attn_item<48>(a, item, live, tr_all); break;
+    default: attn_item<64>(a, item, live, tr_all); break;
+  }
+}
+
+// ------------------------------------------------------------ symbol items
+// ydec[pos(m)][c] = src[(compact ? m : pos(m))][c]
+__device__ __forceinline__ void gather_item(const int32_t* src, int compact, const int* pos, int C,
+                                            int32_t* ydec, long idx) {
+  const int m = idx / C, c = idx % C;
+  const int p = map_row(pos, m);
+  ydec[(size_t)p * C + c] = src[(size_t)(compact ? m : p) * C + c];
+}
+
+// bits[pos(m)][c] = -log2(max(P, 1e-9)) of ydec under N(mean, scale)
+__device__ __forceinline__ void bits_item(const int* pos, int C, const int32_t* ydec,
+                                          const float* mean, const float* scale, float* bits,
+                                          long idx) {
+  const int m = idx / C, c = idx % C;
+  const size_t o = (size_t)map_row(pos, m) * C + c;
+  const float v = fabsf(float(ydec[o]) - mean[o]);
+  const float s2 = scale[o] * 1.41421356237309515f;
+  const float p = 0.5f * (erfcf((v - 0.5f) / s2) - erfcf((v + 0.5f) / s2));
+  bits[o] = -log2f(fmaxf(p, 1e-9f));
+}
+
+}  // namespace dev
+}  // namespace pswa

@@ -1,0 +1,195 @@
+// The network as a list of phases. One pass over a set of rows (one
+// diagonal of one or many frames, or every position of a frame) runs
+//   accumulator: q GEMM -> window attention (+ null slot) -> O GEMM (+ h)
+//   per layer:   QKV GEMM -> window attention -> O GEMM (+ residual)
+//                -> gate/up SwiGLU GEMM -> down GEMM (+ residual)
+//   head:        W1 GEMM (SiLU) -> W2 GEMM (mean, scale, CDF selection)
+//   symbols:     gather the diagonal's symbols, their bits
+//   embedding:   W_in GEMM -> accumulator K/V GEMM
+// The argument builders below are __host__ __device__: the per-launch path
+// calls them on the host, the persistent kernel on the device, so both run
+// the same arithmetic on the same operands.
+#pragma once
+
+#include "pswa_internal.h"
+
+namespace pswa {
+
+constexpr int kMaxLayers = 16;
+
+struct LayerWeights {
+  const float *g1, *Wqkv, *bias, *Wo, *g2, *Wgate, *Wup, *Wdown;
+};
+
+struct DevWeights {
+  const float *hyperW, *P4, *ing, *inW, *acc_gq, *acc_Wq, *acc_gkv, *acc_Wkv, *knull, *vnull,
+      *acc_bias, *acc_Wo;
+  LayerWeights layers[kMaxLayers];
+  const float *head_g, *W1, *W2, *gmu, *bmu, *gsig, *bsig;
+};
+
+struct NetDims {
+  int L, d, heads, dh, r, s, F, C, Ch, n_acc, n_sp, n_tm;
+  float ln_smin, ln_smax, inv_delta;
+};
+
+// Buffers and row maps of one pass.
+struct PassCtx {
+  int M;
+  const int* gpos;            // global position of each row (null: identity)
+  const int* fid;             // frame of each row (null: frame0)
+  const FrameInfo* frames;
+  FrameInfo frame0;
+  int HWt;
+  const float* h;             // hyper tokens [HWt][d]
+  float* acc_kv;              // [HWt][2d]
+  float* kv;                  // layer 0 K/V [HWt][2d]; layer l at kv + l * kv_stride
+  size_t kv_stride;
+  const float* tkv;           // layer 0 temporal K/V [2][HWt][2d] (or null)
+  size_t tkv_stride;
+  float *x, *q, *att, *e, *t1, *hmid;  // row activations
+  float *mean, *scale, *bits;          // [HWt][C]
+  int32_t* center;
+  uint16_t* index;
+  int32_t* center_c;          // compact copies for the bitstream decoder (or null)
+  uint16_t* index_c;
+  int* flag;
+  const int32_t* ysrc;        // symbol source
+  int src_compact;            // 1: ysrc is [M][C] compact, 0: [HWt][C]
+  int32_t* ydec;              // decoded symbols [HWt][C]
+};
+
+struct NetOp {
+  int kind;      // 0: GEMM, 1: attention, 2: symbols (gather + bits)
+  int ak, rms, epi;
+};
+
+__host__ __device__ inline GemmArgs gemm_base(int M, int N, int K, int role) {
+  GemmArgs g{};
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.role = role;
+  return g;
+}
+
+__host__ __device__ inline AttnArgs attn_base(const NetDims& x, const PassCtx& c, int role) {
+  AttnArgs a{};
+  a.role = role;
+  a.M = c.M;
+  a.pos = c.gpos;
+  a.fid = c.fid;
+  a.frames = c.frames;
+  a.frame0 = c.frame0;
+  a.HWt = c.HWt;
+  a.r = x.r;
+  a.heads = x.heads;
+  a.dh = x.dh;
+  a.d = x.d;
+  a.q = c.q;
+  a.ldq = x.d;
+  a.out = c.att;
+  a.ldo = x.d;
+  return a;
+}
+
+// ---- accumulator
+__host__ __device__ inline GemmArgs args_acc_q(const NetDims& x, const DevWeights& w,
+                                               const PassCtx& c) {
+  GemmArgs g = gemm_base(c.M, x.d, x.d, R_ACC_Q);
+  g.X = c.h; g.ldx = x.d; g.xrow = c.gpos; g.gain = w.acc_gq; g.W = w.acc_Wq;
+  g.Y = c.q; g.ldy = x.d;
+  return g;
+}
+__host__ __device__ inline AttnArgs args_acc_attn(const NetDims& x, const DevWeights& w,
+                                                  const PassCtx& c) {
+  AttnArgs a = attn_base(x, c, R_ACC_ATTN);
+  a.kv = c.acc_kv; a.tkv = nullptr; a.bias = w.acc_bias; a.nbias = x.n_acc;
+  a.knull = w.knull; a.vnull = w.vnull; a.include_self = 0;
+  return a;
+}
+__host__ __device__ inline GemmArgs args_acc_o(const NetDims& x, const DevWeights& w,
+                                               const PassCtx& c) {
+  GemmArgs g = gemm_base(c.M, x.d, x.d, R_ACC_O);
+  g.X = c.att; g.ldx = x.d; g.W = w.acc_Wo;
+  g.R = c.h; g.ldr = x.d; g.rrow = c.gpos; g.Y = c.x; g.ldy = x.d;
+  return g;
+}
+
+// ---- layers
+__host__ __device__ inline GemmArgs args_qkv(const NetDims& x, const DevWeights& w,
+                                             const PassCtx& c, int l) {
+  const LayerWeights& L = w.layers[l];
+  GemmArgs g = gemm_base(c.M, 3 * x.d, x.d, R_QKV);
+  g.X = c.x; g.ldx = x.d; g.gain = L.g1; g.W = L.Wqkv;
+  g.Y = c.q; g.ldy = x.d; g.Y2 = c.kv + l * c.kv_stride; g.ldy2 = 2 * x.d; g.y2row = c.gpos;
+  g.nsplit = x.d;
+  return g;
+}
+__host__ __device__ inline AttnArgs args_attn(const NetDims& x, const DevWeights& w,
+                                              const PassCtx& c, int l) {
+  AttnArgs a = attn_base(x, c, R_ATTN);
+  a.kv = c.kv + l * c.kv_stride;
+  a.tkv = c.tkv ? c.tkv + l * c.tkv_stride : nullptr;
+  a.bias = w.layers[l].bias; a.nbias = x.n_sp + x.n_tm;
+  a.knull = nullptr; a.vnull = nullptr; a.include_self = 1;
+  return a;
+}
+__host__ __device__ inline GemmArgs args_o(const NetDims& x, const DevWeights& w,
+                                           const PassCtx& c, int l) {
+  GemmArgs g = gemm_base(c.M, x.d, x.d, R_O);
+  g.X = c.att; g.ldx = x.d; g.W = w.layers[l].Wo;
+  g.R = c.x; g.ldr = x.d; g.Y = c.x; g.ldy = x.d;
+  return g;
+}
+__host__ __device__ inline GemmArgs args_gateup(const NetDims& x, const DevWeights& w,
+                                                const PassCtx& c, int l) {
+  GemmArgs g = gemm_base(c.M, x.F, x.d, R_GATEUP);
+  g.X = c.x; g.ldx = x.d; g.gain = w.layers[l].g2; g.W = w.layers[l].Wgate;
+  g.W2 = w.layers[l].Wup; g.Y = c.hmid; g.ldy = x.F;
+  return g;
+}
+__host__ __device__ inline GemmArgs args_down(const NetDims& x, const DevWeights& w,
+                                              const PassCtx& c, int l) {
+  GemmArgs g = gemm_base(c.M, x.d, x.F, R_DOWN);
+  g.X = c.hmid; g.ldx = x.F; g.W = w.layers[l].Wdown;
+  g.R = c.x; g.ldr = x.d; g.Y = c.x; g.ldy = x.d;
+  return g;
+}
+
+// ---- head
+__host__ __device__ inline GemmArgs args_head1(const NetDims& x, const DevWeights& w,
+                                               const PassCtx& c) {
+  GemmArgs g = gemm_base(c.M, x.d, x.d, R_HEAD1);
+  g.X = c.x; g.ldx = x.d; g.gain = w.head_g; g.W = w.W1; g.Y = c.t1; g.ldy = x.d;
+  return g;
+}
+__host__ __device__ inline GemmArgs args_head2(const NetDims& x, const DevWeights& w,
+                                               const PassCtx& c) {
+  GemmArgs g = gemm_base(c.M, x.C, x.d, R_HEAD2);
+  g.X = c.t1; g.ldx = x.d; g.W = w.W2; g.W2 = w.W2 + (size_t)x.C * x.d; g.yrow = c.gpos;
+  g.head.gmu = w.gmu; g.head.bmu = w.bmu; g.head.gsig = w.gsig; g.head.bsig = w.bsig;
+  g.head.ln_smin = x.ln_smin; g.head.ln_smax = x.ln_smax; g.head.inv_delta = x.inv_delta;
+  g.head.mean = c.mean; g.head.scale = c.scale; g.head.center = c.center;
+  g.head.index = c.index; g.head.center_c = c.center_c; g.head.index_c = c.index_c;
+  g.head.flag = c.flag;
+  return g;
+}
+
+// ---- embedding of decoded symbols (rows read from ydec at their positions)
+__host__ __device__ inline GemmArgs args_embed(const NetDims& x, const DevWeights& w,
+                                               const PassCtx& c) {
+  GemmArgs g = gemm_base(c.M, x.d, x.C, R_EMBED);
+  g.Xi = c.ydec; g.ldx = x.C; g.xrow = c.gpos; g.xscale = w.ing; g.W = w.inW;
+  g.Y = c.e; g.ldy = x.d;
+  return g;
+}
+__host__ __device__ inline GemmArgs args_acc_kv(const NetDims& x, const DevWeights& w,
+                                                const PassCtx& c) {
+  GemmArgs g = gemm_base(c.M, 2 * x.d, x.d, R_ACCKV);
+  g.X = c.e; g.ldx = x.d; g.gain = w.acc_gkv; g.W = w.acc_Wkv;
+  g.Y = c.acc_kv; g.ldy = 2 * x.d; g.yrow = c.gpos;
+  return g;
+}
+
+}  // namespace pswa

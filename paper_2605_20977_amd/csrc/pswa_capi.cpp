@@ -1,4 +1,6 @@
-// C ABI and host runtime of the wavefront context model (see include/pswa.h).
+// C ABI and host runtime of the wavefront context model (see include/pswa.h):
+// model upload, the parallel encode form, the per-diagonal decode and the
+// entropy-coder calls.
 //
 // The runtime owns no device memory: it lays out caller-provided regions
 // (model weights, encode workspace, decode state) and enqueues kernels on the
@@ -17,13 +19,16 @@
 #include <vector>
 
 #include "../../include/pswa.h"
-#include "pswa_internal.h"
+#include "persistent.h"
+#include "runtime.h"
 
 using namespace pswa;
 
-namespace {
+namespace pswa {
 
+namespace {
 thread_local std::string g_last_error;
+}  // namespace
 
 pswa_status fail(pswa_status st, const char* fmt, ...) {
   char buf[512];
@@ -35,33 +40,89 @@ pswa_status fail(pswa_status st, const char* fmt, ...) {
   return st;
 }
 
-#define HIP_TRY(expr)                                                              \
-  do {                                                                             \
-    hipError_t e_ = (expr);                                                        \
-    if (e_ != hipSuccess)                                                          \
-      return fail(PSWA_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));      \
-  } while (0)
+const char* last_error() { return g_last_error.c_str(); }
 
-constexpr size_t kAlign = 256;
-constexpr size_t kTensorAlign = 64;  // floats
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+bool valid_frame(const pswa_frame_desc* f, std::string* why) {
+  if (!f) return *why = "null frame desc", false;
+  if (f->H < 1 || f->W < 1 || (int64_t)f->H * f->W > (1 << 24))
+    return *why = "H, W must be >= 1 with H*W <= 2^24", false;
+  if (f->Hh != (f->H + 3) / 4 || f->Wh != (f->W + 3) / 4)
+    return *why = "hyperprior grid must be ceil(H/4) x ceil(W/4)", false;
+  if (f->n_prev != 0 && f->n_prev != 2) return *why = "n_prev must be 0 or 2", false;
+  return true;
+}
 
-// Bump allocator over a caller-provided region (also used to size it).
-struct Layout {
-  char* base;
-  size_t used = 0;
-  explicit Layout(void* b = nullptr) : base(static_cast<char*>(b)) {}
-  template <class T>
-  T* take(size_t count) {
-    T* p = base ? reinterpret_cast<T*>(base + used) : nullptr;
-    used += align_up(count * sizeof(T));
-    return p;
+int diag_len(int H, int W, int s, int t) {
+  int n = 0;
+  for (int i = 0; i < H; ++i) {
+    const int j = t - s * i;
+    if (j >= 0 && j < W) ++n;
   }
-};
+  return n;
+}
+
+Acts take_acts(Layout& L, const NetDims& x, size_t rows) {
+  Acts a;
+  a.x = L.take<float>(rows * x.d);
+  a.q = L.take<float>(rows * x.d);
+  a.att = L.take<float>(rows * x.d);
+  a.e = L.take<float>(rows * x.d);
+  a.t1 = L.take<float>(rows * x.d);
+  a.hmid = L.take<float>(rows * x.F);
+  return a;
+}
+
+void run_embed(const pswa_model* m, const PassCtx& c, hipStream_t st) {
+  gemm_f32(A_INT, false, EPI_STORE, args_embed(m->x, m->w, c), st);
+  gemm_f32(A_FLOAT, true, EPI_STORE, args_acc_kv(m->x, m->w, c), st);
+}
+
+void embed_prev(const pswa_model* m, int HW, int HWt, int off, const int32_t* prev, float* e_prev,
+                hipStream_t st) {
+  const NetDims& x = m->x;
+  for (int tau = 0; tau < 2; ++tau) {
+    GemmArgs a = gemm_base(HW, x.d, x.C, R_TKV);
+    a.Xi = prev + (size_t)tau * HW * x.C; a.ldx = x.C; a.xscale = m->w.ing; a.W = m->w.inW;
+    a.Y = e_prev + ((size_t)tau * HWt + off) * x.d; a.ldy = x.d;
+    gemm_f32(A_INT, false, EPI_STORE, a, st);
+  }
+}
+
+void temporal_kv_layer(const pswa_model* m, int HW, int HWt, int off, const float* e_prev, int l,
+                       float* tkv_l, hipStream_t st) {
+  const NetDims& x = m->x;
+  for (int tau = 0; tau < 2; ++tau) {
+    GemmArgs a = gemm_base(HW, 2 * x.d, x.d, R_TKV);
+    a.X = e_prev + ((size_t)tau * HWt + off) * x.d; a.ldx = x.d; a.gain = m->w.layers[l].g1;
+    a.W = m->w.layers[l].Wqkv + (size_t)x.d * x.d;
+    a.Y = tkv_l + ((size_t)tau * HWt + off) * 2 * x.d; a.ldy = 2 * x.d;
+    gemm_f32(A_FLOAT, true, EPI_STORE, a, st);
+  }
+}
+
+pswa_status finish_sum(const float* bits, size_t n, float* d_sum, const int* d_flag,
+                       double* h_total, hipStream_t st) {
+  sum_f32(bits, n, d_sum, st);
+  PSWA_HIP_TRY(hipGetLastError());
+  float s = 0.f;
+  int flag = 0;
+  PSWA_HIP_TRY(hipMemcpyAsync(&s, d_sum, sizeof s, hipMemcpyDeviceToHost, st));
+  PSWA_HIP_TRY(hipMemcpyAsync(&flag, d_flag, sizeof flag, hipMemcpyDeviceToHost, st));
+  PSWA_HIP_TRY(hipStreamSynchronize(st));
+  *h_total = double(s);
+  if (flag) return fail(PSWA_E_NUMERIC, "non-finite mean or scale produced");
+  return PSWA_OK;
+}
+
+}  // namespace pswa
+
+namespace {
+
+constexpr size_t kTensorAlign = 64;  // floats
 
 bool valid_desc(const pswa_model_desc* d, std::string* why) {
   if (!d) return *why = "null model desc", false;
-  if (d->L < 1 || d->L > 64) return *why = "L out of range [1, 64]", false;
+  if (d->L < 1 || d->L > kMaxLayers) return *why = "L out of range [1, 16]", false;
   if (d->d < 64 || d->d % 64 != 0 || d->d > 1024) return *why = "d must be a multiple of 64 in [64, 1024]", false;
   if (d->heads < 1 || d->d % d->heads != 0) return *why = "heads must divide d", false;
   const int dh = d->d / d->heads;
@@ -75,17 +136,12 @@ bool valid_desc(const pswa_model_desc* d, std::string* why) {
   return true;
 }
 
-struct Dims {
-  int L, d, heads, dh, r, k, s, F, C, Ch, n_acc, n_sp, n_tm;
-};
-
-Dims dims_of(const pswa_model_desc& m) {
-  Dims x;
+NetDims dims_of(const pswa_model_desc& m) {
+  NetDims x{};
   x.L = m.L;
   x.d = m.d;
   x.heads = m.heads;
   x.dh = m.d / m.heads;
-  x.k = m.window;
   x.r = (m.window - 1) / 2;
   x.s = x.r + 1;
   x.F = m.mlp_ratio * m.d;
@@ -94,24 +150,16 @@ Dims dims_of(const pswa_model_desc& m) {
   x.n_acc = 2 * x.r * (x.r + 1);
   x.n_sp = x.n_acc + 1;
   x.n_tm = 2 * (2 * x.r + 1) * (2 * x.r + 1);
+  x.ln_smin = ln_sigma_min_f32();
+  x.ln_smax = float(std::log(kSigmaMax));
+  x.inv_delta = inv_delta_f32();
   return x;
 }
-
-struct LayerW {
-  const float *g1, *Wqkv, *bias, *Wo, *g2, *Wgate, *Wup, *Wdown;
-};
-
-struct Weights {
-  const float *hyperW, *P4, *ing, *inW, *acc_gq, *acc_Wq, *acc_gkv, *acc_Wkv, *knull, *vnull,
-      *acc_bias, *acc_Wo;
-  std::vector<LayerW> layers;
-  const float *head_g, *W1, *W2, *gmu, *bmu, *gsig, *bsig;
-};
 
 // Walks the documented blob order; with base == nullptr it only counts.
 // align > 1 pads every tensor to a multiple of `align` floats (the device
 // layout keeps each tensor 256-byte aligned for vector loads).
-size_t blob_layout(const Dims& x, const float* base, Weights* w, size_t align = 1,
+size_t blob_layout(const NetDims& x, const float* base, DevWeights* w, size_t align = 1,
                    std::vector<std::pair<size_t, size_t>>* spans = nullptr) {
   size_t off = 0;
   auto t = [&](size_t n) {
@@ -121,8 +169,8 @@ size_t blob_layout(const Dims& x, const float* base, Weights* w, size_t align = 
     return p;
   };
   const size_t d = x.d, C = x.C, Ch = x.Ch, F = x.F, h = x.heads;
-  Weights tmp;
-  Weights& W = w ? *w : tmp;
+  DevWeights tmp{};
+  DevWeights& W = w ? *w : tmp;
   W.hyperW = t(d * Ch);
   W.P4 = t(16 * d);
   W.ing = t(C);
@@ -135,9 +183,8 @@ size_t blob_layout(const Dims& x, const float* base, Weights* w, size_t align = 
   W.vnull = t(d);
   W.acc_bias = t(h * x.n_acc);
   W.acc_Wo = t(d * d);
-  W.layers.assign(x.L, LayerW{});
   for (int l = 0; l < x.L; ++l) {
-    LayerW& L = W.layers[l];
+    LayerWeights& L = W.layers[l];
     L.g1 = t(d);
     L.Wqkv = t(3 * d * d);
     L.bias = t(h * (x.n_sp + x.n_tm));
@@ -157,200 +204,16 @@ size_t blob_layout(const Dims& x, const float* base, Weights* w, size_t align = 
   return off;
 }
 
-}  // namespace
-
-struct pswa_model {
-  pswa_model_desc desc;
-  Dims x;
-  Weights w;
-  float ln_smin, ln_smax, inv_delta;
-};
-
-namespace {
-
-bool valid_frame(const pswa_model* m, const pswa_frame_desc* f, std::string* why) {
-  if (!f) return *why = "null frame desc", false;
-  if (f->H < 1 || f->W < 1 || (int64_t)f->H * f->W > (1 << 24))
-    return *why = "H, W must be >= 1 with H*W <= 2^24", false;
-  if (f->Hh != (f->H + 3) / 4 || f->Wh != (f->W + 3) / 4)
-    return *why = "hyperprior grid must be ceil(H/4) x ceil(W/4)", false;
-  if (f->n_prev != 0 && f->n_prev != 2) return *why = "n_prev must be 0 or 2", false;
-  (void)m;
-  return true;
-}
-
-// Activation buffers for `rows` rows.
-struct Acts {
-  float *x, *q, *att, *e, *t1, *hmid;
-};
-
-Acts take_acts(Layout& L, const Dims& x, size_t rows) {
-  Acts a;
-  a.x = L.take<float>(rows * x.d);
-  a.q = L.take<float>(rows * x.d);
-  a.att = L.take<float>(rows * x.d);
-  a.e = L.take<float>(rows * x.d);
-  a.t1 = L.take<float>(rows * x.d);
-  a.hmid = L.take<float>(rows * x.F);
-  return a;
-}
-
-// Per-symbol outputs [HW][C].
-struct SymOut {
-  float *mean, *scale, *bits;
-  int32_t* center;
-  uint16_t* index;
-};
-
-// Everything one pass over a set of rows needs.
-struct RowPass {
-  int M;
-  const int* pos;        // row -> position (null: identity)
-  const float* h;        // hyper tokens [HW][d]
-  float* acc_kv;         // [HW][2d]
-  Acts a;
-  SymOut out;
-  int32_t* center_c;     // compact copies for the bitstream decoder (or null)
-  uint16_t* index_c;
-  int* flag;
-};
-
-struct FrameGeom {
-  int H, W;
-};
-
-// Accumulator, L layers and head for the pass's rows. kv_of(l) gives layer
-// l's K/V cache [HW][2d]; tkv_of(l) its temporal K/V [2][HW][2d] or null.
-template <class KvOf, class TkvOf, class BeforeLayer>
-void run_rows(const pswa_model* m, const FrameGeom& g, const RowPass& P, KvOf kv_of,
-              TkvOf tkv_of, BeforeLayer before_layer, hipStream_t st) {
-  const Dims& x = m->x;
-  const Weights& w = m->w;
-  const int d = x.d;
-
-  // Accumulator: q from the hyper token, keys strictly past + null slot.
-  GemmArgs q{};
-  q.M = P.M; q.N = d; q.K = d;
-  q.X = P.h; q.ldx = d; q.xrow = P.pos; q.gain = w.acc_gq; q.W = w.acc_Wq;
-  q.Y = P.a.q; q.ldy = d;
-  gemm_f32(A_FLOAT, true, EPI_STORE, q, st);
-
-  AttnArgs at{};
-  at.M = P.M; at.pos = P.pos; at.H = g.H; at.W = g.W; at.r = x.r; at.heads = x.heads;
-  at.dh = x.dh; at.d = d; at.q = P.a.q; at.ldq = d; at.kv = P.acc_kv; at.tkv = nullptr;
-  at.bias = w.acc_bias; at.nbias = x.n_acc; at.knull = w.knull; at.vnull = w.vnull;
-  at.include_self = 0; at.out = P.a.att; at.ldo = d;
-  attention_f32(at, st);
-
-  GemmArgs o{};
-  o.M = P.M; o.N = d; o.K = d;
-  o.X = P.a.att; o.ldx = d; o.W = w.acc_Wo;
-  o.R = P.h; o.ldr = d; o.rrow = P.pos; o.Y = P.a.x; o.ldy = d;
-  gemm_f32(A_FLOAT, false, EPI_RESID, o, st);
-
-  for (int l = 0; l < x.L; ++l) {
-    const LayerW& L = w.layers[l];
-    before_layer(l);
-    float* kv = kv_of(l);
-    GemmArgs a{};
-    a.M = P.M; a.N = 3 * d; a.K = d;
-    a.X = P.a.x; a.ldx = d; a.gain = L.g1; a.W = L.Wqkv;
-    a.Y = P.a.q; a.ldy = d; a.Y2 = kv; a.ldy2 = 2 * d; a.y2row = P.pos; a.nsplit = d;
-    gemm_f32(A_FLOAT, true, EPI_QKV, a, st);
-
-    AttnArgs la = at;
-    la.kv = kv; la.tkv = tkv_of(l); la.bias = L.bias; la.nbias = x.n_sp + x.n_tm;
-    la.knull = nullptr; la.vnull = nullptr; la.include_self = 1;
-    attention_f32(la, st);
-
-    GemmArgs b{};
-    b.M = P.M; b.N = d; b.K = d;
-    b.X = P.a.att; b.ldx = d; b.W = L.Wo; b.R = P.a.x; b.ldr = d; b.Y = P.a.x; b.ldy = d;
-    gemm_f32(A_FLOAT, false, EPI_RESID, b, st);
-
-    GemmArgs c{};
-    c.M = P.M; c.N = x.F; c.K = d;
-    c.X = P.a.x; c.ldx = d; c.gain = L.g2; c.W = L.Wgate; c.W2 = L.Wup;
-    c.Y = P.a.hmid; c.ldy = x.F;
-    gemm_f32(A_FLOAT, true, EPI_SWIGLU, c, st);
-
-    GemmArgs e{};
-    e.M = P.M; e.N = d; e.K = x.F;
-    e.X = P.a.hmid; e.ldx = x.F; e.W = L.Wdown; e.R = P.a.x; e.ldr = d; e.Y = P.a.x; e.ldy = d;
-    gemm_f32(A_FLOAT, false, EPI_RESID, e, st);
-  }
-
-  GemmArgs h1{};
-  h1.M = P.M; h1.N = d; h1.K = d;
-  h1.X = P.a.x; h1.ldx = d; h1.gain = w.head_g; h1.W = w.W1; h1.Y = P.a.t1; h1.ldy = d;
-  gemm_f32(A_FLOAT, true, EPI_SILU, h1, st);
-
-  GemmArgs h2{};
-  h2.M = P.M; h2.N = x.C; h2.K = d;
-  h2.X = P.a.t1; h2.ldx = d; h2.W = w.W2; h2.W2 = w.W2 + (size_t)x.C * d; h2.yrow = P.pos;
-  h2.head.gmu = w.gmu; h2.head.bmu = w.bmu; h2.head.gsig = w.gsig; h2.head.bsig = w.bsig;
-  h2.head.ln_smin = m->ln_smin; h2.head.ln_smax = m->ln_smax; h2.head.inv_delta = m->inv_delta;
-  h2.head.mean = P.out.mean; h2.head.scale = P.out.scale; h2.head.center = P.out.center;
-  h2.head.index = P.out.index; h2.head.center_c = P.center_c; h2.head.index_c = P.index_c;
-  h2.head.flag = P.flag;
-  gemm_f32(A_FLOAT, false, EPI_HEAD, h2, st);
-}
-
-// Embedding of decoded latents (rows given by pos) and their accumulator K/V.
-void embed_rows(const pswa_model* m, int M, const int* pos, const int32_t* lat, float* e,
-                float* acc_kv, hipStream_t st) {
-  const Dims& x = m->x;
-  GemmArgs a{};
-  a.M = M; a.N = x.d; a.K = x.C;
-  a.Xi = lat; a.ldx = x.C; a.xrow = pos; a.xscale = m->w.ing; a.W = m->w.inW;
-  a.Y = e; a.ldy = x.d;
-  gemm_f32(A_INT, false, EPI_STORE, a, st);
-  GemmArgs b{};
-  b.M = M; b.N = 2 * x.d; b.K = x.d;
-  b.X = e; b.ldx = x.d; b.gain = m->w.acc_gkv; b.W = m->w.acc_Wkv;
-  b.Y = acc_kv; b.ldy = 2 * x.d; b.yrow = pos;
-  gemm_f32(A_FLOAT, true, EPI_STORE, b, st);
-}
-
-// Layer-l temporal K/V of the two previous frames from their embeddings.
-void temporal_kv_layer(const pswa_model* m, int HW, const float* e_prev, int l, float* tkv,
-                       hipStream_t st) {
-  const Dims& x = m->x;
-  for (int tau = 0; tau < 2; ++tau) {
-    GemmArgs a{};
-    a.M = HW; a.N = 2 * x.d; a.K = x.d;
-    a.X = e_prev + (size_t)tau * HW * x.d; a.ldx = x.d; a.gain = m->w.layers[l].g1;
-    a.W = m->w.layers[l].Wqkv + (size_t)x.d * x.d;
-    a.Y = tkv + (size_t)tau * HW * 2 * x.d; a.ldy = 2 * x.d;
-    gemm_f32(A_FLOAT, true, EPI_STORE, a, st);
-  }
-}
-
-void embed_prev(const pswa_model* m, int HW, const int32_t* prev, float* e_prev, hipStream_t st) {
-  const Dims& x = m->x;
-  for (int tau = 0; tau < 2; ++tau) {
-    GemmArgs a{};
-    a.M = HW; a.N = x.d; a.K = x.C;
-    a.Xi = prev + (size_t)tau * HW * x.C; a.ldx = x.C; a.xscale = m->w.ing; a.W = m->w.inW;
-    a.Y = e_prev + (size_t)tau * HW * x.d; a.ldy = x.d;
-    gemm_f32(A_INT, false, EPI_STORE, a, st);
-  }
-}
-
 // ------------------------------------------------------------ encode ws
 struct EncodeWs {
-  float* h;
-  float* acc_kv;
-  float* kv;
-  float* tkv;
-  float* e_prev;
+  float *h, *acc_kv, *kv, *tkv, *e_prev;
   Acts a;
   int* flag;
   float* sum;
   size_t bytes;
 };
 
-EncodeWs plan_encode(const Dims& x, const pswa_frame_desc& f, void* base) {
+EncodeWs plan_encode(const NetDims& x, const pswa_frame_desc& f, void* base) {
   Layout L(base);
   const size_t HW = (size_t)f.H * f.W;
   EncodeWs w;
@@ -381,7 +244,9 @@ struct pswa_state {
   // device
   float *h, *acc_kv, *kv, *tkv, *e_prev;
   int32_t* ydec;
-  SymOut out;
+  float *mean, *scale, *bits;
+  int32_t* center;
+  uint16_t* index;
   int* pos_all;
   Acts a;
   int32_t* cc;
@@ -403,25 +268,12 @@ struct pswa_state {
 
 namespace {
 
-int steps_of(int H, int W, int s) { return (W - 1) + s * (H - 1) + 1; }
-
-int diag_len(int H, int W, int s, int t) {
-  int n = 0;
-  for (int i = 0; i < H; ++i) {
-    const int j = t - s * i;
-    if (j >= 0 && j < W) ++n;
-  }
-  return n;
-}
-
-void plan_state(const Dims& x, const pswa_frame_desc& f, void* base, pswa_state* st) {
+void plan_state(const NetDims& x, const pswa_frame_desc& f, void* base, pswa_state* st) {
   Layout L(base);
   const size_t HW = (size_t)f.H * f.W;
-  int nmax = 0;
-  const int T = steps_of(f.H, f.W, x.s);
-  // n_t is maximal on the diagonals where every row fits: min(H, ceil(W/s)) bounds it.
-  nmax = std::min(f.H, (f.W + x.s - 1) / x.s);
-  st->T = T;
+  // n_t never exceeds min(H, ceil(W/s)): one position per row, s-spaced columns.
+  const int nmax = std::min(f.H, (f.W + x.s - 1) / x.s);
+  st->T = steps_of(f.H, f.W, x.s);
   st->nmax = nmax;
   st->h = L.take<float>(HW * x.d);
   st->acc_kv = L.take<float>(HW * 2 * x.d);
@@ -429,11 +281,11 @@ void plan_state(const Dims& x, const pswa_frame_desc& f, void* base, pswa_state*
   st->tkv = f.n_prev ? L.take<float>((size_t)x.L * 2 * HW * 2 * x.d) : nullptr;
   st->e_prev = f.n_prev ? L.take<float>(2 * HW * x.d) : nullptr;
   st->ydec = L.take<int32_t>(HW * x.C);
-  st->out.mean = L.take<float>(HW * x.C);
-  st->out.scale = L.take<float>(HW * x.C);
-  st->out.bits = L.take<float>(HW * x.C);
-  st->out.center = L.take<int32_t>(HW * x.C);
-  st->out.index = L.take<uint16_t>(HW * x.C);
+  st->mean = L.take<float>(HW * x.C);
+  st->scale = L.take<float>(HW * x.C);
+  st->bits = L.take<float>(HW * x.C);
+  st->center = L.take<int32_t>(HW * x.C);
+  st->index = L.take<uint16_t>(HW * x.C);
   st->pos_all = L.take<int>(HW);
   st->a = take_acts(L, x, nmax);
   st->cc = L.take<int32_t>((size_t)nmax * x.C);
@@ -444,25 +296,18 @@ void plan_state(const Dims& x, const pswa_frame_desc& f, void* base, pswa_state*
   st->bytes = L.used;
 }
 
-pswa_status finish_sum(const float* bits, size_t n, float* d_sum, const int* d_flag,
-                       double* h_total, hipStream_t st) {
-  sum_f32(bits, n, d_sum, st);
-  HIP_TRY(hipGetLastError());
-  float s = 0.f;
-  int flag = 0;
-  HIP_TRY(hipMemcpyAsync(&s, d_sum, sizeof s, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(&flag, d_flag, sizeof flag, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  *h_total = double(s);
-  if (flag) return fail(PSWA_E_NUMERIC, "non-finite mean or scale produced");
-  return PSWA_OK;
+PassCtx frame_ctx(const pswa_frame_desc& f) {
+  PassCtx c{};
+  c.frame0 = FrameInfo{f.H, f.W, 0, f.n_prev};
+  c.HWt = f.H * f.W;
+  return c;
 }
 
 }  // namespace
 
 extern "C" {
 
-const char* pswa_last_error(void) { return g_last_error.c_str(); }
+const char* pswa_last_error(void) { return pswa::last_error(); }
 
 size_t pswa_model_blob_floats(const pswa_model_desc* desc) {
   std::string why;
@@ -486,7 +331,7 @@ pswa_status pswa_model_create(const pswa_model_desc* desc, const float* h_blob,
   if (!h_blob || !d_mem) return fail(PSWA_E_ARG, "null blob or device memory");
   if ((reinterpret_cast<uintptr_t>(d_mem) % kAlign) != 0)
     return fail(PSWA_E_ARG, "device memory must be 256-byte aligned");
-  const Dims x = dims_of(*desc);
+  const NetDims x = dims_of(*desc);
   const size_t need = blob_layout(x, nullptr, nullptr);
   if (blob_floats != need)
     return fail(PSWA_E_SHAPE, "blob has %zu floats, model needs %zu", blob_floats, need);
@@ -502,15 +347,14 @@ pswa_status pswa_model_create(const pswa_model_desc* desc, const float* h_blob,
   std::vector<float> padded(dev_floats, 0.f);
   for (size_t i = 0; i < src.size(); ++i)
     std::memcpy(padded.data() + dst[i].first, h_blob + src[i].first, src[i].second * sizeof(float));
-  HIP_TRY(hipMemcpyAsync(d_mem, padded.data(), dev_floats * sizeof(float), hipMemcpyHostToDevice, st));
-  HIP_TRY(hipStreamSynchronize(st));
+  PSWA_HIP_TRY(hipMemcpyAsync(d_mem, padded.data(), dev_floats * sizeof(float),
+                              hipMemcpyHostToDevice, st));
+  PSWA_HIP_TRY(hipStreamSynchronize(st));
   auto* m = new pswa_model;
   m->desc = *desc;
   m->x = x;
+  m->w = DevWeights{};
   blob_layout(x, static_cast<const float*>(d_mem), &m->w, kTensorAlign);
-  m->ln_smin = ln_sigma_min_f32();
-  m->ln_smax = float(std::log(kSigmaMax));
-  m->inv_delta = inv_delta_f32();
   *out = m;
   return PSWA_OK;
 }
@@ -519,7 +363,7 @@ void pswa_model_destroy(pswa_model* model) { delete model; }
 
 size_t pswa_encode_workspace_bytes(const pswa_model* model, const pswa_frame_desc* frame) {
   std::string why;
-  if (!model || !valid_frame(model, frame, &why)) return 0;
+  if (!model || !valid_frame(frame, &why)) return 0;
   return plan_encode(model->x, *frame, nullptr).bytes;
 }
 
@@ -530,40 +374,45 @@ pswa_status pswa_encode_params(const pswa_model* model, const pswa_frame_desc* f
                                double* h_total_bits, void* d_ws, size_t ws_bytes, void* stream) {
   std::string why;
   if (!model) return fail(PSWA_E_ARG, "model is null");
-  if (!valid_frame(model, frame, &why)) return fail(PSWA_E_SHAPE, "invalid frame: %s", why.c_str());
+  if (!valid_frame(frame, &why)) return fail(PSWA_E_SHAPE, "invalid frame: %s", why.c_str());
   if (!d_latents || !d_hyper || !d_mean || !d_scale || !d_bits || !d_cdf_center || !d_cdf_index || !d_ws)
     return fail(PSWA_E_ARG, "null pointer argument");
   if (frame->n_prev == 2 && !d_prev) return fail(PSWA_E_ARG, "P-frame needs d_prev");
   if (frame->n_prev == 0 && d_prev) return fail(PSWA_E_ARG, "I-frame must pass d_prev = NULL");
   if ((reinterpret_cast<uintptr_t>(d_ws) % kAlign) != 0)
     return fail(PSWA_E_ARG, "workspace must be 256-byte aligned");
-  const Dims& x = model->x;
+  const NetDims& x = model->x;
   EncodeWs ws = plan_encode(x, *frame, d_ws);
   if (ws_bytes < ws.bytes) return fail(PSWA_E_ARG, "workspace %zu bytes < %zu", ws_bytes, ws.bytes);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int HW = frame->H * frame->W;
-  const FrameGeom g{frame->H, frame->W};
 
-  HIP_TRY(hipMemsetAsync(ws.flag, 0, sizeof(int), st));
+  zero_ints(ws.flag, 1, st);
   hyper_embed(d_hyper, frame->Hh, frame->Wh, x.Ch, model->w.hyperW, model->w.P4, frame->H,
               frame->W, x.d, ws.h, st);
-  embed_rows(model, HW, nullptr, d_latents, ws.a.e, ws.acc_kv, st);
-  if (frame->n_prev) embed_prev(model, HW, d_prev, ws.e_prev, st);
-
-  RowPass P{};
-  P.M = HW; P.pos = nullptr; P.h = ws.h; P.acc_kv = ws.acc_kv; P.a = ws.a;
-  P.out = SymOut{d_mean, d_scale, d_bits, d_cdf_center, d_cdf_index};
-  P.center_c = nullptr; P.index_c = nullptr; P.flag = ws.flag;
+  PassCtx c = frame_ctx(*frame);
+  c.M = HW;
+  c.h = ws.h;
+  c.acc_kv = ws.acc_kv;
+  c.kv = ws.kv;
+  c.kv_stride = 0;  // one K/V buffer, refilled layer by layer
+  c.tkv = frame->n_prev ? ws.tkv : nullptr;
+  c.tkv_stride = 0;
+  c.x = ws.a.x; c.q = ws.a.q; c.att = ws.a.att; c.e = ws.a.e; c.t1 = ws.a.t1; c.hmid = ws.a.hmid;
+  c.mean = d_mean; c.scale = d_scale; c.bits = d_bits; c.center = d_cdf_center;
+  c.index = d_cdf_index; c.flag = ws.flag;
+  c.ydec = const_cast<int32_t*>(d_latents);  // only read: the encoder knows every symbol
+  run_embed(model, c, st);
+  if (frame->n_prev) embed_prev(model, HW, HW, 0, d_prev, ws.e_prev, st);
   const bool pf = frame->n_prev != 0;
-  run_rows(
-      model, g, P, [&](int) { return ws.kv; },
-      [&](int) -> const float* { return pf ? ws.tkv : nullptr; },
+  run_pass(
+      model, c,
       [&](int l) {
-        if (pf) temporal_kv_layer(model, HW, ws.e_prev, l, ws.tkv, st);
+        if (pf) temporal_kv_layer(model, HW, HW, 0, ws.e_prev, l, ws.tkv, st);
       },
       st);
   symbol_bits(nullptr, HW, x.C, d_latents, d_mean, d_scale, d_bits, st);
-  HIP_TRY(hipGetLastError());
+  PSWA_HIP_TRY(hipGetLastError());
   if (h_total_bits)
     return finish_sum(d_bits, (size_t)HW * x.C, ws.sum, ws.flag, h_total_bits, st);
   return PSWA_OK;
@@ -571,7 +420,7 @@ pswa_status pswa_encode_params(const pswa_model* model, const pswa_frame_desc* f
 
 size_t pswa_state_bytes(const pswa_model* model, const pswa_frame_desc* frame) {
   std::string why;
-  if (!model || !valid_frame(model, frame, &why)) return 0;
+  if (!model || !valid_frame(frame, &why)) return 0;
   pswa_state tmp;
   plan_state(model->x, *frame, nullptr, &tmp);
   return tmp.bytes;
@@ -585,7 +434,7 @@ pswa_status pswa_decode_begin(const pswa_model* model, const pswa_frame_desc* fr
   if (!out) return fail(PSWA_E_ARG, "out is null");
   *out = nullptr;
   if (!model) return fail(PSWA_E_ARG, "model is null");
-  if (!valid_frame(model, frame, &why)) return fail(PSWA_E_SHAPE, "invalid frame: %s", why.c_str());
+  if (!valid_frame(frame, &why)) return fail(PSWA_E_SHAPE, "invalid frame: %s", why.c_str());
   if (!d_hyper || !src || !d_state_mem) return fail(PSWA_E_ARG, "null pointer argument");
   if (symbol_source != PSWA_SRC_DEVICE && symbol_source != PSWA_SRC_BITSTREAM)
     return fail(PSWA_E_ARG, "unknown symbol source %d", symbol_source);
@@ -599,7 +448,7 @@ pswa_status pswa_decode_begin(const pswa_model* model, const pswa_frame_desc* fr
   S->model = model;
   S->f = *frame;
   S->source = symbol_source;
-  const Dims& x = model->x;
+  const NetDims& x = model->x;
   S->start.assign(S->T + 1, 0);
   for (int t = 0; t < S->T; ++t)
     S->start[t + 1] = S->start[t] + diag_len(frame->H, frame->W, x.s, t);
@@ -610,22 +459,22 @@ pswa_status pswa_decode_begin(const pswa_model* model, const pswa_frame_desc* fr
     S->stream.assign(b, b + src_bytes);
     S->dec.reset(new RangeDecoder(S->stream.data(), S->stream.size()));
     const size_t n = (size_t)S->nmax * x.C;
-    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&S->h_cc), n * sizeof(int32_t), hipHostMallocDefault));
-    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&S->h_ci), n * sizeof(uint16_t), hipHostMallocDefault));
-    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&S->h_sym), n * sizeof(int32_t), hipHostMallocDefault));
+    PSWA_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&S->h_cc), n * sizeof(int32_t), hipHostMallocDefault));
+    PSWA_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&S->h_ci), n * sizeof(uint16_t), hipHostMallocDefault));
+    PSWA_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&S->h_sym), n * sizeof(int32_t), hipHostMallocDefault));
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int HW = frame->H * frame->W;
-  HIP_TRY(hipMemsetAsync(S->flag, 0, sizeof(int), st));
+  zero_ints(S->flag, 1, st);
   fill_positions(frame->H, frame->W, x.s, S->pos_all, st);
   hyper_embed(d_hyper, frame->Hh, frame->Wh, x.Ch, model->w.hyperW, model->w.P4, frame->H,
               frame->W, x.d, S->h, st);
   if (frame->n_prev) {
-    embed_prev(model, HW, d_prev, S->e_prev, st);
+    embed_prev(model, HW, HW, 0, d_prev, S->e_prev, st);
     for (int l = 0; l < x.L; ++l)
-      temporal_kv_layer(model, HW, S->e_prev, l, S->tkv + (size_t)l * 2 * HW * 2 * x.d, st);
+      temporal_kv_layer(model, HW, HW, 0, S->e_prev, l, S->tkv + (size_t)l * 2 * HW * 2 * x.d, st);
   }
-  HIP_TRY(hipGetLastError());
+  PSWA_HIP_TRY(hipGetLastError());
   *out = S.release();
   return PSWA_OK;
 }
@@ -638,41 +487,47 @@ pswa_status pswa_decode_step(pswa_state* S, int t, void* stream) {
     return fail(PSWA_E_ORDER, "decode_step(%d) called, next step is %d", t, S->next_t);
   if (t >= S->T) return fail(PSWA_E_ORDER, "all %d steps already decoded", S->T);
   const pswa_model* m = S->model;
-  const Dims& x = m->x;
+  const NetDims& x = m->x;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int HW = S->f.H * S->f.W;
   const int n = S->start[t + 1] - S->start[t];
   const int* pos = S->pos_all + S->start[t];
   const bool bs = S->source == PSWA_SRC_BITSTREAM;
 
-  RowPass P{};
-  P.M = n; P.pos = pos; P.h = S->h; P.acc_kv = S->acc_kv; P.a = S->a; P.out = S->out;
-  P.center_c = bs ? S->cc : nullptr; P.index_c = bs ? S->ci : nullptr; P.flag = S->flag;
-  run_rows(
-      m, FrameGeom{S->f.H, S->f.W}, P,
-      [&](int l) { return S->kv + (size_t)l * HW * 2 * x.d; },
-      [&](int l) -> const float* {
-        return S->tkv ? S->tkv + (size_t)l * 2 * HW * 2 * x.d : nullptr;
-      },
-      [](int) {}, st);
+  PassCtx c = frame_ctx(S->f);
+  c.M = n;
+  c.gpos = pos;
+  c.h = S->h;
+  c.acc_kv = S->acc_kv;
+  c.kv = S->kv;
+  c.kv_stride = (size_t)HW * 2 * x.d;
+  c.tkv = S->tkv;
+  c.tkv_stride = (size_t)2 * HW * 2 * x.d;
+  c.x = S->a.x; c.q = S->a.q; c.att = S->a.att; c.e = S->a.e; c.t1 = S->a.t1; c.hmid = S->a.hmid;
+  c.mean = S->mean; c.scale = S->scale; c.bits = S->bits; c.center = S->center;
+  c.index = S->index; c.flag = S->flag;
+  c.center_c = bs ? S->cc : nullptr;
+  c.index_c = bs ? S->ci : nullptr;
+  c.ydec = S->ydec;
+  run_pass(m, c, [](int) {}, st);
 
   if (!bs) {
     gather_symbols(S->d_src, 0, pos, n, x.C, S->ydec, st);
   } else {
     const size_t cnt = (size_t)n * x.C;
-    HIP_TRY(hipMemcpyAsync(S->h_cc, S->cc, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(S->h_ci, S->ci, cnt * sizeof(uint16_t), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    PSWA_HIP_TRY(hipMemcpyAsync(S->h_cc, S->cc, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    PSWA_HIP_TRY(hipMemcpyAsync(S->h_ci, S->ci, cnt * sizeof(uint16_t), hipMemcpyDeviceToHost, st));
+    PSWA_HIP_TRY(hipStreamSynchronize(st));
     for (size_t k = 0; k < cnt; ++k) {
       if (!S->dec->symbol(S->h_cc[k], S->h_ci[k], &S->h_sym[k]))
         return fail(PSWA_E_CORRUPT, "bitstream corrupt or truncated at step %d", t);
     }
-    HIP_TRY(hipMemcpyAsync(S->csym, S->h_sym, cnt * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    PSWA_HIP_TRY(hipMemcpyAsync(S->csym, S->h_sym, cnt * sizeof(int32_t), hipMemcpyHostToDevice, st));
     gather_symbols(S->csym, 1, pos, n, x.C, S->ydec, st);
   }
-  symbol_bits(pos, n, x.C, S->ydec, S->out.mean, S->out.scale, S->out.bits, st);
-  embed_rows(m, n, pos, S->ydec, S->a.e, S->acc_kv, st);
-  HIP_TRY(hipGetLastError());
+  symbol_bits(pos, n, x.C, S->ydec, S->mean, S->scale, S->bits, st);
+  run_embed(m, c, st);
+  PSWA_HIP_TRY(hipGetLastError());
   S->next_t = t + 1;
   return PSWA_OK;
 }
@@ -688,13 +543,13 @@ pswa_status pswa_decode_end(pswa_state* S, int32_t* d_latents_out, float* d_mean
   auto cp = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
     return dst ? hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st) : hipSuccess;
   };
-  HIP_TRY(cp(d_latents_out, S->ydec, n * sizeof(int32_t)));
-  HIP_TRY(cp(d_mean, S->out.mean, n * sizeof(float)));
-  HIP_TRY(cp(d_scale, S->out.scale, n * sizeof(float)));
-  HIP_TRY(cp(d_bits, S->out.bits, n * sizeof(float)));
-  HIP_TRY(cp(d_cdf_center, S->out.center, n * sizeof(int32_t)));
-  HIP_TRY(cp(d_cdf_index, S->out.index, n * sizeof(uint16_t)));
-  if (h_total_bits) return finish_sum(S->out.bits, n, S->sum, S->flag, h_total_bits, st);
+  PSWA_HIP_TRY(cp(d_latents_out, S->ydec, n * sizeof(int32_t)));
+  PSWA_HIP_TRY(cp(d_mean, S->mean, n * sizeof(float)));
+  PSWA_HIP_TRY(cp(d_scale, S->scale, n * sizeof(float)));
+  PSWA_HIP_TRY(cp(d_bits, S->bits, n * sizeof(float)));
+  PSWA_HIP_TRY(cp(d_cdf_center, S->center, n * sizeof(int32_t)));
+  PSWA_HIP_TRY(cp(d_cdf_index, S->index, n * sizeof(uint16_t)));
+  if (h_total_bits) return finish_sum(S->bits, n, S->sum, S->flag, h_total_bits, st);
   return PSWA_OK;
 }
 
@@ -706,7 +561,7 @@ pswa_status pswa_cdf_select(const float* d_mean, const float* d_log_scale, size_
   if (!d_mean || !d_log_scale || !d_center || !d_index) return fail(PSWA_E_ARG, "null pointer argument");
   cdf_select(d_mean, d_log_scale, n, ln_sigma_min_f32(), inv_delta_f32(), d_center, d_index,
              static_cast<hipStream_t>(stream));
-  HIP_TRY(hipGetLastError());
+  PSWA_HIP_TRY(hipGetLastError());
   return PSWA_OK;
 }
 

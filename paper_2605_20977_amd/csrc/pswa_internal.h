@@ -11,6 +11,17 @@
 
 namespace pswa {
 
+// ------------------------------------------------------------- profiling
+// Role of a launch, for the live kernel timer (profile.cpp).
+enum Role {
+  R_ACC_Q, R_ACC_ATTN, R_ACC_O, R_QKV, R_ATTN, R_O, R_GATEUP, R_DOWN, R_HEAD1, R_HEAD2,
+  R_EMBED, R_ACCKV, R_BITS, R_GATHER, R_HYPER, R_TKV, R_SUM, R_OTHER, R_COUNT
+};
+const char* role_name(int r);
+bool prof_on();
+int prof_begin(hipStream_t s);  // -1 when timing is off
+void prof_end(int ev, hipStream_t s, int role, double bytes, double flops);
+
 // ------------------------------------------------------------------ GEMM
 // Y[m][n] = epilogue( sum_k A[m][k] * W[n][k] ), accumulated k = 0..K-1 in
 // order by one thread per output, so a row's value never depends on how many
@@ -38,6 +49,7 @@ struct HeadOut {
 
 struct GemmArgs {
   int M, N, K;
+  int role = R_OTHER;
   const float* X = nullptr;              // A_FLOAT: row m at X + xrow(m)*ldx
   const int32_t* Xi = nullptr;           // A_INT:   row m at Xi + xrow(m)*ldx, times xscale[k]
   const float* xscale = nullptr;
@@ -60,15 +72,32 @@ struct GemmArgs {
 };
 
 void gemm_f32(AKind ak, bool rms, Epi epi, const GemmArgs& a, hipStream_t s);
+double gemm_alg_bytes(const GemmArgs& a, Epi epi);
+
+// Kernels whose dynamic LDS can exceed 64 KiB opt in to 156 KiB (the
+// 160 KiB per workgroup less room for their static LDS).
+constexpr size_t kMaxDynLds = 156 * 1024;
+bool allow_big_lds(const void* fn);
 
 // ------------------------------------------------------------- attention
+// A frame in the global position space of a launch: its grid, the global
+// index of its position (0, 0), and whether it has previous-frame keys.
+struct FrameInfo {
+  int H, W, off, n_prev;
+};
+
 struct AttnArgs {
+  int role;
   int M;                       // query rows
-  const int* pos;              // flat position i*W + j of row m (null: m)
-  int H, W, r, heads, dh, d;
+  const int* pos;              // global position of row m (null: m)
+  const int* fid;              // frame of row m (null: every row is frame0)
+  const FrameInfo* frames;     // frame table indexed by fid
+  FrameInfo frame0;
+  int HWt;                     // positions in the global space (temporal K/V stride)
+  int r, heads, dh, d;
   const float* q; int ldq;     // [M][d]
-  const float* kv;             // [HW][2d]: K then V per position
-  const float* tkv;            // [2][HW][2d] temporal K/V (or null)
+  const float* kv;             // [HWt][2d]: K then V per position
+  const float* tkv;            // [2][HWt][2d] temporal K/V (or null)
   const float* bias; int nbias;  // [heads][nbias]
   const float* knull;          // accumulator null slot (null in layer mode)
   const float* vnull;
@@ -76,6 +105,7 @@ struct AttnArgs {
   float* out; int ldo;         // [M][d]
 };
 void attention_f32(const AttnArgs& a, hipStream_t s);
+double attn_alg_bytes(const AttnArgs& a);
 
 // ----------------------------------------------------------------- misc
 void hyper_embed(const int32_t* z, int Hh, int Wh, int Ch, const float* Wh_, const float* P4,

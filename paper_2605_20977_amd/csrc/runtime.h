@@ -1,0 +1,92 @@
+// Host runtime pieces shared by the C ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/pswa.h"
+#include "network.h"
+#include "pswa_internal.h"
+
+struct pswa_model {
+  pswa_model_desc desc;
+  pswa::NetDims x;
+  pswa::DevWeights w;
+};
+
+namespace pswa {
+
+pswa_status fail(pswa_status st, const char* fmt, ...);
+
+#define PSWA_HIP_TRY(expr)                                                          \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return ::pswa::fail(PSWA_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Bump allocator over a caller-provided region (also used to size it).
+struct Layout {
+  char* base;
+  size_t used = 0;
+  explicit Layout(void* b = nullptr) : base(static_cast<char*>(b)) {}
+  template <class T>
+  T* take(size_t count) {
+    T* p = base ? reinterpret_cast<T*>(base + used) : nullptr;
+    used += align_up(count * sizeof(T));
+    return p;
+  }
+};
+
+bool valid_frame(const pswa_frame_desc* f, std::string* why);
+inline int steps_of(int H, int W, int s) { return (W - 1) + s * (H - 1) + 1; }
+int diag_len(int H, int W, int s, int t);
+
+// Row activations for `rows` rows.
+struct Acts {
+  float *x, *q, *att, *e, *t1, *hmid;
+};
+Acts take_acts(Layout& L, const NetDims& x, size_t rows);
+
+// One pass of the network over c's rows with per-phase launches.
+// before_layer(l) runs before layer l's QKV (the encode form builds the
+// layer's temporal K/V there).
+template <class BeforeLayer>
+void run_pass(const pswa_model* m, const PassCtx& c, BeforeLayer before_layer, hipStream_t st) {
+  const NetDims& x = m->x;
+  const DevWeights& w = m->w;
+  gemm_f32(A_FLOAT, true, EPI_STORE, args_acc_q(x, w, c), st);
+  attention_f32(args_acc_attn(x, w, c), st);
+  gemm_f32(A_FLOAT, false, EPI_RESID, args_acc_o(x, w, c), st);
+  for (int l = 0; l < x.L; ++l) {
+    before_layer(l);
+    gemm_f32(A_FLOAT, true, EPI_QKV, args_qkv(x, w, c, l), st);
+    attention_f32(args_attn(x, w, c, l), st);
+    gemm_f32(A_FLOAT, false, EPI_RESID, args_o(x, w, c, l), st);
+    gemm_f32(A_FLOAT, true, EPI_SWIGLU, args_gateup(x, w, c, l), st);
+    gemm_f32(A_FLOAT, false, EPI_RESID, args_down(x, w, c, l), st);
+  }
+  gemm_f32(A_FLOAT, true, EPI_SILU, args_head1(x, w, c), st);
+  gemm_f32(A_FLOAT, false, EPI_HEAD, args_head2(x, w, c), st);
+}
+
+// Embedding of decoded symbols (read from c.ydec at the rows' positions) and
+// their accumulator K/V.
+void run_embed(const pswa_model* m, const PassCtx& c, hipStream_t st);
+
+// e_prev[tau] (rows off .. off+HW of a [2][HWt][d] buffer) from prev [2][HW][C].
+void embed_prev(const pswa_model* m, int HW, int HWt, int off, const int32_t* prev, float* e_prev,
+                hipStream_t st);
+// Layer-l temporal K/V (rows off .. off+HW of [2][HWt][2d]) from e_prev.
+void temporal_kv_layer(const pswa_model* m, int HW, int HWt, int off, const float* e_prev, int l,
+                       float* tkv_l, hipStream_t st);
+
+pswa_status finish_sum(const float* bits, size_t n, float* d_sum, const int* d_flag,
+                       double* h_total, hipStream_t st);
+
+}  // namespace pswa

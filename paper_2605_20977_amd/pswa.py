@@ -40,6 +40,11 @@ class FrameDesc(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("H", "W", "Hh", "Wh", "n_prev")]
 
 
+class BatchFrame(C.Structure):
+    _fields_ = [("frame", FrameDesc), ("d_hyper", C.c_void_p), ("d_prev", C.c_void_p),
+                ("d_latents", C.c_void_p)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(
@@ -69,6 +74,22 @@ def _load():
         "pswa_range_encode_seq": (i32, [sz, vp, vp, vp, vp, sz, P(sz)]),
         "pswa_range_decode_seq": (i32, [vp, sz, sz, vp, vp, vp]),
         "pswa_last_error": (C.c_char_p, []),
+        "pswa_batch_workspace_bytes": (sz, [vp, i32, P(BatchFrame)]),
+        "pswa_batch_create": (i32, [vp, i32, P(BatchFrame), i32, vp, sz, vp, P(vp)]),
+        "pswa_batch_run": (i32, [vp, vp]),
+        "pswa_batch_check": (i32, [vp, vp]),
+        "pswa_batch_outputs": (i32, [vp, i32, vp, vp, vp, vp, vp, vp, P(C.c_double), vp]),
+        "pswa_batch_num_steps": (i32, [vp]),
+        "pswa_batch_max_rows": (i32, [vp]),
+        "pswa_batch_grid": (i32, [vp]),
+        "pswa_batch_max_grid": (i32, [vp]),
+        "pswa_batch_set_grid": (i32, [vp, i32]),
+        "pswa_batch_set_spin_limit": (i32, [vp, C.c_int64]),
+        "pswa_batch_destroy": (None, [vp]),
+        "pswa_profile_enable": (i32, [i32]),
+        "pswa_profile_roles": (i32, []),
+        "pswa_profile_read": (i32, [i32, C.c_char_p, sz, P(C.c_double), P(C.c_int64),
+                                    P(C.c_double), P(C.c_double)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -83,7 +104,11 @@ EXPORTED = ("pswa_model_blob_floats", "pswa_model_device_bytes", "pswa_model_cre
             "pswa_state_bytes", "pswa_decode_begin", "pswa_num_steps", "pswa_decode_step",
             "pswa_decode_end", "pswa_state_destroy", "pswa_cdf_select", "pswa_cdf_tables",
             "pswa_range_encode", "pswa_range_encode_seq", "pswa_range_decode_seq",
-            "pswa_last_error")
+            "pswa_last_error", "pswa_profile_enable", "pswa_profile_roles", "pswa_profile_read",
+            "pswa_batch_workspace_bytes", "pswa_batch_create", "pswa_batch_run",
+            "pswa_batch_check", "pswa_batch_outputs", "pswa_batch_num_steps",
+            "pswa_batch_max_rows", "pswa_batch_grid", "pswa_batch_max_grid",
+            "pswa_batch_set_grid", "pswa_batch_set_spin_limit", "pswa_batch_destroy")
 
 
 def lib():
@@ -318,6 +343,89 @@ def index_u16(t):
     return t.cpu().numpy().view(np.uint16)
 
 
+# ---------------------------------------------------------- batched decode
+
+class Batch:
+    """Persistent decode of many frames in one launch.
+
+    frames: list of dict(latents=[H][W][C], hyper=[Hh][Wh][Ch], prev=None or
+    [2][H][W][C]) as numpy arrays or tensors (moved to the model's device)."""
+
+    def __init__(self, model: Model, frames, grid=0):
+        import torch
+        self.model = model
+        dev = model.mem.device
+        self._keep = []
+        arr = (BatchFrame * len(frames))()
+        self.shapes = []
+        for k, f in enumerate(frames):
+            y = _i32(f["latents"], dev)
+            z = _i32(f["hyper"], dev)
+            pv = _i32(f["prev"], dev) if f.get("prev") is not None else None
+            _shape_check(model, y, z, pv)
+            H, W = y.shape[0], y.shape[1]
+            self.shapes.append((H, W))
+            self._keep += [y, z, pv]
+            arr[k].frame = frame_desc(H, W, 2 if pv is not None else 0)
+            arr[k].d_hyper = _ptr(z)
+            arr[k].d_prev = _ptr(pv)
+            arr[k].d_latents = _ptr(y)
+        self._frames = arr
+        nb = _lib.pswa_batch_workspace_bytes(model.handle, len(frames), arr)
+        if nb == 0:
+            raise PswaError(-2, "invalid batch")
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+        h = C.c_void_p()
+        _check(_lib.pswa_batch_create(model.handle, len(frames), arr, grid, _ptr(self.ws), nb,
+                                      _stream(), C.byref(h)))
+        self.handle = h
+        self.T = _lib.pswa_batch_num_steps(h)
+        self.max_rows = _lib.pswa_batch_max_rows(h)
+
+    @property
+    def grid(self):
+        return _lib.pswa_batch_grid(self.handle)
+
+    @property
+    def max_grid(self):
+        return _lib.pswa_batch_max_grid(self.handle)
+
+    def set_grid(self, g):
+        _check(_lib.pswa_batch_set_grid(self.handle, int(g)))
+
+    def set_spin_limit(self, n):
+        _check(_lib.pswa_batch_set_spin_limit(self.handle, int(n)))
+
+    def run(self):
+        _check(_lib.pswa_batch_run(self.handle, _stream()))
+
+    def check(self):
+        _check(_lib.pswa_batch_check(self.handle, _stream()))
+
+    def outputs(self, f, total_bits=True):
+        import torch
+        H, W = self.shapes[f]
+        dev = self.ws.device
+        out = _outputs(H, W, self.model.cfg.C, dev)
+        out["latents"] = torch.empty((H, W, self.model.cfg.C), dtype=torch.int32, device=dev)
+        tot = C.c_double(0.0)
+        _check(_lib.pswa_batch_outputs(self.handle, f, _ptr(out["latents"]), _ptr(out["mean"]),
+                                       _ptr(out["scale"]), _ptr(out["bits"]),
+                                       _ptr(out["center"]), _ptr(out["index"]),
+                                       C.byref(tot) if total_bits else None, _stream()))
+        if total_bits:
+            out["total_bits"] = tot.value
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.pswa_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+
 # ------------------------------------------------------------ entropy side
 
 def pswa_cdf_select(mean, log_scale):
@@ -376,4 +484,25 @@ def pswa_range_decode_seq(data: bytes, center, index):
     _check(_lib.pswa_range_decode_seq(buf.ctypes.data if buf.size else None, buf.size,
                                       ce.size, ce.ctypes.data, ix.ctypes.data,
                                       out.ctypes.data))
+    return out
+
+
+# --------------------------------------------------------------- profiling
+
+def pswa_profile_enable(on: bool):
+    _check(_lib.pswa_profile_enable(1 if on else 0))
+
+
+def pswa_profile_read():
+    """{role: dict(ms, launches, bytes, flops)} for roles with launches."""
+    out = {}
+    name = C.create_string_buffer(64)
+    ms, n = C.c_double(), C.c_int64()
+    by, fl = C.c_double(), C.c_double()
+    for r in range(_lib.pswa_profile_roles()):
+        _check(_lib.pswa_profile_read(r, name, 64, C.byref(ms), C.byref(n), C.byref(by),
+                                      C.byref(fl)))
+        if n.value:
+            out[name.value.decode()] = {"ms": ms.value, "launches": n.value,
+                                        "bytes": by.value, "flops": fl.value}
     return out
