@@ -273,6 +273,15 @@ pswa_status pswa_range_encode_seq(size_t n, const int32_t* h_symbols,
 
 const char* pswa_last_error(void);
 
+/* Host quantization used for projection weights (pswa_model_create):
+ *   PSWA_BF16: h_out uint16 [n], bfloat16 of each value, round to nearest even;
+ *   PSWA_FP8_E4M3: h_out uint8 [n], OCP FP8 e4m3fn (bias 7, max 448, no
+ *     infinities) of value * s with the per-tensor scale s = 448 / max|value|
+ *     (1 for an all-zero tensor), round to nearest even, saturating;
+ *     *h_inv_scale = 1 / s.
+ * PSWA_FP32 is rejected (nothing to do). */
+pswa_status pswa_quantize(int prec, const float* h_in, size_t n, void* h_out, float* h_inv_scale);
+
 /* ------------------------------------------------------------ profiling */
 
 /* Live kernel timer (a profiling aid, off by default). While enabled, every

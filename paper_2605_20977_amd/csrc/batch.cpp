@@ -24,12 +24,19 @@
 
 using namespace pswa;
 
+namespace {
+// Default persistent grid: the barrier's cost grows with the number of
+// blocks, and a decode phase rarely has work for more.
+constexpr int kDefaultGrid = 64;
+}  // namespace
+
 struct pswa_batch {
   const pswa_model* model = nullptr;
   std::vector<pswa_batch_frame> frames;
   std::vector<FrameInfo> finfo;
   int HWt = 0, T = 0, Mmax = 0, grid = 0, max_grid = 0;
   long spin_limit = 1L << 21;  // barrier wait bound (about a second)
+  double alg_bytes = 0, alg_flops = 0;  // one persistent launch, for the timer
   bool any_p = false;
   // device (inside the caller's workspace)
   FrameInfo* d_frames = nullptr;
@@ -181,9 +188,55 @@ pswa_status run(pswa_batch* b, hipStream_t st) {
                           b->tkv + (size_t)l * 2 * b->HWt * 2 * x.d, st);
     }
   }
+  const int ev = prof_begin(st);
   launch_persistent(persist_args(b), b->grid, st);
+  prof_end(ev, st, R_PERSIST, b->alg_bytes, b->alg_flops);
   PSWA_HIP_TRY(hipGetLastError());
   return PSWA_OK;
+}
+
+// Algorithmic bytes and flops of one persistent launch: the per-phase
+// figures of the per-launch path (weights once per phase, activations in and
+// out, every window slot's K and V rows) summed over every step.
+void count_work(pswa_batch* b, const std::vector<int>& row_start) {
+  const NetDims& x = b->model->x;
+  const DevWeights& w = b->model->w;
+  double by = 0, fl = 0;
+  auto g = [&](const GemmArgs& a, Epi e) {
+    by += gemm_alg_bytes(a, e);
+    fl += 2.0 * a.M * a.N * a.K * ((e == EPI_SWIGLU || e == EPI_HEAD) ? 2.0 : 1.0);
+  };
+  auto at = [&](const AttnArgs& a) {
+    by += attn_alg_bytes(a);
+    const int k1 = 2 * a.r + 1;
+    const double keys = 2.0 * a.r * (a.r + 1) + (a.include_self ? 1 : 0) +
+                        (a.knull ? 1 : 0) + (a.tkv ? 2.0 * k1 * k1 : 0.0);
+    fl += double(a.M) * a.heads * keys * 4.0 * a.dh;
+  };
+  PersistArgs P = persist_args(b);
+  for (int t = 0; t < b->T; ++t) {
+    PassCtx c = P.c;
+    c.M = row_start[t + 1] - row_start[t];
+    if (c.M == 0) continue;
+    if (!b->any_p) c.tkv = nullptr;
+    g(args_acc_q(x, w, c), EPI_STORE);
+    at(args_acc_attn(x, w, c));
+    g(args_acc_o(x, w, c), EPI_RESID);
+    for (int l = 0; l < x.L; ++l) {
+      g(args_qkv(x, w, c, l), EPI_QKV);
+      at(args_attn(x, w, c, l));
+      g(args_o(x, w, c, l), EPI_RESID);
+      g(args_gateup(x, w, c, l), EPI_SWIGLU);
+      g(args_down(x, w, c, l), EPI_RESID);
+    }
+    g(args_head1(x, w, c), EPI_SILU);
+    g(args_head2(x, w, c), EPI_HEAD);
+    by += 16.0 * c.M * x.C + 4.0 * c.M;  // symbols and bits
+    g(args_embed(x, w, c), EPI_STORE);
+    g(args_acc_kv(x, w, c), EPI_STORE);
+  }
+  b->alg_bytes = by;
+  b->alg_flops = fl;
 }
 
 }  // namespace
@@ -207,8 +260,6 @@ pswa_status pswa_batch_create(const pswa_model* model, int n, const pswa_batch_f
   if (cs != PSWA_OK) return cs;
   if (!d_ws || (reinterpret_cast<uintptr_t>(d_ws) % kAlign) != 0)
     return fail(PSWA_E_ARG, "workspace must be non-null and 256-byte aligned");
-  if (model->desc.prec != PSWA_FP32)
-    return fail(PSWA_E_UNSUPPORTED, "batched decode of precision %d is not built", model->desc.prec);
   Plan p = make_plan(model->x, n, frames, true);
   std::unique_ptr<pswa_batch> b(new pswa_batch);
   lay_out(model->x, p, n, d_ws, b.get());
@@ -220,9 +271,9 @@ pswa_status pswa_batch_create(const pswa_model* model, int n, const pswa_batch_f
   b->T = p.T;
   b->Mmax = p.Mmax;
   b->any_p = p.any_p;
-  b->max_grid = persistent_max_grid(model->x);
+  b->max_grid = persistent_max_grid(model->x, model->w.prec);
   if (b->max_grid <= 0) return fail(PSWA_E_HIP, "cannot size the persistent grid");
-  b->grid = grid > 0 ? std::min(grid, b->max_grid) : std::min(b->max_grid, 256);
+  b->grid = grid > 0 ? std::min(grid, b->max_grid) : std::min(b->max_grid, kDefaultGrid);
   hipStream_t st = static_cast<hipStream_t>(stream);
   PSWA_HIP_TRY(hipMemcpyAsync(b->d_frames, p.finfo.data(), n * sizeof(FrameInfo),
                               hipMemcpyHostToDevice, st));
@@ -233,6 +284,7 @@ pswa_status pswa_batch_create(const pswa_model* model, int n, const pswa_batch_f
   PSWA_HIP_TRY(hipMemcpyAsync(b->fid_all, p.fid.data(), p.fid.size() * sizeof(int),
                               hipMemcpyHostToDevice, st));
   PSWA_HIP_TRY(hipStreamSynchronize(st));
+  count_work(b.get(), p.row_start);
   *out = b.release();
   return PSWA_OK;
 }

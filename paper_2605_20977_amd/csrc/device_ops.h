@@ -82,6 +82,46 @@ __host__ __device__ inline size_t gemm_lds_bytes(int K) {
   return tile > red ? tile : red;
 }
 
+// Epilogue of one GEMM output (row, n): v is the finished dot product with
+// W, v2 the one with W2 (paired epilogues only).
+template <int EPI>
+__device__ __forceinline__ void epilogue(const GemmArgs& a, int row, int n, float v, float v2) {
+  if (EPI == EPI_STORE) {
+    a.Y[(size_t)map_row(a.yrow, row) * a.ldy + n] = v;
+  } else if (EPI == EPI_RESID) {
+    const float r = a.R[(size_t)map_row(a.rrow, row) * a.ldr + n];
+    a.Y[(size_t)map_row(a.yrow, row) * a.ldy + n] = r + v;
+  } else if (EPI == EPI_QKV) {
+    if (n < a.nsplit)
+      a.Y[(size_t)row * a.ldy + n] = v;
+    else
+      a.Y2[(size_t)map_row(a.y2row, row) * a.ldy2 + (n - a.nsplit)] = v;
+  } else if (EPI == EPI_SILU) {
+    a.Y[(size_t)map_row(a.yrow, row) * a.ldy + n] = silu(v);
+  } else if (EPI == EPI_SWIGLU) {
+    a.Y[(size_t)map_row(a.yrow, row) * a.ldy + n] = silu(v) * v2;
+  } else if (EPI == EPI_HEAD) {
+    const HeadOut& h = a.head;
+    const float mu = fmaf(h.gmu[n], v, h.bmu[n]);
+    const float raw = fmaf(h.gsig[n], v2, h.bsig[n]);
+    const float ls = fminf(h.ln_smax, fmaxf(h.ln_smin, raw));
+    const float sg = expf(ls);
+    const size_t o = (size_t)map_row(a.yrow, row) * a.N + n;
+    h.mean[o] = mu;
+    h.scale[o] = sg;
+    int32_t c;
+    uint16_t x;
+    select_table(mu, ls, h.ln_smin, h.inv_delta, &c, &x);
+    h.center[o] = c;
+    h.index[o] = x;
+    if (h.center_c) {
+      h.center_c[(size_t)row * a.N + n] = c;
+      h.index_c[(size_t)row * a.N + n] = x;
+    }
+    if (!(fabsf(mu) <= FLT_MAX) || !(fabsf(raw) <= FLT_MAX)) atomicOr(h.flag, 1);
+  }
+}
+
 // ---------------------------------------------------------------- GEMM tile
 // Skinny FP32 GEMM tile: 16 weight rows (4 per wave) x up to 16 A rows.
 //   1. each wave loads its 4 weight rows into registers: lane l takes the
@@ -215,40 +255,7 @@ __device__ void gemm_tile(const GemmArgs& a, int bx, int by, float4* smem4, floa
   const int n = n0 + j;
   if (n >= a.N) return;
 
-  if (EPI == EPI_STORE) {
-    a.Y[(size_t)map_row(a.yrow, row) * a.ldy + n] = v;
-  } else if (EPI == EPI_RESID) {
-    const float r = a.R[(size_t)map_row(a.rrow, row) * a.ldr + n];
-    a.Y[(size_t)map_row(a.yrow, row) * a.ldy + n] = r + v;
-  } else if (EPI == EPI_QKV) {
-    if (n < a.nsplit)
-      a.Y[(size_t)row * a.ldy + n] = v;
-    else
-      a.Y2[(size_t)map_row(a.y2row, row) * a.ldy2 + (n - a.nsplit)] = v;
-  } else if (EPI == EPI_SILU) {
-    a.Y[(size_t)map_row(a.yrow, row) * a.ldy + n] = silu(v);
-  } else if (EPI == EPI_SWIGLU) {
-    a.Y[(size_t)map_row(a.yrow, row) * a.ldy + n] = silu(v) * v2;
-  } else if (EPI == EPI_HEAD) {
-    const HeadOut& h = a.head;
-    const float mu = fmaf(h.gmu[n], v, h.bmu[n]);
-    const float raw = fmaf(h.gsig[n], v2, h.bsig[n]);
-    const float ls = fminf(h.ln_smax, fmaxf(h.ln_smin, raw));
-    const float sg = expf(ls);
-    const size_t o = (size_t)map_row(a.yrow, row) * a.N + n;
-    h.mean[o] = mu;
-    h.scale[o] = sg;
-    int32_t c;
-    uint16_t x;
-    select_table(mu, ls, h.ln_smin, h.inv_delta, &c, &x);
-    h.center[o] = c;
-    h.index[o] = x;
-    if (h.center_c) {
-      h.center_c[(size_t)row * a.N + n] = c;
-      h.index_c[(size_t)row * a.N + n] = x;
-    }
-    if (!(fabsf(mu) <= FLT_MAX) || !(fabsf(raw) <= FLT_MAX)) atomicOr(h.flag, 1);
-  }
+  epilogue<EPI>(a, row, n, v, v2);
 }
 
 // Runtime choice of the chunk count (the same choice everywhere).

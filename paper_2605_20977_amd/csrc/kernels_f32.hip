@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device_ops.h"
+#include "mfma_ops.h"
 #include "pswa_internal.h"
 
 namespace pswa {
@@ -20,6 +21,14 @@ __global__ void __launch_bounds__(kThreads) k_gemm(GemmArgs a) {
   extern __shared__ float4 smem4[];
   __shared__ float rstd[kMB];
   gemm_tile<AK, RMS, EPI, KC>(a, blockIdx.x, blockIdx.y, smem4, rstd);
+}
+
+template <int AK, bool RMS, int EPI>
+__global__ void __launch_bounds__(kThreads) k_gemm_q(GemmArgs a) {
+  extern __shared__ float4 smem4[];
+  __shared__ float rstd[kMBq], rmul[kMBq];
+  gemm_tile_q_any<AK, RMS, EPI>(a, blockIdx.x, blockIdx.y, reinterpret_cast<uint8_t*>(smem4),
+                                rstd, rmul);
 }
 
 template <int DH>
@@ -100,6 +109,15 @@ inline unsigned blocks_for(long n, int t) { return unsigned((n + t - 1) / t); }
 
 template <int AK, bool RMS, int EPI>
 void launch_gemm(const GemmArgs& a, hipStream_t s) {
+  if (a.prec != PSWA_PREC_F32) {
+    static const bool attr_set =
+        allow_big_lds(reinterpret_cast<const void*>(&k_gemm_q<AK, RMS, EPI>));
+    (void)attr_set;
+    dim3 grid(qgemm_col_tiles(a.N, EPI), qgemm_row_tiles(a.M));
+    hipLaunchKernelGGL((k_gemm_q<AK, RMS, EPI>), grid, dim3(kThreads),
+                       qgemm_lds_bytes(a.K, a.prec), s, a);
+    return;
+  }
   dim3 grid(gemm_col_tiles(a.N, EPI), gemm_row_tiles(a.M));
   const size_t lds = gemm_lds_bytes(a.K);
 #define PSWA_KC(n)                                                                  \
@@ -156,7 +174,8 @@ bool allow_big_lds(const void* fn) {
 double gemm_alg_bytes(const GemmArgs& a, Epi epi) {
   // weights once, A rows in, outputs (and residual / head outputs) out
   const bool paired = epi == EPI_SWIGLU || epi == EPI_HEAD;
-  const double wmat = (paired ? 2.0 : 1.0) * a.N * a.K * 4.0;
+  const double wbytes = a.prec == PSWA_PREC_BF16 ? 2.0 : a.prec == PSWA_PREC_FP8 ? 1.0 : 4.0;
+  const double wmat = (paired ? 2.0 : 1.0) * a.N * a.K * wbytes;
   const double io = double(a.M) * a.K * 4.0 +
                     double(a.M) * a.N * 4.0 *
                         (epi == EPI_RESID ? 2.0 : epi == EPI_HEAD ? 4.5 : 1.0);
@@ -171,7 +190,7 @@ double attn_alg_bytes(const AttnArgs& a) {
   return double(a.M) * (keys * 2.0 * a.d * 4.0 + 2.0 * a.d * 4.0);
 }
 
-void gemm_f32(AKind ak, bool rms, Epi epi, const GemmArgs& a, hipStream_t s) {
+void gemm_run(AKind ak, bool rms, Epi epi, const GemmArgs& a, hipStream_t s) {
   if (a.M <= 0) return;
   const int ev = prof_begin(s);
   gemm_dispatch(ak, rms, epi, a, s);

@@ -1,0 +1,261 @@
+// Low-precision GEMM tile on gfx950 matrix cores (MFMA), shared by the
+// per-launch kernels and the persistent decode kernel.
+//
+// Projections and MLP run as BF16 or FP8 (OCP e4m3fn) products with FP32
+// accumulation; everything else (norm statistics, softmax, accumulator
+// attention, head nonlinearity, CDF selection) stays FP32.
+//
+// Tile: 32 A rows (two 16-row MFMA blocks) x 64 weight rows (16 per wave).
+//   1. row statistics, one wave per row, lane l over the row's float4 chunks
+//      l, l+64, ... in order: sum of squares (RMSNorm) through a fixed xor
+//      tree, and the row's absolute maximum after the gain (FP8 scale);
+//   2. the block stages the rows, times the gain (RMSNorm input) or the
+//      input scale (integer latents), as BF16 (round to nearest even) or as
+//      FP8 of (value * 448 / row max) (round to nearest even), in LDS with a
+//      16-byte skew per row;
+//   3. each wave runs v_mfma_f32_16x16x32_{bf16,fp8_fp8} over k = 0, 32, ...
+//      for its 16 weight rows (streamed from HBM, all loads of a chunk in
+//      flight) against both row blocks;
+//   4. the epilogue rescales (1/rms, row max / 448, 1 / weight scale) and
+//      applies the same epilogues as the FP32 tile.
+// A row's result depends only on that row, K and the weights: the same in
+// every launch shape, so encode and decode stay bit-identical.
+// Paired epilogues: columns 0-7 of a wave are W rows n..n+7 and columns 8-15
+// the W2 rows n..n+7; lane l (column < 8) takes its partner from lane l + 8.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "device_ops.h"
+
+namespace pswa {
+namespace dev {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMBq = 32;        // A rows per low-precision tile
+constexpr float kFp8Max = 448.0f;
+
+__host__ __device__ inline int qgemm_col_tiles(int N, int epi) {
+  const int per = kWaves * (paired_epi(epi) ? 8 : 16);
+  return (N + per - 1) / per;
+}
+__host__ __device__ inline int qgemm_row_tiles(int M) { return (M + kMBq - 1) / kMBq; }
+// element pitch of a staged row: K plus a 16-byte skew
+__host__ __device__ inline int qgemm_pitch(int K, int prec) { return K + (prec == PSWA_PREC_BF16 ? 8 : 16); }
+__host__ __device__ inline size_t qgemm_lds_bytes(int K, int prec) {
+  return (size_t)kMBq * qgemm_pitch(K, prec) * (prec == PSWA_PREC_BF16 ? 2 : 1);
+}
+
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+
+template <int AK, bool RMS, int EPI, int PREC>
+__device__ void gemm_tile_q(const GemmArgs& a, int bx, int by, uint8_t* smem, float* rstd,
+                            float* rmul) {
+  constexpr bool PAIRED = paired_epi(EPI);
+  constexpr int EB = PREC == PSWA_PREC_BF16 ? 2 : 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int K = a.K, K4 = a.K / 4;
+  const int pitch = qgemm_pitch(K, PREC);
+  const int m0 = by * kMBq;
+  const int rows = min(kMBq, a.M - m0);
+  __syncthreads();  // the previous tile of this block is done with the LDS
+
+  // 1. row statistics (two rows per wave at a time, every chunk in flight)
+  if (RMS || PREC == PSWA_PREC_FP8) {
+    for (int m = wave; m < rows; m += 2 * kWaves) {
+      float4 xs[2][8];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int mm = min(m + h * kWaves, rows - 1);
+        const size_t off = (size_t)map_row(a.xrow, m0 + mm) * a.ldx;
+#pragma unroll
+        for (int it = 0; it < 8; ++it) {
+          const int c = lane + 64 * it;
+          if (c < K4) {
+            if (AK == A_INT) {
+              const int4 xi = *reinterpret_cast<const int4*>(a.Xi + off + 4 * c);
+              xs[h][it] = make_float4(float(xi.x), float(xi.y), float(xi.z), float(xi.w));
+            } else {
+              xs[h][it] = *reinterpret_cast<const float4*>(a.X + off + 4 * c);
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        float ss = 0.f, mx = 0.f;
+#pragma unroll
+        for (int it = 0; it < 8; ++it) {
+          const int c = lane + 64 * it;
+          if (c < K4) {
+            const float4 x = xs[h][it];
+            if (RMS) ss = dot4(x, x, ss);
+            if (PREC == PSWA_PREC_FP8) {
+              float4 g = make_float4(1.f, 1.f, 1.f, 1.f);
+              if (RMS) g = *reinterpret_cast<const float4*>(a.gain + 4 * c);
+              if (AK == A_INT) g = *reinterpret_cast<const float4*>(a.xscale + 4 * c);
+              mx = fmaxf(mx, fmaxf(fmaxf(fabsf(x.x * g.x), fabsf(x.y * g.y)),
+                                   fmaxf(fabsf(x.z * g.z), fabsf(x.w * g.w))));
+            }
+          }
+        }
+        if (RMS) ss = wave_sum(ss);
+        if (PREC == PSWA_PREC_FP8) mx = wave_max(mx);
+        const int mm = m + h * kWaves;
+        if (lane == 0 && mm < rows) {
+          rstd[mm] = RMS ? 1.0f / sqrtf(ss / float(K) + kEps) : 1.0f;
+          // FP8 rows are stored as value * (448 / max); a zero row stays zero
+          rmul[mm] = PREC == PSWA_PREC_FP8 ? (mx > 0.f ? kFp8Max / mx : 1.0f) : 1.0f;
+        }
+      }
+    }
+  } else {
+    if (tid < kMBq) {
+      rstd[tid] = 1.0f;
+      rmul[tid] = 1.0f;
+    }
+  }
+  __syncthreads();
+
+  // 2. stage the scaled rows as BF16 / FP8, 8 loads per thread in flight;
+  // rows past the end of A are zeros (their results are dropped)
+  {
+    const int total = kMBq * K4;
+    for (int base = 0; base < total; base += 8 * kThreads) {
+      float4 xv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = base + u * kThreads + tid;
+        xv[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (e < total && e / K4 < rows) {
+          const int m = e / K4, c = e % K4;
+          const size_t off = (size_t)map_row(a.xrow, m0 + m) * a.ldx + 4 * c;
+          if (AK == A_INT) {
+            const int4 xi = *reinterpret_cast<const int4*>(a.Xi + off);
+            xv[u] = make_float4(float(xi.x), float(xi.y), float(xi.z), float(xi.w));
+          } else {
+            xv[u] = *reinterpret_cast<const float4*>(a.X + off);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = base + u * kThreads + tid;
+        if (e >= total) continue;
+        const int m = e / K4, c = e % K4;
+        float4 g = make_float4(1.f, 1.f, 1.f, 1.f);
+        if (RMS) g = *reinterpret_cast<const float4*>(a.gain + 4 * c);
+        if (AK == A_INT) g = *reinterpret_cast<const float4*>(a.xscale + 4 * c);
+        const float4 x = make_float4(xv[u].x * g.x, xv[u].y * g.y, xv[u].z * g.z, xv[u].w * g.w);
+        if (PREC == PSWA_PREC_BF16) {
+          uint2 v;
+          v.x = uint32_t(bf16_rne(x.x)) | (uint32_t(bf16_rne(x.y)) << 16);
+          v.y = uint32_t(bf16_rne(x.z)) | (uint32_t(bf16_rne(x.w)) << 16);
+          *reinterpret_cast<uint2*>(smem + (size_t)(m * pitch + 4 * c) * EB) = v;
+        } else {
+          const float sc = m < rows ? rmul[m] : 1.0f;
+          const float q0 = fminf(kFp8Max, fmaxf(-kFp8Max, x.x * sc));
+          const float q1 = fminf(kFp8Max, fmaxf(-kFp8Max, x.y * sc));
+          const float q2 = fminf(kFp8Max, fmaxf(-kFp8Max, x.z * sc));
+          const float q3 = fminf(kFp8Max, fmaxf(-kFp8Max, x.w * sc));
+          const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(q0, q1, 0, false);
+          const int hi = __builtin_amdgcn_cvt_pk_fp8_f32(q2, q3, lo, true);
+          *reinterpret_cast<uint32_t*>(smem + (size_t)(m * pitch + 4 * c)) = uint32_t(hi);
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // 3. MFMA over K for this wave's 16 weight rows
+  const int col = lane & 15, kg = lane >> 4;
+  int wn;                 // weight row this lane streams
+  const void* wbase;
+  if (PAIRED) {
+    const int n = bx * kWaves * 8 + wave * 8 + (col & 7);
+    wn = min(n, a.N - 1);
+    wbase = col < 8 ? a.Wq : a.W2q;
+  } else {
+    wn = min(bx * kWaves * 16 + wave * 16 + col, a.N - 1);
+    wbase = a.Wq;
+  }
+  f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+  const int ksteps = K / 32;
+  constexpr int CH = 8;  // k-steps whose weight loads are issued together
+  for (int k0 = 0; k0 < ksteps; k0 += CH) {
+    if (PREC == PSWA_PREC_BF16) {
+      const uint16_t* wr = static_cast<const uint16_t*>(wbase) + (size_t)wn * K + 8 * kg;
+      bf16x8 b[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u)
+        if (k0 + u < ksteps) b[u] = *reinterpret_cast<const bf16x8*>(wr + 32 * (k0 + u));
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        if (k0 + u < ksteps) {
+          const int k = 32 * (k0 + u) + 8 * kg;
+          const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(smem + (size_t)(col * pitch + k) * 2);
+          const bf16x8 a1 =
+              *reinterpret_cast<const bf16x8*>(smem + (size_t)((16 + col) * pitch + k) * 2);
+          c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b[u], c0, 0, 0, 0);
+          c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b[u], c1, 0, 0, 0);
+        }
+      }
+    } else {
+      const uint8_t* wr = static_cast<const uint8_t*>(wbase) + (size_t)wn * K + 8 * kg;
+      long b[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u)
+        if (k0 + u < ksteps) b[u] = *reinterpret_cast<const long*>(wr + 32 * (k0 + u));
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        if (k0 + u < ksteps) {
+          const int k = 32 * (k0 + u) + 8 * kg;
+          const long a0 = *reinterpret_cast<const long*>(smem + (size_t)(col * pitch + k));
+          const long a1 = *reinterpret_cast<const long*>(smem + (size_t)((16 + col) * pitch + k));
+          c0 = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a0, b[u], c0, 0, 0, 0);
+          c1 = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a1, b[u], c1, 0, 0, 0);
+        }
+      }
+    }
+  }
+
+  // 4. epilogue: lane holds rows 16*rb + 4*kg + i of its column
+  const float wsc = (PAIRED && col >= 8) ? a.w2scale : a.wscale;
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int mr = 16 * rb + 4 * kg + i;
+      const float acc = rb == 0 ? c0[i] : c1[i];
+      const int mrc = min(mr, rows - 1);
+      float v = acc * wsc;
+      if (PREC == PSWA_PREC_FP8) v = v / rmul[mrc];
+      if (RMS) v *= rstd[mrc];
+      const float v2 = PAIRED ? __shfl(v, (lane & ~15) | ((col + 8) & 15), 64) : 0.f;
+      if (mr >= rows) continue;
+      if (PAIRED && col >= 8) continue;
+      const int row = m0 + mr;
+      const int n = PAIRED ? bx * kWaves * 8 + wave * 8 + col : bx * kWaves * 16 + wave * 16 + col;
+      if (n >= a.N) continue;
+      epilogue<EPI>(a, row, n, v, v2);
+    }
+  }
+}
+
+template <int AK, bool RMS, int EPI>
+__device__ __forceinline__ void gemm_tile_q_any(const GemmArgs& a, int bx, int by, uint8_t* smem,
+                                                float* rstd, float* rmul) {
+  if (a.prec == PSWA_PREC_BF16)
+    gemm_tile_q<AK, RMS, EPI, PSWA_PREC_BF16>(a, bx, by, smem, rstd, rmul);
+  else
+    gemm_tile_q<AK, RMS, EPI, PSWA_PREC_FP8>(a, bx, by, smem, rstd, rmul);
+}
+
+}  // namespace dev
+}  // namespace pswa

@@ -17,8 +17,16 @@ namespace pswa {
 
 constexpr int kMaxLayers = 16;
 
+// A projection weight in the model's GEMM precision: the BF16 / FP8 copy and
+// 1 / its quantization scale (FP8; 1 for BF16). q is null for FP32 models.
+struct QW {
+  const void* q;
+  float inv_scale;
+};
+
 struct LayerWeights {
   const float *g1, *Wqkv, *bias, *Wo, *g2, *Wgate, *Wup, *Wdown;
+  QW qkv, o, gate, up, down;
 };
 
 struct DevWeights {
@@ -26,6 +34,8 @@ struct DevWeights {
       *acc_bias, *acc_Wo;
   LayerWeights layers[kMaxLayers];
   const float *head_g, *W1, *W2, *gmu, *bmu, *gsig, *bsig;
+  int prec;  // PSWA_PREC_*: arithmetic of every projection below
+  QW in, acc_q, acc_kv, acc_o, head1, head2;
 };
 
 struct NetDims {
@@ -73,6 +83,19 @@ __host__ __device__ inline GemmArgs gemm_base(int M, int N, int K, int role) {
   return g;
 }
 
+__host__ __device__ inline void use_q(GemmArgs& g, int prec, QW w, QW w2 = QW{nullptr, 1.f},
+                                     size_t off = 0, size_t off2 = 0) {
+  if (prec == 0 || !w.q) return;
+  const int eb = prec == 1 ? 2 : 1;
+  g.prec = prec;
+  g.Wq = static_cast<const char*>(w.q) + off * eb;
+  g.wscale = w.inv_scale;
+  if (w2.q) {
+    g.W2q = static_cast<const char*>(w2.q) + off2 * eb;
+    g.w2scale = w2.inv_scale;
+  }
+}
+
 __host__ __device__ inline AttnArgs attn_base(const NetDims& x, const PassCtx& c, int role) {
   AttnArgs a{};
   a.role = role;
@@ -99,6 +122,7 @@ __host__ __device__ inline GemmArgs args_acc_q(const NetDims& x, const DevWeight
   GemmArgs g = gemm_base(c.M, x.d, x.d, R_ACC_Q);
   g.X = c.h; g.ldx = x.d; g.xrow = c.gpos; g.gain = w.acc_gq; g.W = w.acc_Wq;
   g.Y = c.q; g.ldy = x.d;
+  use_q(g, w.prec, w.acc_q);
   return g;
 }
 __host__ __device__ inline AttnArgs args_acc_attn(const NetDims& x, const DevWeights& w,
@@ -113,6 +137,7 @@ __host__ __device__ inline GemmArgs args_acc_o(const NetDims& x, const DevWeight
   GemmArgs g = gemm_base(c.M, x.d, x.d, R_ACC_O);
   g.X = c.att; g.ldx = x.d; g.W = w.acc_Wo;
   g.R = c.h; g.ldr = x.d; g.rrow = c.gpos; g.Y = c.x; g.ldy = x.d;
+  use_q(g, w.prec, w.acc_o);
   return g;
 }
 
@@ -124,6 +149,7 @@ __host__ __device__ inline GemmArgs args_qkv(const NetDims& x, const DevWeights&
   g.X = c.x; g.ldx = x.d; g.gain = L.g1; g.W = L.Wqkv;
   g.Y = c.q; g.ldy = x.d; g.Y2 = c.kv + l * c.kv_stride; g.ldy2 = 2 * x.d; g.y2row = c.gpos;
   g.nsplit = x.d;
+  use_q(g, w.prec, L.qkv);
   return g;
 }
 __host__ __device__ inline AttnArgs args_attn(const NetDims& x, const DevWeights& w,
@@ -140,6 +166,7 @@ __host__ __device__ inline GemmArgs args_o(const NetDims& x, const DevWeights& w
   GemmArgs g = gemm_base(c.M, x.d, x.d, R_O);
   g.X = c.att; g.ldx = x.d; g.W = w.layers[l].Wo;
   g.R = c.x; g.ldr = x.d; g.Y = c.x; g.ldy = x.d;
+  use_q(g, w.prec, w.layers[l].o);
   return g;
 }
 __host__ __device__ inline GemmArgs args_gateup(const NetDims& x, const DevWeights& w,
@@ -147,6 +174,7 @@ __host__ __device__ inline GemmArgs args_gateup(const NetDims& x, const DevWeigh
   GemmArgs g = gemm_base(c.M, x.F, x.d, R_GATEUP);
   g.X = c.x; g.ldx = x.d; g.gain = w.layers[l].g2; g.W = w.layers[l].Wgate;
   g.W2 = w.layers[l].Wup; g.Y = c.hmid; g.ldy = x.F;
+  use_q(g, w.prec, w.layers[l].gate, w.layers[l].up);
   return g;
 }
 __host__ __device__ inline GemmArgs args_down(const NetDims& x, const DevWeights& w,
@@ -154,6 +182,7 @@ __host__ __device__ inline GemmArgs args_down(const NetDims& x, const DevWeights
   GemmArgs g = gemm_base(c.M, x.d, x.F, R_DOWN);
   g.X = c.hmid; g.ldx = x.F; g.W = w.layers[l].Wdown;
   g.R = c.x; g.ldr = x.d; g.Y = c.x; g.ldy = x.d;
+  use_q(g, w.prec, w.layers[l].down);
   return g;
 }
 
@@ -162,6 +191,7 @@ __host__ __device__ inline GemmArgs args_head1(const NetDims& x, const DevWeight
                                                const PassCtx& c) {
   GemmArgs g = gemm_base(c.M, x.d, x.d, R_HEAD1);
   g.X = c.x; g.ldx = x.d; g.gain = w.head_g; g.W = w.W1; g.Y = c.t1; g.ldy = x.d;
+  use_q(g, w.prec, w.head1);
   return g;
 }
 __host__ __device__ inline GemmArgs args_head2(const NetDims& x, const DevWeights& w,
@@ -173,6 +203,7 @@ __host__ __device__ inline GemmArgs args_head2(const NetDims& x, const DevWeight
   g.head.mean = c.mean; g.head.scale = c.scale; g.head.center = c.center;
   g.head.index = c.index; g.head.center_c = c.center_c; g.head.index_c = c.index_c;
   g.head.flag = c.flag;
+  use_q(g, w.prec, w.head2, w.head2, 0, (size_t)x.C * x.d);
   return g;
 }
 
@@ -182,6 +213,7 @@ __host__ __device__ inline GemmArgs args_embed(const NetDims& x, const DevWeight
   GemmArgs g = gemm_base(c.M, x.d, x.C, R_EMBED);
   g.Xi = c.ydec; g.ldx = x.C; g.xrow = c.gpos; g.xscale = w.ing; g.W = w.inW;
   g.Y = c.e; g.ldy = x.d;
+  use_q(g, w.prec, w.in);
   return g;
 }
 __host__ __device__ inline GemmArgs args_acc_kv(const NetDims& x, const DevWeights& w,
@@ -189,6 +221,7 @@ __host__ __device__ inline GemmArgs args_acc_kv(const NetDims& x, const DevWeigh
   GemmArgs g = gemm_base(c.M, 2 * x.d, x.d, R_ACCKV);
   g.X = c.e; g.ldx = x.d; g.gain = w.acc_gkv; g.W = w.acc_Wkv;
   g.Y = c.acc_kv; g.ldy = 2 * x.d; g.yrow = c.gpos;
+  use_q(g, w.prec, w.acc_kv);
   return g;
 }
 

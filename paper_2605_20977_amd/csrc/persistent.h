@@ -18,9 +18,9 @@ struct PersistArgs {
   long spin_limit;
 };
 
-size_t persistent_lds_bytes(const NetDims& x);
+size_t persistent_lds_bytes(const NetDims& x, int prec);
 // Largest grid whose blocks can all be resident at once (0 on error).
-int persistent_max_grid(const NetDims& x);
+int persistent_max_grid(const NetDims& x, int prec);
 void launch_persistent(const PersistArgs& P, int grid, hipStream_t s);
 void zero_ints(int* p, int n, hipStream_t s);
 

@@ -37,7 +37,8 @@ Prof& prof() {
 const char* kRoleNames[R_COUNT] = {
     "acc_q_gemm", "acc_attention", "acc_o_gemm", "qkv_gemm", "layer_attention", "o_gemm",
     "gateup_swiglu_gemm", "down_gemm", "head1_gemm", "head2_gemm", "embed_gemm", "acc_kv_gemm",
-    "symbol_bits", "gather_symbols", "hyper_embed", "temporal_kv_gemm", "sum", "other"};
+    "symbol_bits", "gather_symbols", "hyper_embed", "temporal_kv_gemm", "sum", "other",
+    "persistent_decode"};
 
 }  // namespace
 

@@ -73,8 +73,8 @@ Acts take_acts(Layout& L, const NetDims& x, size_t rows) {
 }
 
 void run_embed(const pswa_model* m, const PassCtx& c, hipStream_t st) {
-  gemm_f32(A_INT, false, EPI_STORE, args_embed(m->x, m->w, c), st);
-  gemm_f32(A_FLOAT, true, EPI_STORE, args_acc_kv(m->x, m->w, c), st);
+  gemm_run(A_INT, false, EPI_STORE, args_embed(m->x, m->w, c), st);
+  gemm_run(A_FLOAT, true, EPI_STORE, args_acc_kv(m->x, m->w, c), st);
 }
 
 void embed_prev(const pswa_model* m, int HW, int HWt, int off, const int32_t* prev, float* e_prev,
@@ -84,7 +84,8 @@ void embed_prev(const pswa_model* m, int HW, int HWt, int off, const int32_t* pr
     GemmArgs a = gemm_base(HW, x.d, x.C, R_TKV);
     a.Xi = prev + (size_t)tau * HW * x.C; a.ldx = x.C; a.xscale = m->w.ing; a.W = m->w.inW;
     a.Y = e_prev + ((size_t)tau * HWt + off) * x.d; a.ldy = x.d;
-    gemm_f32(A_INT, false, EPI_STORE, a, st);
+    use_q(a, m->w.prec, m->w.in);
+    gemm_run(A_INT, false, EPI_STORE, a, st);
   }
 }
 
@@ -96,7 +97,8 @@ void temporal_kv_layer(const pswa_model* m, int HW, int HWt, int off, const floa
     a.X = e_prev + ((size_t)tau * HWt + off) * x.d; a.ldx = x.d; a.gain = m->w.layers[l].g1;
     a.W = m->w.layers[l].Wqkv + (size_t)x.d * x.d;
     a.Y = tkv_l + ((size_t)tau * HWt + off) * 2 * x.d; a.ldy = 2 * x.d;
-    gemm_f32(A_FLOAT, true, EPI_STORE, a, st);
+    use_q(a, m->w.prec, m->w.layers[l].qkv, QW{nullptr, 1.f}, (size_t)x.d * x.d);
+    gemm_run(A_FLOAT, true, EPI_STORE, a, st);
   }
 }
 
@@ -202,6 +204,55 @@ size_t blob_layout(const NetDims& x, const float* base, DevWeights* w, size_t al
   W.gsig = t(C);
   W.bsig = t(C);
   return off;
+}
+
+// Projection weights that run in the model's GEMM precision, as (tensor index
+// in the blob order, field of DevWeights that receives the copy).
+std::vector<std::pair<int, QW*>> quant_targets(DevWeights& w, int L) {
+  std::vector<std::pair<int, QW*>> t = {{3, &w.in}, {5, &w.acc_q}, {7, &w.acc_kv}, {11, &w.acc_o}};
+  for (int l = 0; l < L; ++l) {
+    LayerWeights& Ly = w.layers[l];
+    t.push_back({13 + 8 * l, &Ly.qkv});
+    t.push_back({15 + 8 * l, &Ly.o});
+    t.push_back({17 + 8 * l, &Ly.gate});
+    t.push_back({18 + 8 * l, &Ly.up});
+    t.push_back({19 + 8 * l, &Ly.down});
+  }
+  t.push_back({13 + 8 * L, &w.head1});
+  t.push_back({14 + 8 * L, &w.head2});
+  return t;
+}
+
+uint16_t bf16_rne_host(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+
+// OCP FP8 e4m3fn (bias 7, 3 mantissa bits, max 448, no infinities), round
+// to nearest even, saturating.
+uint8_t fp8_e4m3_rne_host(float f) {
+  const uint8_t sign = std::signbit(f) ? 0x80 : 0x00;
+  const double a = std::fabs(double(f));
+  if (!(a == a)) return 0x7f;
+  if (a >= 448.0) return sign | 0x7e;
+  if (a == 0.0) return sign;
+  int e;
+  std::frexp(a, &e);        // a = fr * 2^e, fr in [0.5, 1)
+  int ex = e - 1;           // a = 1.m * 2^ex
+  if (ex < -6) {            // subnormal: multiples of 2^-9
+    const double q = std::nearbyint(a * 512.0);  // ties to even
+    if (q >= 8.0) return sign | 0x08;            // rounds up to the smallest normal
+    return sign | uint8_t(q);
+  }
+  double q = std::nearbyint((a / std::ldexp(1.0, ex) - 1.0) * 8.0);
+  if (q >= 8.0) {
+    q = 0.0;
+    ++ex;
+  }
+  if (ex > 8 || (ex == 8 && q > 6.0)) return sign | 0x7e;
+  return sign | uint8_t(((ex + 7) << 3) | int(q));
 }
 
 // ------------------------------------------------------------ encode ws
@@ -315,10 +366,26 @@ size_t pswa_model_blob_floats(const pswa_model_desc* desc) {
   return blob_layout(dims_of(*desc), nullptr, nullptr);
 }
 
+// Device layout: the FP32 weights (each tensor 256-byte aligned), then for
+// BF16 / FP8 models a low-precision copy of every projection weight.
+size_t device_layout(const pswa_model_desc& desc, std::vector<std::pair<int, size_t>>* qoff) {
+  const NetDims x = dims_of(desc);
+  std::vector<std::pair<size_t, size_t>> spans;
+  size_t bytes = align_up(blob_layout(x, nullptr, nullptr, kTensorAlign, &spans) * sizeof(float));
+  if (desc.prec == PSWA_FP32) return bytes;
+  const size_t eb = desc.prec == PSWA_BF16 ? 2 : 1;
+  DevWeights tmp{};
+  for (auto& t : quant_targets(tmp, x.L)) {
+    if (qoff) qoff->push_back({t.first, bytes});
+    bytes += align_up(spans[t.first].second * eb);
+  }
+  return bytes;
+}
+
 size_t pswa_model_device_bytes(const pswa_model_desc* desc) {
   std::string why;
   if (!valid_desc(desc, &why)) return 0;
-  return align_up(blob_layout(dims_of(*desc), nullptr, nullptr, kTensorAlign) * sizeof(float));
+  return device_layout(*desc, nullptr);
 }
 
 pswa_status pswa_model_create(const pswa_model_desc* desc, const float* h_blob,
@@ -337,8 +404,8 @@ pswa_status pswa_model_create(const pswa_model_desc* desc, const float* h_blob,
     return fail(PSWA_E_SHAPE, "blob has %zu floats, model needs %zu", blob_floats, need);
   if (d_bytes < pswa_model_device_bytes(desc))
     return fail(PSWA_E_ARG, "device region %zu bytes < %zu", d_bytes, pswa_model_device_bytes(desc));
-  if (desc->prec != PSWA_FP32)
-    return fail(PSWA_E_UNSUPPORTED, "precision %d is not built in this library", desc->prec);
+  if (desc->prec != PSWA_FP32 && (x.C % 32 != 0 || x.d % 32 != 0))
+    return fail(PSWA_E_UNSUPPORTED, "BF16/FP8 models need C and d multiples of 32");
   hipStream_t st = static_cast<hipStream_t>(stream);
   // Re-lay the blob with every tensor 256-byte aligned, then one upload.
   std::vector<std::pair<size_t, size_t>> src, dst;
@@ -349,17 +416,69 @@ pswa_status pswa_model_create(const pswa_model_desc* desc, const float* h_blob,
     std::memcpy(padded.data() + dst[i].first, h_blob + src[i].first, src[i].second * sizeof(float));
   PSWA_HIP_TRY(hipMemcpyAsync(d_mem, padded.data(), dev_floats * sizeof(float),
                               hipMemcpyHostToDevice, st));
-  PSWA_HIP_TRY(hipStreamSynchronize(st));
-  auto* m = new pswa_model;
+  std::unique_ptr<pswa_model> m(new pswa_model);
   m->desc = *desc;
   m->x = x;
   m->w = DevWeights{};
   blob_layout(x, static_cast<const float*>(d_mem), &m->w, kTensorAlign);
-  *out = m;
+  m->w.prec = desc->prec == PSWA_BF16 ? PSWA_PREC_BF16
+              : desc->prec == PSWA_FP8_E4M3 ? PSWA_PREC_FP8 : PSWA_PREC_F32;
+  std::vector<std::vector<uint8_t>> staging;
+  if (desc->prec != PSWA_FP32) {
+    std::vector<std::pair<int, size_t>> qoff;
+    device_layout(*desc, &qoff);
+    auto targets = quant_targets(m->w, x.L);
+    for (size_t i = 0; i < targets.size(); ++i) {
+      const float* w = h_blob + src[targets[i].first].first;
+      const size_t n = src[targets[i].first].second;
+      std::vector<uint8_t> q;
+      float inv = 1.f;
+      if (desc->prec == PSWA_BF16) {
+        q.resize(2 * n);
+        for (size_t k = 0; k < n; ++k) {
+          const uint16_t h = bf16_rne_host(w[k]);
+          std::memcpy(&q[2 * k], &h, 2);
+        }
+      } else {
+        double amax = 0;
+        for (size_t k = 0; k < n; ++k) amax = std::max(amax, std::fabs(double(w[k])));
+        const double sc = amax > 0 ? 448.0 / amax : 1.0;  // static per-tensor scale
+        q.resize(n);
+        for (size_t k = 0; k < n; ++k) q[k] = fp8_e4m3_rne_host(float(double(w[k]) * sc));
+        inv = float(1.0 / sc);
+      }
+      char* dst = static_cast<char*>(d_mem) + qoff[i].second;
+      PSWA_HIP_TRY(hipMemcpyAsync(dst, q.data(), q.size(), hipMemcpyHostToDevice, st));
+      *targets[i].second = QW{dst, inv};
+      staging.push_back(std::move(q));
+    }
+  }
+  PSWA_HIP_TRY(hipStreamSynchronize(st));
+  *out = m.release();
   return PSWA_OK;
 }
 
 void pswa_model_destroy(pswa_model* model) { delete model; }
+
+pswa_status pswa_quantize(int prec, const float* h_in, size_t n, void* h_out, float* h_inv_scale) {
+  if ((n && (!h_in || !h_out)) || !h_inv_scale) return fail(PSWA_E_ARG, "null pointer argument");
+  if (prec == PSWA_BF16) {
+    uint16_t* o = static_cast<uint16_t*>(h_out);
+    for (size_t k = 0; k < n; ++k) o[k] = bf16_rne_host(h_in[k]);
+    *h_inv_scale = 1.f;
+    return PSWA_OK;
+  }
+  if (prec == PSWA_FP8_E4M3) {
+    double amax = 0;
+    for (size_t k = 0; k < n; ++k) amax = std::max(amax, std::fabs(double(h_in[k])));
+    const double sc = amax > 0 ? 448.0 / amax : 1.0;
+    uint8_t* o = static_cast<uint8_t*>(h_out);
+    for (size_t k = 0; k < n; ++k) o[k] = fp8_e4m3_rne_host(float(double(h_in[k]) * sc));
+    *h_inv_scale = float(1.0 / sc);
+    return PSWA_OK;
+  }
+  return fail(PSWA_E_ARG, "precision %d has no quantized form", prec);
+}
 
 size_t pswa_encode_workspace_bytes(const pswa_model* model, const pswa_frame_desc* frame) {
   std::string why;

@@ -15,7 +15,7 @@ namespace pswa {
 // Role of a launch, for the live kernel timer (profile.cpp).
 enum Role {
   R_ACC_Q, R_ACC_ATTN, R_ACC_O, R_QKV, R_ATTN, R_O, R_GATEUP, R_DOWN, R_HEAD1, R_HEAD2,
-  R_EMBED, R_ACCKV, R_BITS, R_GATHER, R_HYPER, R_TKV, R_SUM, R_OTHER, R_COUNT
+  R_EMBED, R_ACCKV, R_BITS, R_GATHER, R_HYPER, R_TKV, R_SUM, R_OTHER, R_PERSIST, R_COUNT
 };
 const char* role_name(int r);
 bool prof_on();
@@ -27,6 +27,8 @@ void prof_end(int ev, hipStream_t s, int role, double bytes, double flops);
 // order by one thread per output, so a row's value never depends on how many
 // rows are in the launch or how they are tiled.
 enum AKind { A_FLOAT = 0, A_INT = 1 };
+// Arithmetic of a GEMM: FP32 SIMT, or BF16 / FP8 (OCP e4m3fn) MFMA.
+constexpr int PSWA_PREC_F32 = 0, PSWA_PREC_BF16 = 1, PSWA_PREC_FP8 = 2;
 enum Epi {
   EPI_STORE = 0,   // Y[yrow(m)][n] = acc
   EPI_RESID = 1,   // Y[yrow(m)][n] = R[rrow(m)][n] + acc
@@ -58,6 +60,10 @@ struct GemmArgs {
   const float* gain = nullptr;           // RMSNorm prologue gain (null: none)
   const float* W = nullptr;              // [N][K]
   const float* W2 = nullptr;             // paired epilogues: second [N][K]
+  int prec = 0;                          // PSWA_PREC_*; low precision reads Wq / W2q
+  const void* Wq = nullptr;              // [N][K] BF16 or FP8 copy of W
+  const void* W2q = nullptr;
+  float wscale = 1.f, w2scale = 1.f;     // 1 / (weight quantization scale)
   float* Y = nullptr;
   int ldy = 0;
   const int* yrow = nullptr;
@@ -71,7 +77,7 @@ struct GemmArgs {
   HeadOut head{};
 };
 
-void gemm_f32(AKind ak, bool rms, Epi epi, const GemmArgs& a, hipStream_t s);
+void gemm_run(AKind ak, bool rms, Epi epi, const GemmArgs& a, hipStream_t s);
 double gemm_alg_bytes(const GemmArgs& a, Epi epi);
 
 // Kernels whose dynamic LDS can exceed 64 KiB opt in to 156 KiB (the

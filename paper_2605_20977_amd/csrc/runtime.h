@@ -60,19 +60,19 @@ template <class BeforeLayer>
 void run_pass(const pswa_model* m, const PassCtx& c, BeforeLayer before_layer, hipStream_t st) {
   const NetDims& x = m->x;
   const DevWeights& w = m->w;
-  gemm_f32(A_FLOAT, true, EPI_STORE, args_acc_q(x, w, c), st);
+  gemm_run(A_FLOAT, true, EPI_STORE, args_acc_q(x, w, c), st);
   attention_f32(args_acc_attn(x, w, c), st);
-  gemm_f32(A_FLOAT, false, EPI_RESID, args_acc_o(x, w, c), st);
+  gemm_run(A_FLOAT, false, EPI_RESID, args_acc_o(x, w, c), st);
   for (int l = 0; l < x.L; ++l) {
     before_layer(l);
-    gemm_f32(A_FLOAT, true, EPI_QKV, args_qkv(x, w, c, l), st);
+    gemm_run(A_FLOAT, true, EPI_QKV, args_qkv(x, w, c, l), st);
     attention_f32(args_attn(x, w, c, l), st);
-    gemm_f32(A_FLOAT, false, EPI_RESID, args_o(x, w, c, l), st);
-    gemm_f32(A_FLOAT, true, EPI_SWIGLU, args_gateup(x, w, c, l), st);
-    gemm_f32(A_FLOAT, false, EPI_RESID, args_down(x, w, c, l), st);
+    gemm_run(A_FLOAT, false, EPI_RESID, args_o(x, w, c, l), st);
+    gemm_run(A_FLOAT, true, EPI_SWIGLU, args_gateup(x, w, c, l), st);
+    gemm_run(A_FLOAT, false, EPI_RESID, args_down(x, w, c, l), st);
   }
-  gemm_f32(A_FLOAT, true, EPI_SILU, args_head1(x, w, c), st);
-  gemm_f32(A_FLOAT, false, EPI_HEAD, args_head2(x, w, c), st);
+  gemm_run(A_FLOAT, true, EPI_SILU, args_head1(x, w, c), st);
+  gemm_run(A_FLOAT, false, EPI_HEAD, args_head2(x, w, c), st);
 }
 
 // Embedding of decoded symbols (read from c.ydec at the rows' positions) and

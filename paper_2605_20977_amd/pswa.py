@@ -86,6 +86,7 @@ def _load():
         "pswa_batch_set_grid": (i32, [vp, i32]),
         "pswa_batch_set_spin_limit": (i32, [vp, C.c_int64]),
         "pswa_batch_destroy": (None, [vp]),
+        "pswa_quantize": (i32, [i32, vp, sz, vp, P(C.c_float)]),
         "pswa_profile_enable": (i32, [i32]),
         "pswa_profile_roles": (i32, []),
         "pswa_profile_read": (i32, [i32, C.c_char_p, sz, P(C.c_double), P(C.c_int64),
@@ -108,7 +109,8 @@ EXPORTED = ("pswa_model_blob_floats", "pswa_model_device_bytes", "pswa_model_cre
             "pswa_batch_workspace_bytes", "pswa_batch_create", "pswa_batch_run",
             "pswa_batch_check", "pswa_batch_outputs", "pswa_batch_num_steps",
             "pswa_batch_max_rows", "pswa_batch_grid", "pswa_batch_max_grid",
-            "pswa_batch_set_grid", "pswa_batch_set_spin_limit", "pswa_batch_destroy")
+            "pswa_batch_set_grid", "pswa_batch_set_spin_limit", "pswa_batch_destroy",
+            "pswa_quantize")
 
 
 def lib():
@@ -485,6 +487,18 @@ def pswa_range_decode_seq(data: bytes, center, index):
                                       ce.size, ce.ctypes.data, ix.ctypes.data,
                                       out.ctypes.data))
     return out
+
+
+# ------------------------------------------------------------ quantization
+
+def pswa_quantize(prec, x):
+    """(codes, inv_scale): uint16 BF16 bits or uint8 FP8 e4m3fn codes."""
+    a = np.ascontiguousarray(x, dtype=np.float32).ravel()
+    p = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+    out = np.empty(a.size, np.uint16 if p == PSWA_BF16 else np.uint8)
+    inv = C.c_float(0)
+    _check(_lib.pswa_quantize(p, a.ctypes.data, a.size, out.ctypes.data, C.byref(inv)))
+    return out, inv.value
 
 
 # --------------------------------------------------------------- profiling
