@@ -225,6 +225,11 @@ pswa_status pswa_batch_set_grid(pswa_batch* batch, int grid);
 /* Bound on the spin count of one grid-barrier wait before the launch aborts
  * (default about a second of waiting). Lowering it forces the abort path. */
 pswa_status pswa_batch_set_spin_limit(pswa_batch* batch, int64_t spins);
+/* Phase timeline (a profiling aid): while d_trace is set, one thread of the
+ * persistent kernel writes the device wall clock (100 MHz) after each of the
+ * first n grid barriers of a run to d_trace[0..n) (device int64). Barriers
+ * per global step: 3 + 5 L + 5. n = 0 turns the trace off. */
+pswa_status pswa_batch_trace(pswa_batch* batch, int64_t* d_trace, int n);
 void pswa_batch_destroy(pswa_batch* batch);
 
 /* ---------------------------------------------------------- entropy side */

@@ -37,6 +37,8 @@ struct pswa_batch {
   int HWt = 0, T = 0, Mmax = 0, grid = 0, max_grid = 0;
   long spin_limit = 1L << 21;  // barrier wait bound (about a second)
   double alg_bytes = 0, alg_flops = 0;  // one persistent launch, for the timer
+  long long* trace = nullptr;
+  int trace_len = 0;
   bool any_p = false;
   // device (inside the caller's workspace)
   FrameInfo* d_frames = nullptr;
@@ -48,6 +50,9 @@ struct pswa_batch {
   uint16_t* index = nullptr;
   Acts a{};
   int* ctl = nullptr;  // [0] barrier arrivals, [1] abort, [2] numeric flag
+  GemmArgs* gtab = nullptr;  // per-step argument tables (see persistent.h)
+  AttnArgs* atab = nullptr;
+  SymArgs* stab = nullptr;
   float* sum = nullptr;
   size_t bytes = 0;
 };
@@ -116,6 +121,9 @@ void lay_out(const NetDims& x, const Plan& p, int n, void* base, pswa_batch* b) 
   b->a = take_acts(L, x, std::max(p.Mmax, 1));
   b->ctl = L.take<int>(64);
   b->sum = L.take<float>(64);
+  b->gtab = L.take<GemmArgs>((size_t)p.T * gemm_phases(x.L));
+  b->atab = L.take<AttnArgs>((size_t)p.T * attn_phases(x.L));
+  b->stab = L.take<SymArgs>(p.T);
   b->bytes = L.used;
 }
 
@@ -136,12 +144,10 @@ pswa_status check_frames(const pswa_model* m, int n, const pswa_batch_frame* fr)
   return PSWA_OK;
 }
 
-PersistArgs persist_args(const pswa_batch* b) {
+// Buffers of the batch as a pass context (M, gpos and fid set per step).
+PassCtx batch_ctx(const pswa_batch* b) {
   const NetDims& x = b->model->x;
-  PersistArgs P{};
-  P.x = x;
-  P.w = b->model->w;
-  PassCtx& c = P.c;
+  PassCtx c{};
   c.frames = b->d_frames;
   c.frame0 = b->finfo[0];
   c.HWt = b->HWt;
@@ -149,7 +155,7 @@ PersistArgs persist_args(const pswa_batch* b) {
   c.acc_kv = b->acc_kv;
   c.kv = b->kv;
   c.kv_stride = (size_t)b->HWt * 2 * x.d;
-  c.tkv = b->tkv;
+  c.tkv = b->any_p ? b->tkv : nullptr;
   c.tkv_stride = (size_t)2 * b->HWt * 2 * x.d;
   c.x = b->a.x; c.q = b->a.q; c.att = b->a.att; c.e = b->a.e; c.t1 = b->a.t1; c.hmid = b->a.hmid;
   c.mean = b->mean; c.scale = b->scale; c.bits = b->bits;
@@ -159,13 +165,54 @@ PersistArgs persist_args(const pswa_batch* b) {
   c.ysrc = b->ysrc;
   c.src_compact = 0;
   c.ydec = b->ydec;
-  P.row_start = b->row_start;
-  P.gpos_all = b->gpos_all;
-  P.fid_all = b->fid_all;
+  return c;
+}
+
+// Argument tables of every step and phase, in the kernel's order.
+void build_tables(const pswa_batch* b, const std::vector<int>& row_start,
+                  std::vector<GemmArgs>* gt, std::vector<AttnArgs>* at, std::vector<SymArgs>* stb) {
+  const NetDims& x = b->model->x;
+  const DevWeights& w = b->model->w;
+  const PassCtx base = batch_ctx(b);
+  gt->clear();
+  at->clear();
+  stb->clear();
+  for (int t = 0; t < b->T; ++t) {
+    PassCtx c = base;
+    c.M = row_start[t + 1] - row_start[t];
+    c.gpos = b->gpos_all + row_start[t];
+    c.fid = b->fid_all + row_start[t];
+    gt->push_back(args_acc_q(x, w, c));
+    gt->push_back(args_acc_o(x, w, c));
+    at->push_back(args_acc_attn(x, w, c));
+    for (int l = 0; l < x.L; ++l) {
+      gt->push_back(args_qkv(x, w, c, l));
+      gt->push_back(args_o(x, w, c, l));
+      gt->push_back(args_gateup(x, w, c, l));
+      gt->push_back(args_down(x, w, c, l));
+      at->push_back(args_attn(x, w, c, l));
+    }
+    gt->push_back(args_head1(x, w, c));
+    gt->push_back(args_head2(x, w, c));
+    gt->push_back(args_embed(x, w, c));
+    gt->push_back(args_acc_kv(x, w, c));
+    stb->push_back(SymArgs{c.M, x.C, c.gpos, c.ysrc, c.src_compact, c.ydec, c.mean, c.scale,
+                           c.bits});
+  }
+}
+
+PersistArgs persist_args(const pswa_batch* b) {
+  PersistArgs P{};
+  P.gtab = b->gtab;
+  P.atab = b->atab;
+  P.stab = b->stab;
   P.T = b->T;
+  P.L = b->model->x.L;
   P.bar = reinterpret_cast<unsigned*>(b->ctl);
   P.abort_flag = b->ctl + 1;
   P.spin_limit = b->spin_limit;
+  P.trace = b->trace;
+  P.trace_len = b->trace_len;
   return P;
 }
 
@@ -189,7 +236,7 @@ pswa_status run(pswa_batch* b, hipStream_t st) {
     }
   }
   const int ev = prof_begin(st);
-  launch_persistent(persist_args(b), b->grid, st);
+  launch_persistent(persist_args(b), m->x, m->w.prec, b->grid, st);
   prof_end(ev, st, R_PERSIST, b->alg_bytes, b->alg_flops);
   PSWA_HIP_TRY(hipGetLastError());
   return PSWA_OK;
@@ -198,42 +245,37 @@ pswa_status run(pswa_batch* b, hipStream_t st) {
 // Algorithmic bytes and flops of one persistent launch: the per-phase
 // figures of the per-launch path (weights once per phase, activations in and
 // out, every window slot's K and V rows) summed over every step.
-void count_work(pswa_batch* b, const std::vector<int>& row_start) {
+void count_work(pswa_batch* b, const std::vector<GemmArgs>& gt,
+                const std::vector<AttnArgs>& at, const std::vector<SymArgs>& stb) {
   const NetDims& x = b->model->x;
-  const DevWeights& w = b->model->w;
+  const int ng = gemm_phases(x.L), na = attn_phases(x.L);
+  static const Epi epis_head[4] = {EPI_SILU, EPI_HEAD, EPI_STORE, EPI_STORE};
   double by = 0, fl = 0;
-  auto g = [&](const GemmArgs& a, Epi e) {
-    by += gemm_alg_bytes(a, e);
-    fl += 2.0 * a.M * a.N * a.K * ((e == EPI_SWIGLU || e == EPI_HEAD) ? 2.0 : 1.0);
-  };
-  auto at = [&](const AttnArgs& a) {
-    by += attn_alg_bytes(a);
-    const int k1 = 2 * a.r + 1;
-    const double keys = 2.0 * a.r * (a.r + 1) + (a.include_self ? 1 : 0) +
-                        (a.knull ? 1 : 0) + (a.tkv ? 2.0 * k1 * k1 : 0.0);
-    fl += double(a.M) * a.heads * keys * 4.0 * a.dh;
-  };
-  PersistArgs P = persist_args(b);
   for (int t = 0; t < b->T; ++t) {
-    PassCtx c = P.c;
-    c.M = row_start[t + 1] - row_start[t];
-    if (c.M == 0) continue;
-    if (!b->any_p) c.tkv = nullptr;
-    g(args_acc_q(x, w, c), EPI_STORE);
-    at(args_acc_attn(x, w, c));
-    g(args_acc_o(x, w, c), EPI_RESID);
-    for (int l = 0; l < x.L; ++l) {
-      g(args_qkv(x, w, c, l), EPI_QKV);
-      at(args_attn(x, w, c, l));
-      g(args_o(x, w, c, l), EPI_RESID);
-      g(args_gateup(x, w, c, l), EPI_SWIGLU);
-      g(args_down(x, w, c, l), EPI_RESID);
+    if (stb[t].M == 0) continue;
+    for (int k = 0; k < ng; ++k) {
+      const GemmArgs& a = gt[(size_t)t * ng + k];
+      Epi e;
+      if (k == 0) e = EPI_STORE;
+      else if (k == 1) e = EPI_RESID;
+      else if (k < 2 + 4 * x.L) {
+        const int r = (k - 2) % 4;
+        e = r == 0 ? EPI_QKV : r == 2 ? EPI_SWIGLU : EPI_RESID;
+      } else {
+        e = epis_head[k - 2 - 4 * x.L];
+      }
+      by += gemm_alg_bytes(a, e);
+      fl += 2.0 * a.M * a.N * a.K * ((e == EPI_SWIGLU || e == EPI_HEAD) ? 2.0 : 1.0);
     }
-    g(args_head1(x, w, c), EPI_SILU);
-    g(args_head2(x, w, c), EPI_HEAD);
-    by += 16.0 * c.M * x.C + 4.0 * c.M;  // symbols and bits
-    g(args_embed(x, w, c), EPI_STORE);
-    g(args_acc_kv(x, w, c), EPI_STORE);
+    for (int k = 0; k < na; ++k) {
+      const AttnArgs& a = at[(size_t)t * na + k];
+      by += attn_alg_bytes(a);
+      const int k1 = 2 * a.r + 1;
+      const double keys = 2.0 * a.r * (a.r + 1) + (a.include_self ? 1 : 0) +
+                          (a.knull ? 1 : 0) + (a.tkv ? 2.0 * k1 * k1 : 0.0);
+      fl += double(a.M) * a.heads * keys * 4.0 * a.dh;
+    }
+    by += 16.0 * stb[t].M * x.C + 4.0 * stb[t].M;  // symbols and bits
   }
   b->alg_bytes = by;
   b->alg_flops = fl;
@@ -283,8 +325,18 @@ pswa_status pswa_batch_create(const pswa_model* model, int n, const pswa_batch_f
                               hipMemcpyHostToDevice, st));
   PSWA_HIP_TRY(hipMemcpyAsync(b->fid_all, p.fid.data(), p.fid.size() * sizeof(int),
                               hipMemcpyHostToDevice, st));
+  std::vector<GemmArgs> gt;
+  std::vector<AttnArgs> at;
+  std::vector<SymArgs> stb;
+  build_tables(b.get(), p.row_start, &gt, &at, &stb);
+  PSWA_HIP_TRY(hipMemcpyAsync(b->gtab, gt.data(), gt.size() * sizeof(GemmArgs),
+                              hipMemcpyHostToDevice, st));
+  PSWA_HIP_TRY(hipMemcpyAsync(b->atab, at.data(), at.size() * sizeof(AttnArgs),
+                              hipMemcpyHostToDevice, st));
+  PSWA_HIP_TRY(hipMemcpyAsync(b->stab, stb.data(), stb.size() * sizeof(SymArgs),
+                              hipMemcpyHostToDevice, st));
   PSWA_HIP_TRY(hipStreamSynchronize(st));
-  count_work(b.get(), p.row_start);
+  count_work(b.get(), gt, at, stb);
   *out = b.release();
   return PSWA_OK;
 }
@@ -348,6 +400,14 @@ pswa_status pswa_batch_set_spin_limit(pswa_batch* b, int64_t spins) {
   if (!b) return fail(PSWA_E_ARG, "batch is null");
   if (spins < 0) return fail(PSWA_E_ARG, "spin limit must be >= 0");
   b->spin_limit = long(spins);
+  return PSWA_OK;
+}
+
+pswa_status pswa_batch_trace(pswa_batch* b, int64_t* d_trace, int n) {
+  if (!b) return fail(PSWA_E_ARG, "batch is null");
+  if (n < 0 || (n > 0 && !d_trace)) return fail(PSWA_E_ARG, "bad trace buffer");
+  b->trace = reinterpret_cast<long long*>(d_trace);
+  b->trace_len = n;
   return PSWA_OK;
 }
 

@@ -301,22 +301,22 @@ __device__ void attn_item(const AttnArgs& a, int item, bool live, float* tr_all)
   const float scale = 1.0f / sqrtf(float(DH));
   __syncthreads();  // the block's previous items are done with the LDS
 
-  float4 q[DH / 4];
-  {
-    const float* qv = a.q + (size_t)m * a.ldq + hd * DH;
-#pragma unroll
-    for (int e = 0; e < DH / 4; ++e) q[e] = *reinterpret_cast<const float4*>(qv + 4 * e);
-  }
+  // the query sits in LDS, read by every lane as a broadcast
+  float* qs = tr_all + kWaves * (DH * 65) + (threadIdx.x >> 6) * DH;
+  if (lane < DH) qs[lane] = a.q[(size_t)m * a.ldq + hd * DH + lane];
+  __syncthreads();
 
   float mx = -INFINITY, sum = 0.f;
   float o[DH];
 #pragma unroll
   for (int e = 0; e < DH; ++e) o[e] = 0.f;
 
-#pragma unroll
+  // one key per iteration: its K and V rows are the lane's only loads in
+  // flight (most lanes own a single key)
+#pragma unroll 1
   for (int u = 0; u < kMaxKeys / 64; ++u) {
     const int kk = lane + 64 * u;
-    if (kk >= n_keys) continue;
+    if (kk >= n_keys) break;
     const float* kp = nullptr;
     const float* vp = nullptr;
     float b = 0.f;
@@ -357,7 +357,8 @@ __device__ void attn_item(const AttnArgs& a, int item, bool live, float* tr_all)
     }
     float dot = 0.f;
 #pragma unroll
-    for (int e = 0; e < DH / 4; ++e) dot = dot4(q[e], kr[e], dot);
+    for (int e = 0; e < DH / 4; ++e)
+      dot = dot4(*reinterpret_cast<const float4*>(qs + 4 * e), kr[e], dot);
     const float lg = dot * scale + b;
     const float mn = fmaxf(mx, lg);
     const float c_old = expf(mx - mn);  // 0 for the first key (mx = -inf)
@@ -388,7 +389,7 @@ __device__ void attn_item(const AttnArgs& a, int item, bool live, float* tr_all)
 }
 
 __host__ __device__ inline size_t attn_lds_bytes(int dh) {
-  return (size_t)kWaves * dh * 65 * sizeof(float);
+  return (size_t)kWaves * dh * 66 * sizeof(float);  // transpose buffer + query
 }
 
 template <int DH_dummy = 0>

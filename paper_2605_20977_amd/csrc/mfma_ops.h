@@ -14,8 +14,9 @@
 //      FP8 of (value * 448 / row max) (round to nearest even), in LDS with a
 //      16-byte skew per row;
 //   3. each wave runs v_mfma_f32_16x16x32_{bf16,fp8_fp8} over k = 0, 32, ...
-//      for its 16 weight rows (streamed from HBM, all loads of a chunk in
-//      flight) against both row blocks;
+//      in order for its 16 weight rows (16 k-steps of weight loads in flight
+//      at a time) against both row blocks: an output is one MFMA chain over K,
+//      whatever the tiling;
 //   4. the epilogue rescales (1/rms, row max / 448, 1 / weight scale) and
 //      applies the same epilogues as the FP32 tile.
 // A row's result depends only on that row, K and the weights: the same in
@@ -41,11 +42,15 @@ __host__ __device__ inline int qgemm_col_tiles(int N, int epi) {
   const int per = kWaves * (paired_epi(epi) ? 8 : 16);
   return (N + per - 1) / per;
 }
+constexpr int kKchunk = 16;  // k-steps whose weight loads are issued together
 __host__ __device__ inline int qgemm_row_tiles(int M) { return (M + kMBq - 1) / kMBq; }
 // element pitch of a staged row: K plus a 16-byte skew
 __host__ __device__ inline int qgemm_pitch(int K, int prec) { return K + (prec == PSWA_PREC_BF16 ? 8 : 16); }
+// LDS of a tile: the staged A tile (kQRedBytes is a spare prefix kept for
+// alignment of the tile).
+constexpr size_t kQRedBytes = 256;
 __host__ __device__ inline size_t qgemm_lds_bytes(int K, int prec) {
-  return (size_t)kMBq * qgemm_pitch(K, prec) * (prec == PSWA_PREC_BF16 ? 2 : 1);
+  return kQRedBytes + (size_t)kMBq * qgemm_pitch(K, prec) * (prec == PSWA_PREC_BF16 ? 2 : 1);
 }
 
 __device__ __forceinline__ uint16_t bf16_rne(float f) {
@@ -54,9 +59,12 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
   return uint16_t(u >> 16);
 }
 
+// stage = false reuses the A tile (and its row statistics) that this block
+// staged for the same row tile of the same GEMM just before.
 template <int AK, bool RMS, int EPI, int PREC>
-__device__ void gemm_tile_q(const GemmArgs& a, int bx, int by, uint8_t* smem, float* rstd,
-                            float* rmul) {
+__device__ void gemm_tile_q(const GemmArgs& a, int bx, int by, uint8_t* lds, float* rstd,
+                            float* rmul, bool stage = true) {
+  uint8_t* smem = lds + kQRedBytes;
   constexpr bool PAIRED = paired_epi(EPI);
   constexpr int EB = PREC == PSWA_PREC_BF16 ? 2 : 1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -67,7 +75,9 @@ __device__ void gemm_tile_q(const GemmArgs& a, int bx, int by, uint8_t* smem, fl
   __syncthreads();  // the previous tile of this block is done with the LDS
 
   // 1. row statistics (two rows per wave at a time, every chunk in flight)
-  if (RMS || PREC == PSWA_PREC_FP8) {
+  if (!stage) {
+    // A tile and statistics kept from the previous tile
+  } else if (RMS || PREC == PSWA_PREC_FP8) {
     for (int m = wave; m < rows; m += 2 * kWaves) {
       float4 xs[2][8];
 #pragma unroll
@@ -123,14 +133,14 @@ __device__ void gemm_tile_q(const GemmArgs& a, int bx, int by, uint8_t* smem, fl
   }
   __syncthreads();
 
-  // 2. stage the scaled rows as BF16 / FP8, 8 loads per thread in flight;
+  // 2. stage the scaled rows as BF16 / FP8, 16 loads per thread in flight;
   // rows past the end of A are zeros (their results are dropped)
-  {
+  if (stage) {
     const int total = kMBq * K4;
-    for (int base = 0; base < total; base += 8 * kThreads) {
-      float4 xv[8];
+    for (int base = 0; base < total; base += 16 * kThreads) {
+      float4 xv[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < 16; ++u) {
         const int e = base + u * kThreads + tid;
         xv[u] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (e < total && e / K4 < rows) {
@@ -145,7 +155,7 @@ __device__ void gemm_tile_q(const GemmArgs& a, int bx, int by, uint8_t* smem, fl
         }
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < 16; ++u) {
         const int e = base + u * kThreads + tid;
         if (e >= total) continue;
         const int m = e / K4, c = e % K4;
@@ -178,8 +188,7 @@ __device__ void gemm_tile_q(const GemmArgs& a, int bx, int by, uint8_t* smem, fl
   int wn;                 // weight row this lane streams
   const void* wbase;
   if (PAIRED) {
-    const int n = bx * kWaves * 8 + wave * 8 + (col & 7);
-    wn = min(n, a.N - 1);
+    wn = min(bx * kWaves * 8 + wave * 8 + (col & 7), a.N - 1);
     wbase = col < 8 ? a.Wq : a.W2q;
   } else {
     wn = min(bx * kWaves * 16 + wave * 16 + col, a.N - 1);
@@ -187,16 +196,15 @@ __device__ void gemm_tile_q(const GemmArgs& a, int bx, int by, uint8_t* smem, fl
   }
   f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
   const int ksteps = K / 32;
-  constexpr int CH = 8;  // k-steps whose weight loads are issued together
-  for (int k0 = 0; k0 < ksteps; k0 += CH) {
+  for (int k0 = 0; k0 < ksteps; k0 += kKchunk) {
     if (PREC == PSWA_PREC_BF16) {
       const uint16_t* wr = static_cast<const uint16_t*>(wbase) + (size_t)wn * K + 8 * kg;
-      bf16x8 b[CH];
+      bf16x8 b[kKchunk];
 #pragma unroll
-      for (int u = 0; u < CH; ++u)
+      for (int u = 0; u < kKchunk; ++u)
         if (k0 + u < ksteps) b[u] = *reinterpret_cast<const bf16x8*>(wr + 32 * (k0 + u));
 #pragma unroll
-      for (int u = 0; u < CH; ++u) {
+      for (int u = 0; u < kKchunk; ++u) {
         if (k0 + u < ksteps) {
           const int k = 32 * (k0 + u) + 8 * kg;
           const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(smem + (size_t)(col * pitch + k) * 2);
@@ -208,12 +216,12 @@ __device__ void gemm_tile_q(const GemmArgs& a, int bx, int by, uint8_t* smem, fl
       }
     } else {
       const uint8_t* wr = static_cast<const uint8_t*>(wbase) + (size_t)wn * K + 8 * kg;
-      long b[CH];
+      long b[kKchunk];
 #pragma unroll
-      for (int u = 0; u < CH; ++u)
+      for (int u = 0; u < kKchunk; ++u)
         if (k0 + u < ksteps) b[u] = *reinterpret_cast<const long*>(wr + 32 * (k0 + u));
 #pragma unroll
-      for (int u = 0; u < CH; ++u) {
+      for (int u = 0; u < kKchunk; ++u) {
         if (k0 + u < ksteps) {
           const int k = 32 * (k0 + u) + 8 * kg;
           const long a0 = *reinterpret_cast<const long*>(smem + (size_t)(col * pitch + k));
@@ -241,7 +249,8 @@ __device__ void gemm_tile_q(const GemmArgs& a, int bx, int by, uint8_t* smem, fl
       if (mr >= rows) continue;
       if (PAIRED && col >= 8) continue;
       const int row = m0 + mr;
-      const int n = PAIRED ? bx * kWaves * 8 + wave * 8 + col : bx * kWaves * 16 + wave * 16 + col;
+      const int n =
+          PAIRED ? bx * kWaves * 8 + wave * 8 + col : bx * kWaves * 16 + wave * 16 + col;
       if (n >= a.N) continue;
       epilogue<EPI>(a, row, n, v, v2);
     }
@@ -249,12 +258,12 @@ __device__ void gemm_tile_q(const GemmArgs& a, int bx, int by, uint8_t* smem, fl
 }
 
 template <int AK, bool RMS, int EPI>
-__device__ __forceinline__ void gemm_tile_q_any(const GemmArgs& a, int bx, int by, uint8_t* smem,
-                                                float* rstd, float* rmul) {
+__device__ __forceinline__ void gemm_tile_q_any(const GemmArgs& a, int bx, int by, uint8_t* lds,
+                                                float* rstd, float* rmul, bool stage = true) {
   if (a.prec == PSWA_PREC_BF16)
-    gemm_tile_q<AK, RMS, EPI, PSWA_PREC_BF16>(a, bx, by, smem, rstd, rmul);
+    gemm_tile_q<AK, RMS, EPI, PSWA_PREC_BF16>(a, bx, by, lds, rstd, rmul, stage);
   else
-    gemm_tile_q<AK, RMS, EPI, PSWA_PREC_FP8>(a, bx, by, smem, rstd, rmul);
+    gemm_tile_q<AK, RMS, EPI, PSWA_PREC_FP8>(a, bx, by, lds, rstd, rmul, stage);
 }
 
 }  // namespace dev

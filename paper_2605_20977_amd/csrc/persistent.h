@@ -5,23 +5,46 @@
 
 namespace pswa {
 
+// Symbols phase of one global step: gather the step's symbols from the
+// source and compute their bits.
+struct SymArgs {
+  int M, C;
+  const int* gpos;
+  const int32_t* ysrc;
+  int src_compact;
+  int32_t* ydec;
+  const float *mean, *scale;
+  float* bits;
+};
+
+// Per global step t the kernel runs, in order (g = GEMM table entry, a =
+// attention table entry; every phase ends with a grid barrier):
+//   g0 acc q, a0 acc attention, g1 acc O,
+//   per layer l: g(2+4l) QKV, a(1+l) attention, g(3+4l) O, g(4+4l) gate/up,
+//                g(5+4l) down,
+//   g(2+4L) head W1, g(3+4L) head W2, symbols, g(4+4L) embed, g(5+4L) acc K/V.
+// The argument tables are built on the host for every step and phase and
+// read by the kernel from device memory (uniform loads), so no argument
+// structure is ever built in per-lane memory.
 struct PersistArgs {
-  NetDims x;
-  DevWeights w;
-  PassCtx c;               // buffers; M, gpos and fid are set per step
-  const int* row_start;    // [T+1]: rows of global step t are [row_start[t], row_start[t+1])
-  const int* gpos_all;     // global position of each row
-  const int* fid_all;      // frame of each row
-  int T;
+  const GemmArgs* gtab;    // [T][6 + 4L]
+  const AttnArgs* atab;    // [T][1 + L]
+  const SymArgs* stab;     // [T]
+  int T, L;
   unsigned* bar;           // barrier arrivals (zeroed before each launch)
   int* abort_flag;         // set when a barrier wait exceeds spin_limit
   long spin_limit;
+  long long* trace;        // optional: wall clock after each barrier (block 0)
+  int trace_len;
 };
+
+inline int gemm_phases(int L) { return 6 + 4 * L; }
+inline int attn_phases(int L) { return 1 + L; }
 
 size_t persistent_lds_bytes(const NetDims& x, int prec);
 // Largest grid whose blocks can all be resident at once (0 on error).
 int persistent_max_grid(const NetDims& x, int prec);
-void launch_persistent(const PersistArgs& P, int grid, hipStream_t s);
+void launch_persistent(const PersistArgs& P, const NetDims& x, int prec, int grid, hipStream_t s);
 void zero_ints(int* p, int n, hipStream_t s);
 
 }  // namespace pswa

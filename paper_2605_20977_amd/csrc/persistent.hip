@@ -54,14 +54,20 @@ __device__ bool grid_barrier(unsigned* bar, unsigned& target, int* abort_flag, l
   return s_ok != 0;
 }
 
-template <int AK, bool RMS, int EPI>
+template <int AK, bool RMS, int EPI, bool Q>
 __device__ void gemm_phase(const GemmArgs& a, float4* smem4, float* rstd) {
   __shared__ float rmul[kMBq];
-  if (a.prec != PSWA_PREC_F32) {
+  if (Q) {
+    // tiles in row-tile-major order: a block re-stages A only when its next
+    // tile starts a new row tile
     const int ct = qgemm_col_tiles(a.N, EPI), rt = qgemm_row_tiles(a.M);
-    for (int t = blockIdx.x; t < ct * rt; t += gridDim.x)
-      gemm_tile_q_any<AK, RMS, EPI>(a, t % ct, t / ct, reinterpret_cast<uint8_t*>(smem4), rstd,
-                                    rmul);
+    int staged = -1;
+    for (int t = blockIdx.x; t < ct * rt; t += gridDim.x) {
+      const int r = t / ct;
+      gemm_tile_q_any<AK, RMS, EPI>(a, t % ct, r, reinterpret_cast<uint8_t*>(smem4), rstd, rmul,
+                                    r != staged);
+      staged = r;
+    }
     return;
   }
   const int ct = gemm_col_tiles(a.N, EPI), rt = gemm_row_tiles(a.M);
@@ -69,66 +75,71 @@ __device__ void gemm_phase(const GemmArgs& a, float4* smem4, float* rstd) {
     gemm_tile_any<AK, RMS, EPI>(a, t % ct, t / ct, smem4, rstd);
 }
 
+template <int DH>
 __device__ void attn_phase(const AttnArgs& a, float* smem) {
   const int groups = (a.M * a.heads + kWaves - 1) / kWaves;
   for (int g = blockIdx.x; g < groups; g += gridDim.x)
-    attn_item_any(a, g * kWaves + (threadIdx.x >> 6), true, smem);
+    attn_item<DH>(a, g * kWaves + (threadIdx.x >> 6), true, smem);
 }
 
-__device__ void symbol_phase(const PassCtx& c, int C) {
-  const long n = (long)c.M * C;
+__device__ void symbol_phase(const SymArgs& c) {
+  const long n = (long)c.M * c.C;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long)gridDim.x * blockDim.x) {
-    gather_item(c.ysrc, c.src_compact, c.gpos, C, c.ydec, i);
-    bits_item(c.gpos, C, c.ydec, c.mean, c.scale, c.bits, i);
+    gather_item(c.ysrc, c.src_compact, c.gpos, c.C, c.ydec, i);
+    bits_item(c.gpos, c.C, c.ydec, c.mean, c.scale, c.bits, i);
   }
 }
 
+// Q: the model's projections run on MFMA (BF16/FP8) rather than FP32 SIMT;
+// one instance per arithmetic keeps each one's register budget separate.
+template <bool Q, int DH>
 __global__ void __launch_bounds__(kThreads) k_persistent(PersistArgs P) {
   extern __shared__ float4 smem4[];
   __shared__ float rstd[kMBq];
   float* smem = reinterpret_cast<float*>(smem4);
-  const NetDims& x = P.x;
-  const DevWeights& w = P.w;
+  const int L = P.L, ng = 6 + 4 * L, na = 1 + L;
   unsigned target = 0;
-#define PSWA_SYNC                                                        \
-  if (!grid_barrier(P.bar, target, P.abort_flag, P.spin_limit)) return;
+  int nsync = 0;
+#define PSWA_SYNC                                                                  \
+  if (!grid_barrier(P.bar, target, P.abort_flag, P.spin_limit)) return;            \
+  if (P.trace && blockIdx.x == 0 && threadIdx.x == 0 && nsync < P.trace_len)       \
+    P.trace[nsync] = wall_clock64();                                              \
+  ++nsync;
 
   for (int t = 0; t < P.T; ++t) {
-    PassCtx c = P.c;
-    const int r0 = P.row_start[t];
-    c.M = P.row_start[t + 1] - r0;
-    if (c.M == 0) continue;  // same for every block
-    c.gpos = P.gpos_all + r0;
-    c.fid = P.fid_all + r0;
+    const SymArgs& sy = P.stab[t];
+    if (sy.M == 0) continue;  // same for every block
+    const GemmArgs* g = P.gtab + (size_t)t * ng;
+    const AttnArgs* at = P.atab + (size_t)t * na;
 
-    gemm_phase<A_FLOAT, true, EPI_STORE>(args_acc_q(x, w, c), smem4, rstd);
+    gemm_phase<A_FLOAT, true, EPI_STORE, Q>(g[0], smem4, rstd);
     PSWA_SYNC
-    attn_phase(args_acc_attn(x, w, c), smem);
+    attn_phase<DH>(at[0], smem);
     PSWA_SYNC
-    gemm_phase<A_FLOAT, false, EPI_RESID>(args_acc_o(x, w, c), smem4, rstd);
+    gemm_phase<A_FLOAT, false, EPI_RESID, Q>(g[1], smem4, rstd);
     PSWA_SYNC
-    for (int l = 0; l < x.L; ++l) {
-      gemm_phase<A_FLOAT, true, EPI_QKV>(args_qkv(x, w, c, l), smem4, rstd);
+    for (int l = 0; l < L; ++l) {
+      gemm_phase<A_FLOAT, true, EPI_QKV, Q>(g[2 + 4 * l], smem4, rstd);
       PSWA_SYNC
-      attn_phase(args_attn(x, w, c, l), smem);
+      attn_phase<DH>(at[1 + l], smem);
       PSWA_SYNC
-      gemm_phase<A_FLOAT, false, EPI_RESID>(args_o(x, w, c, l), smem4, rstd);
+      gemm_phase<A_FLOAT, false, EPI_RESID, Q>(g[3 + 4 * l], smem4, rstd);
       PSWA_SYNC
-      gemm_phase<A_FLOAT, true, EPI_SWIGLU>(args_gateup(x, w, c, l), smem4, rstd);
+      gemm_phase<A_FLOAT, true, EPI_SWIGLU, Q>(g[4 + 4 * l], smem4, rstd);
       PSWA_SYNC
-      gemm_phase<A_FLOAT, false, EPI_RESID>(args_down(x, w, c, l), smem4, rstd);
+      gemm_phase<A_FLOAT, false, EPI_RESID, Q>(g[5 + 4 * l], smem4, rstd);
       PSWA_SYNC
     }
-    gemm_phase<A_FLOAT, true, EPI_SILU>(args_head1(x, w, c), smem4, rstd);
+    gemm_phase<A_FLOAT, true, EPI_SILU, Q>(g[2 + 4 * L], smem4, rstd);
     PSWA_SYNC
-    gemm_phase<A_FLOAT, false, EPI_HEAD>(args_head2(x, w, c), smem4, rstd);
+    gemm_phase<A_FLOAT, false, EPI_HEAD, Q>(g[3 + 4 * L], smem4, rstd);
     PSWA_SYNC
-    symbol_phase(c, x.C);
+    symbol_phase(sy);
     PSWA_SYNC
-    gemm_phase<A_INT, false, EPI_STORE>(args_embed(x, w, c), smem4, rstd);
+    gemm_phase<A_INT, false, EPI_STORE, Q>(g[4 + 4 * L], smem4, rstd);
     PSWA_SYNC
-    gemm_phase<A_FLOAT, true, EPI_STORE>(args_acc_kv(x, w, c), smem4, rstd);
+    gemm_phase<A_FLOAT, true, EPI_STORE, Q>(g[5 + 4 * L], smem4, rstd);
     PSWA_SYNC
   }
 #undef PSWA_SYNC
@@ -150,14 +161,24 @@ size_t persistent_lds_bytes(const NetDims& x, int prec) {
   return b;
 }
 
+// The instance for a model: projection arithmetic and head size.
+const void* persistent_fn(int prec, int dh) {
+#define PSWA_P(Q_, D_) \
+  if (bool(prec) == Q_ && dh == D_) return reinterpret_cast<const void*>(&k_persistent<Q_, D_>)
+  PSWA_P(false, 16); PSWA_P(false, 32); PSWA_P(false, 48); PSWA_P(false, 64);
+  PSWA_P(true, 16); PSWA_P(true, 32); PSWA_P(true, 48); PSWA_P(true, 64);
+#undef PSWA_P
+  return nullptr;
+}
+
 int persistent_max_grid(const NetDims& x, int prec) {
-  static const bool attr = allow_big_lds(reinterpret_cast<const void*>(&k_persistent));
-  (void)attr;
+  const void* fn = persistent_fn(prec, x.dh);
+  if (!fn || !allow_big_lds(fn)) return 0;
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent, kThreads,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads,
                                                    persistent_lds_bytes(x, prec)) != hipSuccess)
     return 0;
   return cus * per_cu;
@@ -167,11 +188,12 @@ void zero_ints(int* p, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_ints, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
 }
 
-void launch_persistent(const PersistArgs& P, int grid, hipStream_t s) {
-  static const bool attr = allow_big_lds(reinterpret_cast<const void*>(&k_persistent));
-  (void)attr;
-  hipLaunchKernelGGL(k_persistent, dim3(grid), dim3(kThreads), persistent_lds_bytes(P.x, P.w.prec),
-                     s, P);
+void launch_persistent(const PersistArgs& P, const NetDims& x, int prec, int grid,
+                       hipStream_t s) {
+  const void* fn = persistent_fn(prec, x.dh);
+  if (!fn) return;  // head sizes are checked when the model is created
+  void* args[] = {const_cast<PersistArgs*>(&P)};
+  (void)hipLaunchKernel(fn, dim3(grid), dim3(kThreads), args, persistent_lds_bytes(x, prec), s);
 }
 
 }  // namespace pswa

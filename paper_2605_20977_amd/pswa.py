@@ -85,6 +85,7 @@ def _load():
         "pswa_batch_max_grid": (i32, [vp]),
         "pswa_batch_set_grid": (i32, [vp, i32]),
         "pswa_batch_set_spin_limit": (i32, [vp, C.c_int64]),
+        "pswa_batch_trace": (i32, [vp, vp, i32]),
         "pswa_batch_destroy": (None, [vp]),
         "pswa_quantize": (i32, [i32, vp, sz, vp, P(C.c_float)]),
         "pswa_profile_enable": (i32, [i32]),
@@ -110,7 +111,7 @@ EXPORTED = ("pswa_model_blob_floats", "pswa_model_device_bytes", "pswa_model_cre
             "pswa_batch_check", "pswa_batch_outputs", "pswa_batch_num_steps",
             "pswa_batch_max_rows", "pswa_batch_grid", "pswa_batch_max_grid",
             "pswa_batch_set_grid", "pswa_batch_set_spin_limit", "pswa_batch_destroy",
-            "pswa_quantize")
+            "pswa_quantize", "pswa_batch_trace")
 
 
 def lib():
@@ -397,6 +398,10 @@ class Batch:
 
     def set_spin_limit(self, n):
         _check(_lib.pswa_batch_set_spin_limit(self.handle, int(n)))
+
+    def set_trace(self, buf):
+        """buf: int64 device tensor (or None to stop tracing)."""
+        _check(_lib.pswa_batch_trace(self.handle, _ptr(buf), 0 if buf is None else buf.numel()))
 
     def run(self):
         _check(_lib.pswa_batch_run(self.handle, _stream()))
