@@ -220,8 +220,25 @@ int pswa_batch_num_steps(const pswa_batch* batch);  /* global steps */
 int pswa_batch_max_rows(const pswa_batch* batch);   /* largest step */
 int pswa_batch_grid(const pswa_batch* batch);       /* current grid */
 int pswa_batch_max_grid(const pswa_batch* batch);   /* co-resident limit */
-/* Choose the persistent grid (the autotuner's knob); 1 <= grid <= max. */
+/* Choose the persistent grid (an autotuner knob); 1 <= grid <= max. */
 pswa_status pswa_batch_set_grid(pswa_batch* batch, int grid);
+/* Rows per BF16/FP8 GEMM tile, 16 or 32 (an autotuner knob; it changes which
+ * tile computes a row, never the row's arithmetic). FP32 models reject 16. */
+pswa_status pswa_batch_set_rtile(pswa_batch* batch, int rtile);
+int pswa_batch_rtile(const pswa_batch* batch);
+/* Autotuner: times every (grid, row tile) candidate on a window of the
+ * widest global steps (reps timed runs each, median) and keeps the fastest.
+ * With cache_path, a result for the same device, model and frame mix is read
+ * from that file (JSON lines) instead of timing, and new results are
+ * appended. Reports the choice and the estimated whole-run time. Waits. */
+pswa_status pswa_batch_autotune(pswa_batch* batch, const char* cache_path, int reps,
+                                void* stream, int* out_grid, int* out_rtile, float* out_ms);
+/* Record one full run (as pswa_batch_run does it) into a HIP graph; later
+ * pswa_batch_run calls launch the graph, which reads the frames' input
+ * buffers as they are at launch time. Changing the grid, row tile, spin limit
+ * or trace buffer drops the graph. The capture uses a private stream; the kernel timer must be
+ * off. */
+pswa_status pswa_batch_capture(pswa_batch* batch, void* stream);
 /* Bound on the spin count of one grid-barrier wait before the launch aborts
  * (default about a second of waiting). Lowering it forces the abort path. */
 pswa_status pswa_batch_set_spin_limit(pswa_batch* batch, int64_t spins);

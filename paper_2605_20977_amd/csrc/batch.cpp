@@ -39,6 +39,11 @@ struct pswa_batch {
   double alg_bytes = 0, alg_flops = 0;  // one persistent launch, for the timer
   long long* trace = nullptr;
   int trace_len = 0;
+  int rtile = 32;                       // A rows per MFMA tile (16 or 32)
+  hipGraphExec_t graph = nullptr;       // captured run (pswa_batch_capture)
+  ~pswa_batch() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+  }
   bool any_p = false;
   // device (inside the caller's workspace)
   FrameInfo* d_frames = nullptr;
@@ -208,6 +213,8 @@ PersistArgs persist_args(const pswa_batch* b) {
   P.stab = b->stab;
   P.T = b->T;
   P.L = b->model->x.L;
+  P.t_begin = 0;
+  P.t_end = b->T;
   P.bar = reinterpret_cast<unsigned*>(b->ctl);
   P.abort_flag = b->ctl + 1;
   P.spin_limit = b->spin_limit;
@@ -217,6 +224,10 @@ PersistArgs persist_args(const pswa_batch* b) {
 }
 
 pswa_status run(pswa_batch* b, hipStream_t st) {
+  if (b->graph) {
+    PSWA_HIP_TRY(hipGraphLaunch(b->graph, st));
+    return PSWA_OK;
+  }
   const pswa_model* m = b->model;
   const NetDims& x = m->x;
   zero_ints(b->ctl, 3, st);
@@ -236,10 +247,18 @@ pswa_status run(pswa_batch* b, hipStream_t st) {
     }
   }
   const int ev = prof_begin(st);
-  launch_persistent(persist_args(b), m->x, m->w.prec, b->grid, st);
+  launch_persistent(persist_args(b), m->x, m->w.prec, b->rtile, b->grid, st);
   prof_end(ev, st, R_PERSIST, b->alg_bytes, b->alg_flops);
   PSWA_HIP_TRY(hipGetLastError());
   return PSWA_OK;
+}
+
+// Any change to the launch configuration invalidates a captured graph.
+void drop_graph(pswa_batch* b) {
+  if (b->graph) {
+    (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+  }
 }
 
 // Algorithmic bytes and flops of one persistent launch: the per-phase
@@ -351,6 +370,135 @@ pswa_status pswa_batch_set_grid(pswa_batch* b, int grid) {
   if (grid < 1 || grid > b->max_grid)
     return fail(PSWA_E_ARG, "grid %d outside [1, %d]", grid, b->max_grid);
   b->grid = grid;
+  drop_graph(b);
+  return PSWA_OK;
+}
+
+pswa_status pswa_batch_set_rtile(pswa_batch* b, int rtile) {
+  if (!b) return fail(PSWA_E_ARG, "batch is null");
+  if (rtile != 16 && rtile != 32) return fail(PSWA_E_ARG, "row tile must be 16 or 32");
+  if (rtile == 16 && b->model->w.prec == PSWA_PREC_F32)
+    return fail(PSWA_E_UNSUPPORTED, "FP32 models use 16-row FP32 tiles only");
+  b->rtile = rtile;
+  drop_graph(b);
+  return PSWA_OK;
+}
+
+int pswa_batch_rtile(const pswa_batch* b) { return b ? b->rtile : -1; }
+
+pswa_status pswa_batch_capture(pswa_batch* b, void* stream) {
+  if (!b) return fail(PSWA_E_ARG, "batch is null");
+  if (prof_on()) return fail(PSWA_E_ARG, "turn the kernel timer off before capturing");
+  (void)stream;
+  drop_graph(b);
+  // capture on a private stream (the null stream cannot be captured)
+  hipStream_t cs;
+  PSWA_HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  pswa_status st = PSWA_OK;
+  if (e == hipSuccess) {
+    st = run(b, cs);
+    e = hipStreamEndCapture(cs, &g);
+  }
+  if (e == hipSuccess && st == PSWA_OK) e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipStreamDestroy(cs);
+  if (st != PSWA_OK) return st;
+  if (e != hipSuccess) {
+    b->graph = nullptr;
+    return fail(PSWA_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+  }
+  return PSWA_OK;
+}
+
+pswa_status pswa_batch_autotune(pswa_batch* b, const char* cache_path, int reps, void* stream,
+                                int* out_grid, int* out_rtile, float* out_ms) {
+  if (!b || !out_grid || !out_rtile || !out_ms) return fail(PSWA_E_ARG, "null argument");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const pswa_model* m = b->model;
+  const NetDims& x = m->x;
+  // cache key: device, model shape and precision, frame mix
+  int dev = 0;
+  hipDeviceProp_t prop;
+  PSWA_HIP_TRY(hipGetDevice(&dev));
+  PSWA_HIP_TRY(hipGetDeviceProperties(&prop, dev));
+  std::ostringstream key;
+  key << prop.gcnArchName << "|L" << x.L << ".d" << x.d << ".h" << x.heads << ".r" << x.r
+      << ".F" << x.F << ".C" << x.C << ".p" << m->w.prec << "|";
+  for (const FrameInfo& f : b->finfo) key << f.H << "x" << f.W << (f.n_prev ? "P" : "I") << ",";
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      const std::string k = "{\"key\": \"" + key.str() + "\"";
+      if (line.compare(0, k.size(), k) != 0) continue;
+      int g = 0, r = 0;
+      float ms = 0;
+      if (std::sscanf(line.c_str() + k.size(), ", \"grid\": %d, \"rtile\": %d, \"ms\": %f", &g,
+                      &r, &ms) == 3 &&
+          g >= 1 && g <= b->max_grid && (r == 16 || r == 32)) {
+        b->grid = g;
+        b->rtile = r;
+        *out_grid = g;
+        *out_rtile = r;
+        *out_ms = ms;
+        return PSWA_OK;
+      }
+    }
+  }
+  // time a window of the widest global steps
+  const int w = std::min(b->T, 24);
+  const int t0 = std::max(0, b->T / 2 - w / 2);
+  std::vector<int> grids;
+  for (int g : {16, 24, 32, 48, 64, 96, 128, 192, 256})
+    if (g <= b->max_grid) grids.push_back(g);
+  std::vector<int> rtiles = m->w.prec ? std::vector<int>{16, 32} : std::vector<int>{32};
+  hipEvent_t e0, e1;
+  PSWA_HIP_TRY(hipEventCreate(&e0));
+  PSWA_HIP_TRY(hipEventCreate(&e1));
+  float best = 1e30f;
+  int bg = b->grid, br = b->rtile;
+  for (int r : rtiles)
+    for (int g : grids) {
+      PersistArgs P = persist_args(b);
+      P.t_begin = t0;
+      P.t_end = t0 + w;
+      P.trace = nullptr;
+      std::vector<float> t;
+      for (int i = 0; i <= std::max(1, reps); ++i) {
+        zero_ints(b->ctl, 2, st);
+        PSWA_HIP_TRY(hipEventRecord(e0, st));
+        launch_persistent(P, x, m->w.prec, r, g, st);
+        PSWA_HIP_TRY(hipEventRecord(e1, st));
+        PSWA_HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0;
+        PSWA_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (i > 0) t.push_back(ms);  // the first run warms up
+      }
+      int ab = 0;
+      PSWA_HIP_TRY(hipMemcpy(&ab, b->ctl + 1, sizeof ab, hipMemcpyDeviceToHost));
+      std::sort(t.begin(), t.end());
+      const float med = t[t.size() / 2];
+      if (!ab && med < best) {
+        best = med;
+        bg = g;
+        br = r;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->grid = bg;
+  b->rtile = br;
+  drop_graph(b);
+  *out_grid = bg;
+  *out_rtile = br;
+  *out_ms = best * float(b->T) / float(w);  // whole-run estimate
+  if (cache_path) {
+    std::ofstream o(cache_path, std::ios::app);
+    o << "{\"key\": \"" << key.str() << "\", \"grid\": " << bg << ", \"rtile\": " << br
+      << ", \"ms\": " << *out_ms << "}\n";
+  }
   return PSWA_OK;
 }
 
@@ -400,6 +548,7 @@ pswa_status pswa_batch_set_spin_limit(pswa_batch* b, int64_t spins) {
   if (!b) return fail(PSWA_E_ARG, "batch is null");
   if (spins < 0) return fail(PSWA_E_ARG, "spin limit must be >= 0");
   b->spin_limit = long(spins);
+  drop_graph(b);
   return PSWA_OK;
 }
 
@@ -408,6 +557,7 @@ pswa_status pswa_batch_trace(pswa_batch* b, int64_t* d_trace, int n) {
   if (n < 0 || (n > 0 && !d_trace)) return fail(PSWA_E_ARG, "bad trace buffer");
   b->trace = reinterpret_cast<long long*>(d_trace);
   b->trace_len = n;
+  drop_graph(b);
   return PSWA_OK;
 }
 

@@ -35,7 +35,7 @@ namespace dev {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kMBq = 32;        // A rows per low-precision tile
+constexpr int kMBq = 32;        // largest A-row count of a low-precision tile
 constexpr float kFp8Max = 448.0f;
 
 __host__ __device__ inline int qgemm_col_tiles(int N, int epi) {
@@ -43,7 +43,7 @@ __host__ __device__ inline int qgemm_col_tiles(int N, int epi) {
   return (N + per - 1) / per;
 }
 constexpr int kKchunk = 16;  // k-steps whose weight loads are issued together
-__host__ __device__ inline int qgemm_row_tiles(int M) { return (M + kMBq - 1) / kMBq; }
+__host__ __device__ inline int qgemm_row_tiles(int M, int R = kMBq) { return (M + R - 1) / R; }
 // element pitch of a staged row: K plus a 16-byte skew
 __host__ __device__ inline int qgemm_pitch(int K, int prec) { return K + (prec == PSWA_PREC_BF16 ? 8 : 16); }
 // LDS of a tile: the staged A tile (kQRedBytes is a spare prefix kept for
@@ -59,9 +59,11 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
   return uint16_t(u >> 16);
 }
 
-// stage = false reuses the A tile (and its row statistics) that this block
-// staged for the same row tile of the same GEMM just before.
-template <int AK, bool RMS, int EPI, int PREC>
+// R = A rows per tile (16 or 32, one or two 16-row MFMA blocks); a row
+// always sits at position (row % 16) of its MFMA block, so R changes which
+// tile computes a row, never how. stage = false reuses the A tile (and its
+// row statistics) this block staged for the same row tile just before.
+template <int AK, bool RMS, int EPI, int PREC, int R = kMBq>
 __device__ void gemm_tile_q(const GemmArgs& a, int bx, int by, uint8_t* lds, float* rstd,
                             float* rmul, bool stage = true) {
   uint8_t* smem = lds + kQRedBytes;
@@ -70,8 +72,8 @@ __device__ void gemm_tile_q(const GemmArgs& a, int bx, int by, uint8_t* lds, flo
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int K = a.K, K4 = a.K / 4;
   const int pitch = qgemm_pitch(K, PREC);
-  const int m0 = by * kMBq;
-  const int rows = min(kMBq, a.M - m0);
+  const int m0 = by * R;
+  const int rows = min(R, a.M - m0);
   __syncthreads();  // the previous tile of this block is done with the LDS
 
   // 1. row statistics (two rows per wave at a time, every chunk in flight)
@@ -126,7 +128,7 @@ __device__ void gemm_tile_q(const GemmArgs& a, int bx, int by, uint8_t* lds, flo
       }
     }
   } else {
-    if (tid < kMBq) {
+    if (tid < R) {
       rstd[tid] = 1.0f;
       rmul[tid] = 1.0f;
     }
@@ -136,7 +138,7 @@ __device__ void gemm_tile_q(const GemmArgs& a, int bx, int by, uint8_t* lds, flo
   // 2. stage the scaled rows as BF16 / FP8, 16 loads per thread in flight;
   // rows past the end of A are zeros (their results are dropped)
   if (stage) {
-    const int total = kMBq * K4;
+    const int total = R * K4;
     for (int base = 0; base < total; base += 16 * kThreads) {
       float4 xv[16];
 #pragma unroll
@@ -208,10 +210,11 @@ __device__ void gemm_tile_q(const GemmArgs& a, int bx, int by, uint8_t* lds, flo
         if (k0 + u < ksteps) {
           const int k = 32 * (k0 + u) + 8 * kg;
           const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(smem + (size_t)(col * pitch + k) * 2);
-          const bf16x8 a1 =
-              *reinterpret_cast<const bf16x8*>(smem + (size_t)((16 + col) * pitch + k) * 2);
+          const bf16x8 a1 = R == 32 ? *reinterpret_cast<const bf16x8*>(
+                                          smem + (size_t)((16 + col) * pitch + k) * 2)
+                                    : a0;
           c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b[u], c0, 0, 0, 0);
-          c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b[u], c1, 0, 0, 0);
+          if (R == 32) c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b[u], c1, 0, 0, 0);
         }
       }
     } else {
@@ -225,9 +228,10 @@ __device__ void gemm_tile_q(const GemmArgs& a, int bx, int by, uint8_t* lds, flo
         if (k0 + u < ksteps) {
           const int k = 32 * (k0 + u) + 8 * kg;
           const long a0 = *reinterpret_cast<const long*>(smem + (size_t)(col * pitch + k));
-          const long a1 = *reinterpret_cast<const long*>(smem + (size_t)((16 + col) * pitch + k));
+          const long a1 =
+              R == 32 ? *reinterpret_cast<const long*>(smem + (size_t)((16 + col) * pitch + k)) : a0;
           c0 = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a0, b[u], c0, 0, 0, 0);
-          c1 = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a1, b[u], c1, 0, 0, 0);
+          if (R == 32) c1 = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a1, b[u], c1, 0, 0, 0);
         }
       }
     }
@@ -236,7 +240,7 @@ __device__ void gemm_tile_q(const GemmArgs& a, int bx, int by, uint8_t* lds, flo
   // 4. epilogue: lane holds rows 16*rb + 4*kg + i of its column
   const float wsc = (PAIRED && col >= 8) ? a.w2scale : a.wscale;
 #pragma unroll
-  for (int rb = 0; rb < 2; ++rb) {
+  for (int rb = 0; rb < R / 16; ++rb) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int mr = 16 * rb + 4 * kg + i;
@@ -257,13 +261,13 @@ __device__ void gemm_tile_q(const GemmArgs& a, int bx, int by, uint8_t* lds, flo
   }
 }
 
-template <int AK, bool RMS, int EPI>
+template <int AK, bool RMS, int EPI, int R = kMBq>
 __device__ __forceinline__ void gemm_tile_q_any(const GemmArgs& a, int bx, int by, uint8_t* lds,
                                                 float* rstd, float* rmul, bool stage = true) {
   if (a.prec == PSWA_PREC_BF16)
-    gemm_tile_q<AK, RMS, EPI, PSWA_PREC_BF16>(a, bx, by, lds, rstd, rmul, stage);
+    gemm_tile_q<AK, RMS, EPI, PSWA_PREC_BF16, R>(a, bx, by, lds, rstd, rmul, stage);
   else
-    gemm_tile_q<AK, RMS, EPI, PSWA_PREC_FP8>(a, bx, by, lds, rstd, rmul, stage);
+    gemm_tile_q<AK, RMS, EPI, PSWA_PREC_FP8, R>(a, bx, by, lds, rstd, rmul, stage);
 }
 
 }  // namespace dev

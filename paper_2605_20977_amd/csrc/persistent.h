@@ -31,6 +31,7 @@ struct PersistArgs {
   const AttnArgs* atab;    // [T][1 + L]
   const SymArgs* stab;     // [T]
   int T, L;
+  int t_begin, t_end;      // global steps run by this launch (0, T for a decode)
   unsigned* bar;           // barrier arrivals (zeroed before each launch)
   int* abort_flag;         // set when a barrier wait exceeds spin_limit
   long spin_limit;
@@ -44,7 +45,8 @@ inline int attn_phases(int L) { return 1 + L; }
 size_t persistent_lds_bytes(const NetDims& x, int prec);
 // Largest grid whose blocks can all be resident at once (0 on error).
 int persistent_max_grid(const NetDims& x, int prec);
-void launch_persistent(const PersistArgs& P, const NetDims& x, int prec, int grid, hipStream_t s);
+void launch_persistent(const PersistArgs& P, const NetDims& x, int prec, int rtile, int grid,
+                       hipStream_t s);
 void zero_ints(int* p, int n, hipStream_t s);
 
 }  // namespace pswa

@@ -54,18 +54,18 @@ __device__ bool grid_barrier(unsigned* bar, unsigned& target, int* abort_flag, l
   return s_ok != 0;
 }
 
-template <int AK, bool RMS, int EPI, bool Q>
+template <int AK, bool RMS, int EPI, bool Q, int R>
 __device__ void gemm_phase(const GemmArgs& a, float4* smem4, float* rstd) {
   __shared__ float rmul[kMBq];
   if (Q) {
     // tiles in row-tile-major order: a block re-stages A only when its next
     // tile starts a new row tile
-    const int ct = qgemm_col_tiles(a.N, EPI), rt = qgemm_row_tiles(a.M);
+    const int ct = qgemm_col_tiles(a.N, EPI), rt = qgemm_row_tiles(a.M, R);
     int staged = -1;
     for (int t = blockIdx.x; t < ct * rt; t += gridDim.x) {
       const int r = t / ct;
-      gemm_tile_q_any<AK, RMS, EPI>(a, t % ct, r, reinterpret_cast<uint8_t*>(smem4), rstd, rmul,
-                                    r != staged);
+      gemm_tile_q_any<AK, RMS, EPI, R>(a, t % ct, r, reinterpret_cast<uint8_t*>(smem4), rstd,
+                                       rmul, r != staged);
       staged = r;
     }
     return;
@@ -93,7 +93,7 @@ __device__ void symbol_phase(const SymArgs& c) {
 
 // Q: the model's projections run on MFMA (BF16/FP8) rather than FP32 SIMT;
 // one instance per arithmetic keeps each one's register budget separate.
-template <bool Q, int DH>
+template <bool Q, int DH, int R>
 __global__ void __launch_bounds__(kThreads) k_persistent(PersistArgs P) {
   extern __shared__ float4 smem4[];
   __shared__ float rstd[kMBq];
@@ -107,39 +107,39 @@ __global__ void __launch_bounds__(kThreads) k_persistent(PersistArgs P) {
     P.trace[nsync] = wall_clock64();                                              \
   ++nsync;
 
-  for (int t = 0; t < P.T; ++t) {
+  for (int t = P.t_begin; t < P.t_end; ++t) {
     const SymArgs& sy = P.stab[t];
     if (sy.M == 0) continue;  // same for every block
     const GemmArgs* g = P.gtab + (size_t)t * ng;
     const AttnArgs* at = P.atab + (size_t)t * na;
 
-    gemm_phase<A_FLOAT, true, EPI_STORE, Q>(g[0], smem4, rstd);
+    gemm_phase<A_FLOAT, true, EPI_STORE, Q, R>(g[0], smem4, rstd);
     PSWA_SYNC
     attn_phase<DH>(at[0], smem);
     PSWA_SYNC
-    gemm_phase<A_FLOAT, false, EPI_RESID, Q>(g[1], smem4, rstd);
+    gemm_phase<A_FLOAT, false, EPI_RESID, Q, R>(g[1], smem4, rstd);
     PSWA_SYNC
     for (int l = 0; l < L; ++l) {
-      gemm_phase<A_FLOAT, true, EPI_QKV, Q>(g[2 + 4 * l], smem4, rstd);
+      gemm_phase<A_FLOAT, true, EPI_QKV, Q, R>(g[2 + 4 * l], smem4, rstd);
       PSWA_SYNC
       attn_phase<DH>(at[1 + l], smem);
       PSWA_SYNC
-      gemm_phase<A_FLOAT, false, EPI_RESID, Q>(g[3 + 4 * l], smem4, rstd);
+      gemm_phase<A_FLOAT, false, EPI_RESID, Q, R>(g[3 + 4 * l], smem4, rstd);
       PSWA_SYNC
-      gemm_phase<A_FLOAT, true, EPI_SWIGLU, Q>(g[4 + 4 * l], smem4, rstd);
+      gemm_phase<A_FLOAT, true, EPI_SWIGLU, Q, R>(g[4 + 4 * l], smem4, rstd);
       PSWA_SYNC
-      gemm_phase<A_FLOAT, false, EPI_RESID, Q>(g[5 + 4 * l], smem4, rstd);
+      gemm_phase<A_FLOAT, false, EPI_RESID, Q, R>(g[5 + 4 * l], smem4, rstd);
       PSWA_SYNC
     }
-    gemm_phase<A_FLOAT, true, EPI_SILU, Q>(g[2 + 4 * L], smem4, rstd);
+    gemm_phase<A_FLOAT, true, EPI_SILU, Q, R>(g[2 + 4 * L], smem4, rstd);
     PSWA_SYNC
-    gemm_phase<A_FLOAT, false, EPI_HEAD, Q>(g[3 + 4 * L], smem4, rstd);
+    gemm_phase<A_FLOAT, false, EPI_HEAD, Q, R>(g[3 + 4 * L], smem4, rstd);
     PSWA_SYNC
     symbol_phase(sy);
     PSWA_SYNC
-    gemm_phase<A_INT, false, EPI_STORE, Q>(g[4 + 4 * L], smem4, rstd);
+    gemm_phase<A_INT, false, EPI_STORE, Q, R>(g[4 + 4 * L], smem4, rstd);
     PSWA_SYNC
-    gemm_phase<A_FLOAT, true, EPI_STORE, Q>(g[5 + 4 * L], smem4, rstd);
+    gemm_phase<A_FLOAT, true, EPI_STORE, Q, R>(g[5 + 4 * L], smem4, rstd);
     PSWA_SYNC
   }
 #undef PSWA_SYNC
@@ -161,18 +161,21 @@ size_t persistent_lds_bytes(const NetDims& x, int prec) {
   return b;
 }
 
-// The instance for a model: projection arithmetic and head size.
-const void* persistent_fn(int prec, int dh) {
-#define PSWA_P(Q_, D_) \
-  if (bool(prec) == Q_ && dh == D_) return reinterpret_cast<const void*>(&k_persistent<Q_, D_>)
-  PSWA_P(false, 16); PSWA_P(false, 32); PSWA_P(false, 48); PSWA_P(false, 64);
-  PSWA_P(true, 16); PSWA_P(true, 32); PSWA_P(true, 48); PSWA_P(true, 64);
+// The instance for a model: projection arithmetic, head size and (for
+// BF16/FP8) the row-tile height.
+const void* persistent_fn(int prec, int dh, int rtile) {
+#define PSWA_P(Q_, D_, R_)                                                    \
+  if (bool(prec) == Q_ && dh == D_ && (!Q_ || rtile == R_))                   \
+  return reinterpret_cast<const void*>(&k_persistent<Q_, D_, R_>)
+  PSWA_P(false, 16, 32); PSWA_P(false, 32, 32); PSWA_P(false, 48, 32); PSWA_P(false, 64, 32);
+  PSWA_P(true, 16, 16); PSWA_P(true, 32, 16); PSWA_P(true, 48, 16); PSWA_P(true, 64, 16);
+  PSWA_P(true, 16, 32); PSWA_P(true, 32, 32); PSWA_P(true, 48, 32); PSWA_P(true, 64, 32);
 #undef PSWA_P
   return nullptr;
 }
 
 int persistent_max_grid(const NetDims& x, int prec) {
-  const void* fn = persistent_fn(prec, x.dh);
+  const void* fn = persistent_fn(prec, x.dh, kMBq);
   if (!fn || !allow_big_lds(fn)) return 0;
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -188,10 +191,19 @@ void zero_ints(int* p, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_ints, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
 }
 
-void launch_persistent(const PersistArgs& P, const NetDims& x, int prec, int grid,
+void launch_persistent(const PersistArgs& P, const NetDims& x, int prec, int rtile, int grid,
                        hipStream_t s) {
-  const void* fn = persistent_fn(prec, x.dh);
-  if (!fn) return;  // head sizes are checked when the model is created
+  const void* fn = persistent_fn(prec, x.dh, rtile);
+  if (!fn) return;  // head sizes and tile heights are checked by the callers
+  static const bool attr = [] {
+    bool ok = true;
+    for (int q = 0; q < 2; ++q)
+      for (int d : {16, 32, 48, 64})
+        for (int r : {16, 32})
+          if (const void* f = persistent_fn(q, d, r)) ok = allow_big_lds(f) && ok;
+    return ok;
+  }();
+  (void)attr;
   void* args[] = {const_cast<PersistArgs*>(&P)};
   (void)hipLaunchKernel(fn, dim3(grid), dim3(kThreads), args, persistent_lds_bytes(x, prec), s);
 }

@@ -86,6 +86,10 @@ def _load():
         "pswa_batch_set_grid": (i32, [vp, i32]),
         "pswa_batch_set_spin_limit": (i32, [vp, C.c_int64]),
         "pswa_batch_trace": (i32, [vp, vp, i32]),
+        "pswa_batch_set_rtile": (i32, [vp, i32]),
+        "pswa_batch_rtile": (i32, [vp]),
+        "pswa_batch_autotune": (i32, [vp, C.c_char_p, i32, vp, P(i32), P(i32), P(C.c_float)]),
+        "pswa_batch_capture": (i32, [vp, vp]),
         "pswa_batch_destroy": (None, [vp]),
         "pswa_quantize": (i32, [i32, vp, sz, vp, P(C.c_float)]),
         "pswa_profile_enable": (i32, [i32]),
@@ -111,7 +115,8 @@ EXPORTED = ("pswa_model_blob_floats", "pswa_model_device_bytes", "pswa_model_cre
             "pswa_batch_check", "pswa_batch_outputs", "pswa_batch_num_steps",
             "pswa_batch_max_rows", "pswa_batch_grid", "pswa_batch_max_grid",
             "pswa_batch_set_grid", "pswa_batch_set_spin_limit", "pswa_batch_destroy",
-            "pswa_quantize", "pswa_batch_trace")
+            "pswa_quantize", "pswa_batch_trace", "pswa_batch_set_rtile", "pswa_batch_rtile",
+            "pswa_batch_autotune", "pswa_batch_capture")
 
 
 def lib():
@@ -395,6 +400,29 @@ class Batch:
 
     def set_grid(self, g):
         _check(_lib.pswa_batch_set_grid(self.handle, int(g)))
+
+    def inputs(self, k):
+        """Device tensors (latents, hyper, prev or None) that frame k reads."""
+        return tuple(self._keep[3 * k:3 * k + 3])
+
+    @property
+    def rtile(self):
+        return _lib.pswa_batch_rtile(self.handle)
+
+    def set_rtile(self, r):
+        _check(_lib.pswa_batch_set_rtile(self.handle, int(r)))
+
+    def autotune(self, cache_path=None, reps=3):
+        """Pick (grid, row tile) by timing; returns (grid, rtile, est_ms)."""
+        g, r, ms = C.c_int(), C.c_int(), C.c_float()
+        _check(_lib.pswa_batch_autotune(self.handle,
+                                        cache_path.encode() if cache_path else None, reps,
+                                        _stream(), C.byref(g), C.byref(r), C.byref(ms)))
+        return g.value, r.value, ms.value
+
+    def capture(self):
+        """Record one run into a HIP graph; later run() calls replay it."""
+        _check(_lib.pswa_batch_capture(self.handle, _stream()))
 
     def set_spin_limit(self, n):
         _check(_lib.pswa_batch_set_spin_limit(self.handle, int(n)))

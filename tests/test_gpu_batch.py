@@ -126,3 +126,85 @@ def test_batch_1080p_mix_equals_step_decode(P):
     b.check()
     for k in range(len(fr)):
         _assert_same(b.outputs(k), _per_frame(P, model, fr[k]), f"frame {k}")
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_batch_row_tile_and_autotune_keep_outputs(P, prec, tmp_path):
+    """The row tile and grid only move rows between tiles and blocks: every
+    (grid, row tile) choice, the autotuner's included, gives the same bits."""
+    cfg = synth.TINY
+    model = P.Model(cfg, synth.model_weights(cfg, 1), prec)
+    fr = _frames(cfg, [(16, 16, 0), (13, 21, 2), (4, 37, 0)], 700)
+    b = P.Batch(model, fr)
+    b.run()
+    ref = [b.outputs(k) for k in range(len(fr))]
+    for k in range(len(fr)):
+        _assert_same(ref[k], _per_frame(P, model, fr[k]), f"{prec} frame {k}")
+    for r in (16, 32):
+        for g in (5, 64):
+            print(f"case {prec} rtile {r} grid {g}", flush=True)
+            b.set_rtile(r)
+            b.set_grid(g)
+            b.run()
+            b.check()
+            for k in range(len(fr)):
+                _assert_same(b.outputs(k), ref[k], f"{prec} rtile {r} grid {g} frame {k}")
+    cache = str(tmp_path / "tune.jsonl")
+    g1, r1, ms1 = b.autotune(cache, reps=2)
+    assert 1 <= g1 <= b.max_grid and r1 in (16, 32) and ms1 > 0
+    assert (b.grid, b.rtile) == (g1, r1)
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and f'"grid": {g1}' in lines[0]
+    b.set_grid(1)
+    g2, r2, ms2 = b.autotune(cache, reps=2)          # answered from the cache
+    assert (g2, r2) == (g1, r1) and len(open(cache).read().splitlines()) == 1
+    b.run()
+    b.check()
+    for k in range(len(fr)):
+        _assert_same(b.outputs(k), ref[k], f"{prec} autotuned frame {k}")
+
+
+def test_batch_fp32_rejects_short_row_tile(P, tiny):
+    cfg, Wt, model = tiny
+    b = P.Batch(model, _frames(cfg, [(4, 4, 0)], 800))
+    with pytest.raises(P.PswaError):
+        b.set_rtile(16)
+    with pytest.raises(P.PswaError):
+        b.set_rtile(8)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_batch_graph_replays_match_eager(P, prec):
+    """A captured run replays bit-identically, several times, with eager work
+    in between, and reads the frames' inputs as they are at replay time."""
+    cfg = synth.TINY
+    model = P.Model(cfg, synth.model_weights(cfg, 1), prec)
+    fa = _frames(cfg, [(9, 11, 2), (16, 16, 0)], 900)
+    fb = _frames(cfg, [(9, 11, 2)], 950)[0]
+    ref_a = [_per_frame(P, model, f) for f in fa]
+    ref_b = _per_frame(P, model, fb)
+    b = P.Batch(model, fa, grid=24)
+    b.run()
+    for k in range(2):
+        _assert_same(b.outputs(k), ref_a[k], f"{prec} eager frame {k}")
+    print(f"case graph capture {prec}", flush=True)
+    b.capture()
+    for rep in range(3):
+        b.run()
+        b.check()
+        for k in range(2):
+            _assert_same(b.outputs(k), ref_a[k], f"{prec} replay {rep} frame {k}")
+        # eager work on the same stream between replays
+        _assert_same(_per_frame(P, model, fa[1]), ref_a[1], f"{prec} eager between {rep}")
+    y, z, pv = b.inputs(0)
+    y.copy_(torch.as_tensor(fb["latents"], device=y.device))
+    z.copy_(torch.as_tensor(fb["hyper"], device=z.device))
+    pv.copy_(torch.as_tensor(fb["prev"], device=pv.device))
+    b.run()
+    b.check()
+    _assert_same(b.outputs(0), ref_b, f"{prec} replay on new inputs")
+    _assert_same(b.outputs(1), ref_a[1], f"{prec} replay on new inputs, frame 1")
+    b.set_grid(7)                                     # drops the graph: eager again
+    b.run()
+    b.check()
+    _assert_same(b.outputs(0), ref_b, f"{prec} eager after drop")
