@@ -235,9 +235,10 @@ pswa_status pswa_batch_autotune(pswa_batch* batch, const char* cache_path, int r
                                 void* stream, int* out_grid, int* out_rtile, float* out_ms);
 /* Record one full run (as pswa_batch_run does it) into a HIP graph; later
  * pswa_batch_run calls launch the graph, which reads the frames' input
- * buffers as they are at launch time. Changing the grid, row tile, spin limit
- * or trace buffer drops the graph. The capture uses a private stream; the kernel timer must be
- * off. */
+ * buffers as they are at launch time. While the kernel timer is on, runs are
+ * issued kernel by kernel (same kernels, same arguments) so each is timed.
+ * Changing the grid, row tile, spin limit or trace buffer drops the graph.
+ * The capture uses a private stream; the kernel timer must be off. */
 pswa_status pswa_batch_capture(pswa_batch* batch, void* stream);
 /* Bound on the spin count of one grid-barrier wait before the launch aborts
  * (default about a second of waiting). Lowering it forces the abort path. */

@@ -8,17 +8,22 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpswa.so")
+OBJ = os.path.join(PKG, "_build")
 
 SOURCES = ["kernels_f32.hip", "persistent.hip", "pswa_capi.cpp", "batch.cpp", "coder.cpp",
            "profile.cpp"]
+# persistent_kernel.hip is compiled once per (arithmetic, head size, row tile)
+PERSISTENT_INSTANCES = [(0, d, 32) for d in (16, 32, 48, 64)] + [
+    (p, d, r) for p in (1, 2) for r in (16, 32) for d in (16, 32, 48, 64)]
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no implicit multiply-add contraction: identical source gives identical
     # arithmetic in every kernel and translation unit
     "-ffp-contract=off",
@@ -28,24 +33,51 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = True) -> str:
-    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           *srcs, "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
+def _run(cmd):
     r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
+    # host-pass notes about the packed-fp32 feature are expected
+    err = "\n".join(ln for ln in r.stderr.splitlines() if "packed-fp32-ops" not in ln)
+    return r.returncode, err
+
+
+def build(verbose: bool = True, jobs: int | None = None) -> str:
+    """Compile every object (in parallel) and link libpswa.so."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    os.makedirs(OBJ, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    units = []  # the long persistent instances first
+    for p, d, r in PERSISTENT_INSTANCES:
+        obj = os.path.join(OBJ, f"persistent_kernel_{p}_{d}_{r}.o")
+        units.append([hipcc, *HIPCC_FLAGS, *inc, f"-DPSWA_PREC={p}", f"-DPSWA_DH={d}",
+                      f"-DPSWA_R={r}", "-c", os.path.join(CSRC, "persistent_kernel.hip"),
+                      "-o", obj])
+    for src in SOURCES:
+        obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
+        units.append([hipcc, *HIPCC_FLAGS, *inc, "-c", os.path.join(CSRC, src), "-o", obj])
+    jobs = jobs or min(16, os.cpu_count() or 1)
+    if verbose:
+        print(f"compiling {len(units)} objects with {jobs} jobs", flush=True)
+    with ThreadPoolExecutor(jobs) as ex:
+        results = list(ex.map(_run, units))
+    failed = False
+    for cmd, (rc, err) in zip(units, results):
+        if rc != 0:
+            failed = True
+            sys.stderr.write(" ".join(cmd) + "\n" + err + "\n")
+        elif verbose and err.strip():
+            sys.stderr.write(err + "\n")
+    if failed:
         raise RuntimeError("hipcc failed building libpswa.so")
-    if verbose and r.stderr.strip():
-        # host-pass notes about the packed-fp32 feature are expected
-        lines = [ln for ln in r.stderr.splitlines() if "packed-fp32-ops" not in ln]
-        if lines:
-            sys.stderr.write("\n".join(lines) + "\n")
+    tmp = LIB + ".tmp"
+    objs = [u[-1] for u in units]
+    link = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    rc, err = _run(link)
+    if rc != 0:
+        sys.stderr.write(" ".join(link) + "\n" + err + "\n")
+        raise RuntimeError("linking libpswa.so failed")
     os.replace(tmp, LIB)
+    if verbose:
+        print(f"built {LIB}", flush=True)
     return LIB
 
 

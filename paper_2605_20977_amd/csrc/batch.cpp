@@ -224,7 +224,7 @@ PersistArgs persist_args(const pswa_batch* b) {
 }
 
 pswa_status run(pswa_batch* b, hipStream_t st) {
-  if (b->graph) {
+  if (b->graph && !prof_on()) {
     PSWA_HIP_TRY(hipGraphLaunch(b->graph, st));
     return PSWA_OK;
   }

@@ -137,7 +137,7 @@ __device__ __forceinline__ void epilogue(const GemmArgs& a, int row, int n, floa
 // An output's arithmetic depends only on K. Paired epilogues (SwiGLU, head):
 // a wave's weight rows are W[n], W[n+1], W2[n], W2[n+1] -> outputs n, n+1.
 template <int AK, bool RMS, int EPI, int KC>
-__device__ void gemm_tile(const GemmArgs& a, int bx, int by, float4* smem4, float* rstd) {
+__device__ __forceinline__ void gemm_tile(const GemmArgs& a, int bx, int by, float4* smem4, float* rstd) {
   constexpr bool PAIRED = paired_epi(EPI);
   float* smem = reinterpret_cast<float*>(smem4);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -178,6 +178,7 @@ __device__ void gemm_tile(const GemmArgs& a, int bx, int by, float4* smem4, floa
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int e = base + u * kThreads + tid;
+        x[u] = make_float4(0.f, 0.f, 0.f, 0.f);  // (keeps x in registers)
         if (e < total) {
           const int m = e / K4, c = e % K4;
           const size_t off = (size_t)map_row(a.xrow, m0 + m) * a.ldx + 4 * c;
@@ -282,7 +283,7 @@ __device__ __forceinline__ void gemm_tile_any(const GemmArgs& a, int bx, int by,
 // and its offset in the global position space; temporal K/V of frame
 // position g in previous frame tau is at (tau * HWt + g) * 2d.
 template <int DH>
-__device__ void attn_item(const AttnArgs& a, int item, bool live, float* tr_all) {
+__device__ __forceinline__ void attn_item(const AttnArgs& a, int item, bool live, float* tr_all) {
   float* tr = tr_all + (threadIdx.x >> 6) * (DH * 65);
   const int lane = threadIdx.x & 63;
   live = live && item < a.M * a.heads;

@@ -64,7 +64,7 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
 // tile computes a row, never how. stage = false reuses the A tile (and its
 // row statistics) this block staged for the same row tile just before.
 template <int AK, bool RMS, int EPI, int PREC, int R = kMBq>
-__device__ void gemm_tile_q(const GemmArgs& a, int bx, int by, uint8_t* lds, float* rstd,
+__device__ __forceinline__ void gemm_tile_q(const GemmArgs& a, int bx, int by, uint8_t* lds, float* rstd,
                             float* rmul, bool stage = true) {
   uint8_t* smem = lds + kQRedBytes;
   constexpr bool PAIRED = paired_epi(EPI);

@@ -39,6 +39,19 @@ struct PersistArgs {
   int trace_len;
 };
 
+// Kernel instances: (projection arithmetic, head size, row tile). Each is
+// built as its own object from persistent_kernel.hip and reached through
+// pswa_persistent_kernel_<PREC>_<DH>_<R>().
+#define PSWA_PERSISTENT_INSTANCES(X)                                              \
+  X(0, 16, 32) X(0, 32, 32) X(0, 48, 32) X(0, 64, 32)                             \
+  X(1, 16, 16) X(1, 32, 16) X(1, 48, 16) X(1, 64, 16)                             \
+  X(1, 16, 32) X(1, 32, 32) X(1, 48, 32) X(1, 64, 32)                             \
+  X(2, 16, 16) X(2, 32, 16) X(2, 48, 16) X(2, 64, 16)                             \
+  X(2, 16, 32) X(2, 32, 32) X(2, 48, 32) X(2, 64, 32)
+#define PSWA_PERSISTENT_NAME(P_, D_, R_) pswa_persistent_kernel_##P_##_##D_##_##R_
+#define PSWA_PERSISTENT_NAME_X(P_, D_, R_) PSWA_PERSISTENT_NAME(P_, D_, R_)
+#define PSWA_PERSISTENT_GETTER(P_, D_, R_) const void* PSWA_PERSISTENT_NAME_X(P_, D_, R_)()
+
 inline int gemm_phases(int L) { return 6 + 4 * L; }
 inline int attn_phases(int L) { return 1 + L; }
 
