@@ -10,8 +10,9 @@ frame); inputs resident in HBM, symbols read from device memory. Paths
   mixed<N>:<prec>  -- N frames of the mixed batch (15x20, 34x60, 45x80 and
                       68x120 in equal numbers, I- and P-frames alternating)
                       in one persistent launch;
-with <prec> one of fp32, bf16, fp8. Persistent paths pick (grid, row tile)
-with the library's autotuner and replay a captured HIP graph unless told not
+with <prec> one of fp32, bf16, fp8. Persistent paths split their frames into
+groups that run behind their own barriers; the library's autotuner picks the
+grouping and row tile, and runs replay a captured HIP graph, unless told not
 to. One step = one pass of a path over its batch. The headline `value` is the
 fastest path; `paths` gives every path's rate and its ratio to plain FP32.
 The roofline is that of the headline path's dominant kernel, timed live with
@@ -54,8 +55,10 @@ def parse():
     ap.add_argument("--paths", default=DEFAULT_PATHS,
                     help="comma list of plain:<prec>, batch<N>:<prec>, mixed<N>:<prec>")
     ap.add_argument("--grid", type=int, default=0,
-                    help="persistent grid; 0 lets the autotuner choose")
+                    help="one group of this many blocks; 0 lets the autotuner choose")
     ap.add_argument("--rtile", type=int, default=0, help="row tile 16/32; 0: autotuner")
+    ap.add_argument("--groups", default="", metavar="FxB",
+                    help="F frames per group, B blocks per group (default: autotuner)")
     ap.add_argument("--tune-cache", default=None, help="autotuner JSON-lines cache file")
     ap.add_argument("--no-graph", action="store_true", help="issue runs without a HIP graph")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -237,9 +240,13 @@ def main():
                 b.set_grid(args.grid)
             if args.rtile:
                 b.set_rtile(args.rtile)
-            if not args.grid and not args.rtile:
-                g, r, est = b.autotune(args.tune_cache, reps=2)
-                tuned = {"grid": g, "rtile": r, "est_ms": round(est, 2)}
+            if args.groups:
+                f, g = (int(v) for v in args.groups.split("x"))
+                b.set_groups(f, g)
+            if not args.grid and not args.rtile and not args.groups:
+                f, g, r, est = b.autotune(args.tune_cache, reps=2)
+                tuned = {"frames_per_group": f, "blocks_per_group": g, "rtile": r,
+                         "est_ms": round(est, 2)}
             if not args.no_graph:
                 b.capture()
 
@@ -247,8 +254,10 @@ def main():
                 b.run()
             dt = timed(run, args.steps, args.warmup)
             b.check()
+            fpg, bpg, ngr = b.groups
             paths[spec] = {"frames": n, "symbols_per_step": nsym, "grid": b.grid,
-                           "rtile": b.rtile, "graph": not args.no_graph, "autotuned": tuned,
+                           "groups": f"{ngr} x ({fpg} frames, {bpg} blocks)", "rtile": b.rtile,
+                           "graph": not args.no_graph, "autotuned": tuned,
                            "ms_per_step": 1e3 * dt / args.steps,
                            "value": nsym * args.steps / dt}
             runners[spec] = run
@@ -271,7 +280,8 @@ def main():
         workload = f"{hp['frames']} 1080p-shaped I-frames, one persistent launch"
         path_descr = (f"{prec.upper()} projections on MFMA (FP32 accumulate; FP32 softmax, "
                       f"norms, accumulator and CDF), one persistent launch per batch of "
-                      f"{hp['frames']} frames, grid {hp['grid']}, row tile {hp['rtile']}"
+                      f"{hp['frames']} frames, {hp['groups']} groups with their own barriers, "
+                      f"row tile {hp['rtile']}"
                       + (", HIP graph replay" if hp["graph"] else ""))
     roof = kernels = None
     if not args.no_roofline:

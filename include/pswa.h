@@ -189,13 +189,17 @@ typedef struct {
 typedef struct pswa_batch pswa_batch;
 
 /* Workspace bytes for the batch (0 for invalid frames). The workspace holds
- * every frame's caches and outputs plus the step tables. */
+ * every frame's caches and outputs plus row and argument tables sized for
+ * any grouping of the frames. */
 size_t pswa_batch_workspace_bytes(const pswa_model* model, int n, const pswa_batch_frame* frames);
 
 /* Plan a batch in caller-owned workspace (256-byte aligned): builds and
- * uploads the per-step row tables and waits for the upload. grid = number of
- * persistent workgroups (0: default; clamped to what can be co-resident).
- * The frames' device buffers must stay valid until pswa_batch_destroy. */
+ * uploads the row and argument tables and waits for the upload. The frames
+ * are split into groups, each decoded by its own persistent workgroups
+ * behind its own barrier (frames never depend on each other). grid > 0: one
+ * group of `grid` workgroups; grid = 0: a default grouping (8 to 32
+ * workgroups per group). Grids are clamped to what can be co-resident. The
+ * frames' device buffers must stay valid until pswa_batch_destroy. */
 pswa_status pswa_batch_create(const pswa_model* model, int n, const pswa_batch_frame* frames,
                               int grid, void* d_ws, size_t ws_bytes, void* stream,
                               pswa_batch** out);
@@ -216,37 +220,49 @@ pswa_status pswa_batch_outputs(pswa_batch* batch, int f, int32_t* d_latents_out,
                                float* d_scale, float* d_bits, int32_t* d_cdf_center,
                                uint16_t* d_cdf_index, double* h_total_bits, void* stream);
 
-int pswa_batch_num_steps(const pswa_batch* batch);  /* global steps */
-int pswa_batch_max_rows(const pswa_batch* batch);   /* largest step */
-int pswa_batch_grid(const pswa_batch* batch);       /* current grid */
+int pswa_batch_num_steps(const pswa_batch* batch);  /* global steps (longest frame) */
+int pswa_batch_max_rows(const pswa_batch* batch);   /* rows of all frames at one step, max */
+int pswa_batch_grid(const pswa_batch* batch);       /* workgroups of the launch */
 int pswa_batch_max_grid(const pswa_batch* batch);   /* co-resident limit */
-/* Choose the persistent grid (an autotuner knob); 1 <= grid <= max. */
+/* One group of `grid` workgroups for all frames; 1 <= grid <= max. Waits. */
 pswa_status pswa_batch_set_grid(pswa_batch* batch, int grid);
+/* Groups of at most frames_per_group frames with blocks_per_group
+ * workgroups each (autotuner knobs); the number of groups times
+ * blocks_per_group must not exceed the co-resident limit. Rebuilds and
+ * uploads the tables on `stream` and waits. */
+pswa_status pswa_batch_set_groups(pswa_batch* batch, int frames_per_group, int blocks_per_group,
+                                  void* stream);
+pswa_status pswa_batch_groups(const pswa_batch* batch, int* frames_per_group,
+                              int* blocks_per_group, int* n_groups);
 /* Rows per BF16/FP8 GEMM tile, 16 or 32 (an autotuner knob; it changes which
  * tile computes a row, never the row's arithmetic). FP32 models reject 16. */
 pswa_status pswa_batch_set_rtile(pswa_batch* batch, int rtile);
 int pswa_batch_rtile(const pswa_batch* batch);
-/* Autotuner: times every (grid, row tile) candidate on a window of the
- * widest global steps (reps timed runs each, median) and keeps the fastest.
- * With cache_path, a result for the same device, model and frame mix is read
- * from that file (JSON lines) instead of timing, and new results are
- * appended. Reports the choice and the estimated whole-run time. Waits. */
+/* Autotuner: times every grouping candidate (frames per group and blocks
+ * per group in powers of two) with 32-row tiles, then 16-row tiles on the
+ * best grouping (BF16/FP8), each on a window of the widest global steps
+ * (reps timed runs, median), and keeps the fastest. With cache_path, a
+ * result for the same device, model and frame mix is read from that file
+ * (JSON lines) instead of timing, and new results are appended. Reports the
+ * choice and the estimated whole-run time. Waits. */
 pswa_status pswa_batch_autotune(pswa_batch* batch, const char* cache_path, int reps,
-                                void* stream, int* out_grid, int* out_rtile, float* out_ms);
+                                void* stream, int* out_frames_per_group,
+                                int* out_blocks_per_group, int* out_rtile, float* out_ms);
 /* Record one full run (as pswa_batch_run does it) into a HIP graph; later
  * pswa_batch_run calls launch the graph, which reads the frames' input
  * buffers as they are at launch time. While the kernel timer is on, runs are
  * issued kernel by kernel (same kernels, same arguments) so each is timed.
- * Changing the grid, row tile, spin limit or trace buffer drops the graph.
- * The capture uses a private stream; the kernel timer must be off. */
+ * Changing the grouping, row tile, spin limit or trace buffer drops the
+ * graph. The capture uses a private stream; the kernel timer must be off. */
 pswa_status pswa_batch_capture(pswa_batch* batch, void* stream);
-/* Bound on the spin count of one grid-barrier wait before the launch aborts
+/* Bound on the spin count of one barrier wait before the launch aborts
  * (default about a second of waiting). Lowering it forces the abort path. */
 pswa_status pswa_batch_set_spin_limit(pswa_batch* batch, int64_t spins);
 /* Phase timeline (a profiling aid): while d_trace is set, one thread of the
- * persistent kernel writes the device wall clock (100 MHz) after each of the
- * first n grid barriers of a run to d_trace[0..n) (device int64). Barriers
- * per global step: 3 + 5 L + 5. n = 0 turns the trace off. */
+ * persistent kernel (rank 0 of group 0) writes the device wall clock
+ * (100 MHz) after each of the first n barriers of its group in a run to
+ * d_trace[0..n) (device int64). Barriers per step: 3 + 5 L + 5. n = 0 turns
+ * the trace off. */
 pswa_status pswa_batch_trace(pswa_batch* batch, int64_t* d_trace, int n);
 void pswa_batch_destroy(pswa_batch* batch);
 

@@ -2,10 +2,12 @@
 // sizes, I and P mixed, decoded in one persistent launch.
 //
 // All frames live in one global position space: frame f owns positions
-// [off_f, off_f + H_f W_f). At global step t the launch processes the union
-// of every frame's diagonal t (frames start together; a frame with fewer
-// steps simply has no rows at later steps). The per-step row tables (global
-// position and frame of each row) are built on the host once per batch.
+// [off_f, off_f + H_f W_f). The frames are split into groups (frames per
+// group and blocks per group are launch knobs); a group's rows at step t are
+// the union of its frames' diagonal t. Frames never read each other's
+// positions, so each group runs at its own pace behind its own barrier. The
+// per-step row tables (global position and frame of each row) and argument
+// tables are rebuilt on the host whenever the grouping changes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,16 +27,30 @@
 using namespace pswa;
 
 namespace {
-// Default persistent grid: the barrier's cost grows with the number of
-// blocks, and a decode phase rarely has work for more.
-constexpr int kDefaultGrid = 64;
+// Blocks of a block map (device table), a bound on any grid.
+constexpr int kMaxBlocks = 4096;
+// Ints between two groups' barrier counters (separate 256-byte lines).
+constexpr int kBarStride = 64;
 }  // namespace
+
+// One group of a grouping: its frames, steps, rows and table offsets.
+struct GroupPlan {
+  std::vector<int> frames;
+  int T = 0, Mmax = 0;
+  size_t row_off = 0;   // first activation row of the group
+  size_t tab_off = 0;   // first step record of the group in the tables
+  size_t pos_off = 0;   // first entry of the group in the row tables
+  std::vector<int> row_start;  // [T + 1], relative to pos_off
+};
 
 struct pswa_batch {
   const pswa_model* model = nullptr;
   std::vector<pswa_batch_frame> frames;
   std::vector<FrameInfo> finfo;
-  int HWt = 0, T = 0, Mmax = 0, grid = 0, max_grid = 0;
+  int HWt = 0, T = 0, Mmax = 0, max_grid = 0;
+  int fpg = 1, bpg = 1, grid = 0;       // frames and blocks per group, total blocks
+  std::vector<GroupPlan> groups;
+  size_t rows_cap = 0, steps_cap = 0;   // worst case over groupings
   long spin_limit = 1L << 21;  // barrier wait bound (about a second)
   double alg_bytes = 0, alg_flops = 0;  // one persistent launch, for the timer
   long long* trace = nullptr;
@@ -47,15 +63,18 @@ struct pswa_batch {
   bool any_p = false;
   // device (inside the caller's workspace)
   FrameInfo* d_frames = nullptr;
-  int *row_start = nullptr, *gpos_all = nullptr, *fid_all = nullptr;
+  int *gpos_all = nullptr, *fid_all = nullptr;
   float *h = nullptr, *acc_kv = nullptr, *kv = nullptr, *tkv = nullptr, *e_prev = nullptr;
   int32_t *ysrc = nullptr, *ydec = nullptr;
   float *mean = nullptr, *scale = nullptr, *bits = nullptr;
   int32_t* center = nullptr;
   uint16_t* index = nullptr;
   Acts a{};
-  int* ctl = nullptr;  // [0] barrier arrivals, [1] abort, [2] numeric flag
-  GemmArgs* gtab = nullptr;  // per-step argument tables (see persistent.h)
+  int* ctl = nullptr;   // [1] abort, [2] numeric flag
+  int* bars = nullptr;  // [frames][kBarStride]: group barrier counters
+  GroupInfo* d_groups = nullptr;
+  int* block_map = nullptr;
+  GemmArgs* gtab = nullptr;  // per-group, per-step argument tables
   AttnArgs* atab = nullptr;
   SymArgs* stab = nullptr;
   float* sum = nullptr;
@@ -65,40 +84,35 @@ struct pswa_batch {
 namespace {
 
 
+// Frame layout of a batch and the worst-case sizes of any grouping: rows of
+// all groups together (at most the sum of each frame's longest diagonal)
+// and step records (at most the sum of each frame's steps).
 struct Plan {
   std::vector<FrameInfo> finfo;
   int HWt = 0, T = 0, Mmax = 0;
+  size_t rows_cap = 0, steps_cap = 0;
   bool any_p = false;
-  std::vector<int> row_start, gpos, fid;
 };
 
-Plan make_plan(const NetDims& x, int n, const pswa_batch_frame* fr, bool tables) {
+Plan make_plan(const NetDims& x, int n, const pswa_batch_frame* fr) {
   Plan p;
   int off = 0;
   for (int f = 0; f < n; ++f) {
     const pswa_frame_desc& d = fr[f].frame;
     p.finfo.push_back(FrameInfo{d.H, d.W, off, d.n_prev});
     off += d.H * d.W;
-    p.T = std::max(p.T, steps_of(d.H, d.W, x.s));
+    const int T = steps_of(d.H, d.W, x.s);
+    p.T = std::max(p.T, T);
+    p.steps_cap += T;
+    int mf = 0;
+    for (int t = 0; t < T; ++t) mf = std::max(mf, diag_len(d.H, d.W, x.s, t));
+    p.rows_cap += mf;
     p.any_p = p.any_p || d.n_prev > 0;
   }
   p.HWt = off;
-  p.row_start.assign(p.T + 1, 0);
   for (int t = 0; t < p.T; ++t) {
     int cnt = 0;
-    for (int f = 0; f < n; ++f) {
-      const FrameInfo& fi = p.finfo[f];
-      for (int i = 0; i < fi.H; ++i) {
-        const int j = t - x.s * i;
-        if (j < 0 || j >= fi.W) continue;
-        ++cnt;
-        if (tables) {
-          p.gpos.push_back(fi.off + i * fi.W + j);
-          p.fid.push_back(f);
-        }
-      }
-    }
-    p.row_start[t + 1] = p.row_start[t] + cnt;
+    for (int f = 0; f < n; ++f) cnt += diag_len(fr[f].frame.H, fr[f].frame.W, x.s, t);
     p.Mmax = std::max(p.Mmax, cnt);
   }
   return p;
@@ -108,7 +122,6 @@ void lay_out(const NetDims& x, const Plan& p, int n, void* base, pswa_batch* b) 
   Layout L(base);
   const size_t HWt = p.HWt;
   b->d_frames = L.take<FrameInfo>(n);
-  b->row_start = L.take<int>(p.T + 1);
   b->gpos_all = L.take<int>(HWt);
   b->fid_all = L.take<int>(HWt);
   b->h = L.take<float>(HWt * x.d);
@@ -123,12 +136,15 @@ void lay_out(const NetDims& x, const Plan& p, int n, void* base, pswa_batch* b) 
   b->bits = L.take<float>(HWt * x.C);
   b->center = L.take<int32_t>(HWt * x.C);
   b->index = L.take<uint16_t>(HWt * x.C);
-  b->a = take_acts(L, x, std::max(p.Mmax, 1));
+  b->a = take_acts(L, x, std::max<size_t>(p.rows_cap, 1));
   b->ctl = L.take<int>(64);
+  b->bars = L.take<int>((size_t)n * kBarStride);
+  b->d_groups = L.take<GroupInfo>(n);
+  b->block_map = L.take<int>(kMaxBlocks);
   b->sum = L.take<float>(64);
-  b->gtab = L.take<GemmArgs>((size_t)p.T * gemm_phases(x.L));
-  b->atab = L.take<AttnArgs>((size_t)p.T * attn_phases(x.L));
-  b->stab = L.take<SymArgs>(p.T);
+  b->gtab = L.take<GemmArgs>(p.steps_cap * gemm_phases(x.L));
+  b->atab = L.take<AttnArgs>(p.steps_cap * attn_phases(x.L));
+  b->stab = L.take<SymArgs>(p.steps_cap);
   b->bytes = L.used;
 }
 
@@ -149,12 +165,13 @@ pswa_status check_frames(const pswa_model* m, int n, const pswa_batch_frame* fr)
   return PSWA_OK;
 }
 
-// Buffers of the batch as a pass context (M, gpos and fid set per step).
-PassCtx batch_ctx(const pswa_batch* b) {
+// Buffers of the batch as a pass context for one group (M, gpos and fid
+// are set per step); the group's activations start at its first row.
+PassCtx batch_ctx(const pswa_batch* b, const GroupPlan& g) {
   const NetDims& x = b->model->x;
   PassCtx c{};
   c.frames = b->d_frames;
-  c.frame0 = b->finfo[0];
+  c.frame0 = b->finfo[g.frames[0]];
   c.HWt = b->HWt;
   c.h = b->h;
   c.acc_kv = b->acc_kv;
@@ -162,7 +179,13 @@ PassCtx batch_ctx(const pswa_batch* b) {
   c.kv_stride = (size_t)b->HWt * 2 * x.d;
   c.tkv = b->any_p ? b->tkv : nullptr;
   c.tkv_stride = (size_t)2 * b->HWt * 2 * x.d;
-  c.x = b->a.x; c.q = b->a.q; c.att = b->a.att; c.e = b->a.e; c.t1 = b->a.t1; c.hmid = b->a.hmid;
+  const size_t r = g.row_off;
+  c.x = b->a.x + r * x.d;
+  c.q = b->a.q + r * x.d;
+  c.att = b->a.att + r * x.d;
+  c.e = b->a.e + r * x.d;
+  c.t1 = b->a.t1 + r * x.d;
+  c.hmid = b->a.hmid + r * x.F;
   c.mean = b->mean; c.scale = b->scale; c.bits = b->bits;
   c.center = b->center; c.index = b->index;
   c.center_c = nullptr; c.index_c = nullptr;
@@ -173,20 +196,17 @@ PassCtx batch_ctx(const pswa_batch* b) {
   return c;
 }
 
-// Argument tables of every step and phase, in the kernel's order.
-void build_tables(const pswa_batch* b, const std::vector<int>& row_start,
-                  std::vector<GemmArgs>* gt, std::vector<AttnArgs>* at, std::vector<SymArgs>* stb) {
+// Argument tables of one group's steps and phases, in the kernel's order.
+void build_tables(const pswa_batch* b, const GroupPlan& g, std::vector<GemmArgs>* gt,
+                  std::vector<AttnArgs>* at, std::vector<SymArgs>* stb) {
   const NetDims& x = b->model->x;
   const DevWeights& w = b->model->w;
-  const PassCtx base = batch_ctx(b);
-  gt->clear();
-  at->clear();
-  stb->clear();
-  for (int t = 0; t < b->T; ++t) {
+  const PassCtx base = batch_ctx(b, g);
+  for (int t = 0; t < g.T; ++t) {
     PassCtx c = base;
-    c.M = row_start[t + 1] - row_start[t];
-    c.gpos = b->gpos_all + row_start[t];
-    c.fid = b->fid_all + row_start[t];
+    c.M = g.row_start[t + 1] - g.row_start[t];
+    c.gpos = b->gpos_all + g.pos_off + g.row_start[t];
+    c.fid = b->fid_all + g.pos_off + g.row_start[t];
     gt->push_back(args_acc_q(x, w, c));
     gt->push_back(args_acc_o(x, w, c));
     at->push_back(args_acc_attn(x, w, c));
@@ -208,19 +228,121 @@ void build_tables(const pswa_batch* b, const std::vector<int>& row_start,
 
 PersistArgs persist_args(const pswa_batch* b) {
   PersistArgs P{};
-  P.gtab = b->gtab;
-  P.atab = b->atab;
-  P.stab = b->stab;
-  P.T = b->T;
+  P.groups = b->d_groups;
+  P.block_map = b->block_map;
   P.L = b->model->x.L;
   P.t_begin = 0;
   P.t_end = b->T;
-  P.bar = reinterpret_cast<unsigned*>(b->ctl);
   P.abort_flag = b->ctl + 1;
   P.spin_limit = b->spin_limit;
   P.trace = b->trace;
   P.trace_len = b->trace_len;
   return P;
+}
+
+// Any change to the launch configuration invalidates a captured graph.
+void drop_graph(pswa_batch* b) {
+  if (b->graph) {
+    (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+  }
+}
+
+void count_work(pswa_batch* b, const std::vector<GemmArgs>& gt,
+                const std::vector<AttnArgs>& at, const std::vector<SymArgs>& stb);
+
+// Split the frames into groups of at most fpg frames (frames with the most
+// steps spread first, so groups get similar work), give each group bpg
+// blocks, and rebuild and upload every row and argument table. Blocks are
+// numbered across the XCDs in dispatch order (block b runs on XCD b mod 8),
+// so a group's blocks sit on as few XCDs as possible. Waits for the upload.
+pswa_status apply_groups(pswa_batch* b, int fpg, int bpg, hipStream_t st) {
+  const NetDims& x = b->model->x;
+  const int n = (int)b->finfo.size();
+  if (fpg < 1 || bpg < 1) return fail(PSWA_E_ARG, "frames and blocks per group must be >= 1");
+  fpg = std::min(fpg, n);
+  const int ng = (n + fpg - 1) / fpg;
+  if ((long)ng * bpg > b->max_grid || (long)ng * bpg > kMaxBlocks)
+    return fail(PSWA_E_ARG, "%d groups of %d blocks exceed the co-resident limit %d", ng, bpg,
+                b->max_grid);
+  std::vector<int> order(n);
+  for (int f = 0; f < n; ++f) order[f] = f;
+  std::stable_sort(order.begin(), order.end(), [&](int u, int v) {
+    return b->finfo[u].H * b->finfo[u].W > b->finfo[v].H * b->finfo[v].W;
+  });
+  std::vector<GroupPlan> groups(ng);
+  for (int k = 0; k < n; ++k) groups[k % ng].frames.push_back(order[k]);
+  std::vector<int> gpos, fid;
+  size_t row_off = 0, tab_off = 0;
+  for (GroupPlan& g : groups) {
+    std::sort(g.frames.begin(), g.frames.end());
+    for (int f : g.frames) g.T = std::max(g.T, steps_of(b->finfo[f].H, b->finfo[f].W, x.s));
+    g.row_off = row_off;
+    g.tab_off = tab_off;
+    g.pos_off = gpos.size();
+    g.row_start.assign(g.T + 1, 0);
+    for (int t = 0; t < g.T; ++t) {
+      int cnt = 0;
+      for (int f : g.frames) {
+        const FrameInfo& fi = b->finfo[f];
+        for (int i = 0; i < fi.H; ++i) {
+          const int j = t - x.s * i;
+          if (j < 0 || j >= fi.W) continue;
+          gpos.push_back(fi.off + i * fi.W + j);
+          fid.push_back(f);
+          ++cnt;
+        }
+      }
+      g.row_start[t + 1] = g.row_start[t] + cnt;
+      g.Mmax = std::max(g.Mmax, cnt);
+    }
+    row_off += g.Mmax;
+    tab_off += g.T;
+  }
+  if (row_off > b->rows_cap || tab_off > b->steps_cap || gpos.size() != (size_t)b->HWt)
+    return fail(PSWA_E_ARG, "internal: grouping exceeds its workspace");
+  std::vector<GemmArgs> gt;
+  std::vector<AttnArgs> at;
+  std::vector<SymArgs> stb;
+  std::vector<GroupInfo> gi(ng);
+  const int na = attn_phases(x.L), ngm = gemm_phases(x.L);
+  for (int k = 0; k < ng; ++k) {
+    const GroupPlan& g = groups[k];
+    build_tables(b, g, &gt, &at, &stb);
+    gi[k].gtab = b->gtab + g.tab_off * ngm;
+    gi[k].atab = b->atab + g.tab_off * na;
+    gi[k].stab = b->stab + g.tab_off;
+    gi[k].T = g.T;
+    gi[k].nblocks = bpg;
+    gi[k].bar = reinterpret_cast<unsigned*>(b->bars + (size_t)k * kBarStride);
+  }
+  const int grid = ng * bpg;
+  std::vector<int> bmap(grid), xcd_order;
+  for (int xc = 0; xc < 8; ++xc)
+    for (int blk = xc; blk < grid; blk += 8) xcd_order.push_back(blk);
+  for (int p = 0; p < grid; ++p) bmap[xcd_order[p]] = ((p / bpg) << 16) | (p % bpg);
+  PSWA_HIP_TRY(hipMemcpyAsync(b->gpos_all, gpos.data(), gpos.size() * sizeof(int),
+                              hipMemcpyHostToDevice, st));
+  PSWA_HIP_TRY(hipMemcpyAsync(b->fid_all, fid.data(), fid.size() * sizeof(int),
+                              hipMemcpyHostToDevice, st));
+  PSWA_HIP_TRY(hipMemcpyAsync(b->gtab, gt.data(), gt.size() * sizeof(GemmArgs),
+                              hipMemcpyHostToDevice, st));
+  PSWA_HIP_TRY(hipMemcpyAsync(b->atab, at.data(), at.size() * sizeof(AttnArgs),
+                              hipMemcpyHostToDevice, st));
+  PSWA_HIP_TRY(hipMemcpyAsync(b->stab, stb.data(), stb.size() * sizeof(SymArgs),
+                              hipMemcpyHostToDevice, st));
+  PSWA_HIP_TRY(hipMemcpyAsync(b->d_groups, gi.data(), gi.size() * sizeof(GroupInfo),
+                              hipMemcpyHostToDevice, st));
+  PSWA_HIP_TRY(hipMemcpyAsync(b->block_map, bmap.data(), bmap.size() * sizeof(int),
+                              hipMemcpyHostToDevice, st));
+  PSWA_HIP_TRY(hipStreamSynchronize(st));
+  b->groups = std::move(groups);
+  b->fpg = fpg;
+  b->bpg = bpg;
+  b->grid = grid;
+  count_work(b, gt, at, stb);
+  drop_graph(b);
+  return PSWA_OK;
 }
 
 pswa_status run(pswa_batch* b, hipStream_t st) {
@@ -231,6 +353,7 @@ pswa_status run(pswa_batch* b, hipStream_t st) {
   const pswa_model* m = b->model;
   const NetDims& x = m->x;
   zero_ints(b->ctl, 3, st);
+  zero_ints(b->bars, (int)b->groups.size() * kBarStride, st);
   for (size_t f = 0; f < b->frames.size(); ++f) {
     const pswa_batch_frame& fr = b->frames[f];
     const FrameInfo& fi = b->finfo[f];
@@ -253,14 +376,6 @@ pswa_status run(pswa_batch* b, hipStream_t st) {
   return PSWA_OK;
 }
 
-// Any change to the launch configuration invalidates a captured graph.
-void drop_graph(pswa_batch* b) {
-  if (b->graph) {
-    (void)hipGraphExecDestroy(b->graph);
-    b->graph = nullptr;
-  }
-}
-
 // Algorithmic bytes and flops of one persistent launch: the per-phase
 // figures of the per-launch path (weights once per phase, activations in and
 // out, every window slot's K and V rows) summed over every step.
@@ -270,7 +385,7 @@ void count_work(pswa_batch* b, const std::vector<GemmArgs>& gt,
   const int ng = gemm_phases(x.L), na = attn_phases(x.L);
   static const Epi epis_head[4] = {EPI_SILU, EPI_HEAD, EPI_STORE, EPI_STORE};
   double by = 0, fl = 0;
-  for (int t = 0; t < b->T; ++t) {
+  for (size_t t = 0; t < stb.size(); ++t) {
     if (stb[t].M == 0) continue;
     for (int k = 0; k < ng; ++k) {
       const GemmArgs& a = gt[(size_t)t * ng + k];
@@ -306,7 +421,7 @@ extern "C" {
 
 size_t pswa_batch_workspace_bytes(const pswa_model* model, int n, const pswa_batch_frame* frames) {
   if (check_frames(model, n, frames) != PSWA_OK) return 0;
-  Plan p = make_plan(model->x, n, frames, false);
+  Plan p = make_plan(model->x, n, frames);
   pswa_batch tmp;
   lay_out(model->x, p, n, nullptr, &tmp);
   return tmp.bytes;
@@ -321,7 +436,7 @@ pswa_status pswa_batch_create(const pswa_model* model, int n, const pswa_batch_f
   if (cs != PSWA_OK) return cs;
   if (!d_ws || (reinterpret_cast<uintptr_t>(d_ws) % kAlign) != 0)
     return fail(PSWA_E_ARG, "workspace must be non-null and 256-byte aligned");
-  Plan p = make_plan(model->x, n, frames, true);
+  Plan p = make_plan(model->x, n, frames);
   std::unique_ptr<pswa_batch> b(new pswa_batch);
   lay_out(model->x, p, n, d_ws, b.get());
   if (ws_bytes < b->bytes) return fail(PSWA_E_ARG, "workspace %zu bytes < %zu", ws_bytes, b->bytes);
@@ -331,31 +446,26 @@ pswa_status pswa_batch_create(const pswa_model* model, int n, const pswa_batch_f
   b->HWt = p.HWt;
   b->T = p.T;
   b->Mmax = p.Mmax;
+  b->rows_cap = p.rows_cap;
+  b->steps_cap = p.steps_cap;
   b->any_p = p.any_p;
-  b->max_grid = persistent_max_grid(model->x, model->w.prec);
+  b->max_grid = std::min(persistent_max_grid(model->x, model->w.prec), kMaxBlocks);
   if (b->max_grid <= 0) return fail(PSWA_E_HIP, "cannot size the persistent grid");
-  b->grid = grid > 0 ? std::min(grid, b->max_grid) : std::min(b->max_grid, kDefaultGrid);
   hipStream_t st = static_cast<hipStream_t>(stream);
   PSWA_HIP_TRY(hipMemcpyAsync(b->d_frames, p.finfo.data(), n * sizeof(FrameInfo),
                               hipMemcpyHostToDevice, st));
-  PSWA_HIP_TRY(hipMemcpyAsync(b->row_start, p.row_start.data(), (p.T + 1) * sizeof(int),
-                              hipMemcpyHostToDevice, st));
-  PSWA_HIP_TRY(hipMemcpyAsync(b->gpos_all, p.gpos.data(), p.gpos.size() * sizeof(int),
-                              hipMemcpyHostToDevice, st));
-  PSWA_HIP_TRY(hipMemcpyAsync(b->fid_all, p.fid.data(), p.fid.size() * sizeof(int),
-                              hipMemcpyHostToDevice, st));
-  std::vector<GemmArgs> gt;
-  std::vector<AttnArgs> at;
-  std::vector<SymArgs> stb;
-  build_tables(b.get(), p.row_start, &gt, &at, &stb);
-  PSWA_HIP_TRY(hipMemcpyAsync(b->gtab, gt.data(), gt.size() * sizeof(GemmArgs),
-                              hipMemcpyHostToDevice, st));
-  PSWA_HIP_TRY(hipMemcpyAsync(b->atab, at.data(), at.size() * sizeof(AttnArgs),
-                              hipMemcpyHostToDevice, st));
-  PSWA_HIP_TRY(hipMemcpyAsync(b->stab, stb.data(), stb.size() * sizeof(SymArgs),
-                              hipMemcpyHostToDevice, st));
-  PSWA_HIP_TRY(hipStreamSynchronize(st));
-  count_work(b.get(), gt, at, stb);
+  int fpg, bpg;
+  if (grid > 0) {  // one group of `grid` blocks
+    fpg = n;
+    bpg = std::min(grid, b->max_grid);
+  } else {         // about 8 to 32 blocks per group, as many groups as fit
+    bpg = 8;
+    while (bpg < 32 && (long)n * bpg * 2 <= b->max_grid) bpg *= 2;
+    const int ng = std::max(1, std::min(n, b->max_grid / bpg));
+    fpg = (n + ng - 1) / ng;
+  }
+  const pswa_status gs = apply_groups(b.get(), fpg, bpg, st);
+  if (gs != PSWA_OK) return gs;
   *out = b.release();
   return PSWA_OK;
 }
@@ -369,8 +479,21 @@ pswa_status pswa_batch_set_grid(pswa_batch* b, int grid) {
   if (!b) return fail(PSWA_E_ARG, "batch is null");
   if (grid < 1 || grid > b->max_grid)
     return fail(PSWA_E_ARG, "grid %d outside [1, %d]", grid, b->max_grid);
-  b->grid = grid;
-  drop_graph(b);
+  return apply_groups(b, (int)b->finfo.size(), grid, nullptr);
+}
+
+pswa_status pswa_batch_set_groups(pswa_batch* b, int frames_per_group, int blocks_per_group,
+                                  void* stream) {
+  if (!b) return fail(PSWA_E_ARG, "batch is null");
+  return apply_groups(b, frames_per_group, blocks_per_group, static_cast<hipStream_t>(stream));
+}
+
+pswa_status pswa_batch_groups(const pswa_batch* b, int* frames_per_group, int* blocks_per_group,
+                              int* n_groups) {
+  if (!b) return fail(PSWA_E_ARG, "batch is null");
+  if (frames_per_group) *frames_per_group = b->fpg;
+  if (blocks_per_group) *blocks_per_group = b->bpg;
+  if (n_groups) *n_groups = (int)b->groups.size();
   return PSWA_OK;
 }
 
@@ -413,11 +536,12 @@ pswa_status pswa_batch_capture(pswa_batch* b, void* stream) {
 }
 
 pswa_status pswa_batch_autotune(pswa_batch* b, const char* cache_path, int reps, void* stream,
-                                int* out_grid, int* out_rtile, float* out_ms) {
-  if (!b || !out_grid || !out_rtile || !out_ms) return fail(PSWA_E_ARG, "null argument");
+                                int* out_fpg, int* out_bpg, int* out_rtile, float* out_ms) {
+  if (!b || !out_fpg || !out_bpg || !out_rtile || !out_ms) return fail(PSWA_E_ARG, "null argument");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const pswa_model* m = b->model;
   const NetDims& x = m->x;
+  const int n = (int)b->finfo.size();
   // cache key: device, model shape and precision, frame mix
   int dev = 0;
   hipDeviceProp_t prop;
@@ -430,74 +554,101 @@ pswa_status pswa_batch_autotune(pswa_batch* b, const char* cache_path, int reps,
   if (cache_path) {
     std::ifstream in(cache_path);
     std::string line;
+    const std::string k = "{\"key\": \"" + key.str() + "\"";
     while (std::getline(in, line)) {
-      const std::string k = "{\"key\": \"" + key.str() + "\"";
       if (line.compare(0, k.size(), k) != 0) continue;
-      int g = 0, r = 0;
+      int f = 0, g = 0, r = 0;
       float ms = 0;
-      if (std::sscanf(line.c_str() + k.size(), ", \"grid\": %d, \"rtile\": %d, \"ms\": %f", &g,
-                      &r, &ms) == 3 &&
-          g >= 1 && g <= b->max_grid && (r == 16 || r == 32)) {
-        b->grid = g;
+      if (std::sscanf(line.c_str() + k.size(),
+                      ", \"frames_per_group\": %d, \"blocks_per_group\": %d, \"rtile\": %d, "
+                      "\"ms\": %f", &f, &g, &r, &ms) == 4 &&
+          (r == 16 || r == 32) && (r == 32 || m->w.prec)) {
+        const pswa_status s2 = apply_groups(b, f, g, st);
+        if (s2 != PSWA_OK) continue;  // a stale entry (another device limit): retune
         b->rtile = r;
-        *out_grid = g;
+        *out_fpg = b->fpg;
+        *out_bpg = b->bpg;
         *out_rtile = r;
         *out_ms = ms;
         return PSWA_OK;
       }
     }
   }
-  // time a window of the widest global steps
+  // time a window of the widest global steps for each candidate
   const int w = std::min(b->T, 24);
   const int t0 = std::max(0, b->T / 2 - w / 2);
-  std::vector<int> grids;
-  for (int g : {16, 24, 32, 48, 64, 96, 128, 192, 256})
-    if (g <= b->max_grid) grids.push_back(g);
-  std::vector<int> rtiles = m->w.prec ? std::vector<int>{16, 32} : std::vector<int>{32};
   hipEvent_t e0, e1;
   PSWA_HIP_TRY(hipEventCreate(&e0));
   PSWA_HIP_TRY(hipEventCreate(&e1));
+  auto time_it = [&](int r, float* med) -> pswa_status {
+    PersistArgs P = persist_args(b);
+    P.t_begin = t0;
+    P.t_end = t0 + w;
+    P.trace = nullptr;
+    std::vector<float> t;
+    for (int i = 0; i <= std::max(1, reps); ++i) {
+      zero_ints(b->ctl, 3, st);
+      zero_ints(b->bars, (int)b->groups.size() * kBarStride, st);
+      PSWA_HIP_TRY(hipEventRecord(e0, st));
+      launch_persistent(P, x, m->w.prec, r, b->grid, st);
+      PSWA_HIP_TRY(hipEventRecord(e1, st));
+      PSWA_HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0;
+      PSWA_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (i > 0) t.push_back(ms);  // the first run warms up
+    }
+    int ab = 0;
+    PSWA_HIP_TRY(hipMemcpy(&ab, b->ctl + 1, sizeof ab, hipMemcpyDeviceToHost));
+    std::sort(t.begin(), t.end());
+    *med = ab ? 1e30f : t[t.size() / 2];
+    return PSWA_OK;
+  };
+  // (frames per group, blocks per group): powers of two (and all frames),
+  // using at least a sixteenth of the co-resident blocks
+  std::vector<int> fpgs;
+  for (int f = 1; f < n; f *= 2) fpgs.push_back(f);
+  fpgs.push_back(n);
   float best = 1e30f;
-  int bg = b->grid, br = b->rtile;
-  for (int r : rtiles)
-    for (int g : grids) {
-      PersistArgs P = persist_args(b);
-      P.t_begin = t0;
-      P.t_end = t0 + w;
-      P.trace = nullptr;
-      std::vector<float> t;
-      for (int i = 0; i <= std::max(1, reps); ++i) {
-        zero_ints(b->ctl, 2, st);
-        PSWA_HIP_TRY(hipEventRecord(e0, st));
-        launch_persistent(P, x, m->w.prec, r, g, st);
-        PSWA_HIP_TRY(hipEventRecord(e1, st));
-        PSWA_HIP_TRY(hipEventSynchronize(e1));
-        float ms = 0;
-        PSWA_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-        if (i > 0) t.push_back(ms);  // the first run warms up
-      }
-      int ab = 0;
-      PSWA_HIP_TRY(hipMemcpy(&ab, b->ctl + 1, sizeof ab, hipMemcpyDeviceToHost));
-      std::sort(t.begin(), t.end());
-      const float med = t[t.size() / 2];
-      if (!ab && med < best) {
+  int bf = b->fpg, bb = b->bpg, br = 32;
+  for (int f : fpgs)
+    for (int g = 2; g <= b->max_grid; g *= 2) {
+      const int ng = (n + f - 1) / f;
+      if ((long)ng * g > b->max_grid || ng * g < std::min(16, b->max_grid / 16)) continue;
+      if (apply_groups(b, f, g, st) != PSWA_OK) continue;
+      float med = 0;
+      const pswa_status ts = time_it(32, &med);
+      if (ts != PSWA_OK) return ts;
+      if (med < best) {
         best = med;
-        bg = g;
-        br = r;
+        bf = f;
+        bb = g;
       }
     }
+  pswa_status gs = apply_groups(b, bf, bb, st);
+  if (gs != PSWA_OK) return gs;
+  if (m->w.prec != PSWA_PREC_F32) {
+    float med = 0;
+    const pswa_status ts = time_it(16, &med);
+    if (ts != PSWA_OK) return ts;
+    if (med < best) {
+      best = med;
+      br = 16;
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  b->grid = bg;
+  if (best >= 1e30f) return fail(PSWA_E_HIP, "autotune: every candidate aborted");
   b->rtile = br;
   drop_graph(b);
-  *out_grid = bg;
+  *out_fpg = bf;
+  *out_bpg = bb;
   *out_rtile = br;
   *out_ms = best * float(b->T) / float(w);  // whole-run estimate
   if (cache_path) {
     std::ofstream o(cache_path, std::ios::app);
-    o << "{\"key\": \"" << key.str() << "\", \"grid\": " << bg << ", \"rtile\": " << br
-      << ", \"ms\": " << *out_ms << "}\n";
+    o << "{\"key\": \"" << key.str() << "\", \"frames_per_group\": " << bf
+      << ", \"blocks_per_group\": " << bb << ", \"rtile\": " << br << ", \"ms\": " << *out_ms
+      << "}\n";
   }
   return PSWA_OK;
 }

@@ -38,18 +38,26 @@ __global__ void __launch_bounds__(kThreads) k_attn(AttnArgs a) {
                 reinterpret_cast<float*>(smem4));
 }
 
+// One block per hyperprior cell: W_h z is shared by the cell's (up to) 4x4
+// positions, which differ only in their sub-position embedding.
 __global__ void k_hyper_embed(const int32_t* z, int Hh, int Wh, int Ch, const float* Wm,
                               const float* P4, int H, int W, int d, float* h) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long)H * W * d) return;
-  const int n = idx % d;
-  const int p = idx / d;
-  const int i = p / W, j = p % W;
-  const int32_t* zr = z + ((size_t)(i / 4) * Wh + (j / 4)) * Ch;
-  const float* wr = Wm + (size_t)n * Ch;
-  float acc = 0.f;
-  for (int k = 0; k < Ch; ++k) acc = fmaf(float(zr[k]), wr[k], acc);
-  h[idx] = acc + P4[((i % 4) * 4 + (j % 4)) * d + n];
+  const int ci = blockIdx.x / Wh, cj = blockIdx.x % Wh;
+  const int32_t* zr = z + (size_t)blockIdx.x * Ch;
+  for (int n = threadIdx.x; n < d; n += blockDim.x) {
+    const float* wr = Wm + (size_t)n * Ch;
+    float acc = 0.f;
+    for (int k = 0; k < Ch; ++k) acc = fmaf(float(zr[k]), wr[k], acc);
+    for (int a = 0; a < 4; ++a) {
+      const int i = 4 * ci + a;
+      if (i >= H) break;
+      for (int b = 0; b < 4; ++b) {
+        const int j = 4 * cj + b;
+        if (j >= W) break;
+        h[((size_t)i * W + j) * d + n] = acc + P4[(a * 4 + b) * d + n];
+      }
+    }
+  }
 }
 
 __global__ void k_gather_symbols(const int32_t* src, int compact, const int* pos, int M, int C,
@@ -214,11 +222,11 @@ void attention_f32(const AttnArgs& a, hipStream_t s) {
 void hyper_embed(const int32_t* z, int Hh, int Wh, int Ch, const float* Wm, const float* P4,
                  int H, int W, int d, float* h, hipStream_t s) {
   const int ev = prof_begin(s);
-  hipLaunchKernelGGL(k_hyper_embed, dim3(blocks_for((long)H * W * d, 256)), dim3(256), 0, s, z,
-                     Hh, Wh, Ch, Wm, P4, H, W, d, h);
+  hipLaunchKernelGGL(k_hyper_embed, dim3(Hh * Wh), dim3(256), 0, s, z, Hh, Wh, Ch, Wm, P4, H,
+                     W, d, h);
   prof_end(ev, s, R_HYPER,
            4.0 * (double(Hh) * Wh * Ch + double(d) * Ch + 16.0 * d + double(H) * W * d),
-           2.0 * H * W * d * Ch);
+           2.0 * Hh * Wh * d * Ch);
 }
 
 void gather_symbols(const int32_t* src, int compact, const int* pos, int M, int C,

@@ -17,25 +17,38 @@ struct SymArgs {
   float* bits;
 };
 
-// Per global step t the kernel runs, in order (g = GEMM table entry, a =
-// attention table entry; every phase ends with a grid barrier):
+// Frames of a batch are split into groups, each served by its own set of
+// blocks: a group walks the global steps of its frames (the union of their
+// diagonals) and its blocks meet at the group's own barrier between
+// dependent phases. Frames never read each other's data, so groups never
+// wait for one another.
+//
+// Per step t a group runs, in order (g = GEMM table entry, a = attention
+// table entry; every phase ends with the group barrier):
 //   g0 acc q, a0 acc attention, g1 acc O,
 //   per layer l: g(2+4l) QKV, a(1+l) attention, g(3+4l) O, g(4+4l) gate/up,
 //                g(5+4l) down,
 //   g(2+4L) head W1, g(3+4L) head W2, symbols, g(4+4L) embed, g(5+4L) acc K/V.
-// The argument tables are built on the host for every step and phase and
-// read by the kernel from device memory (uniform loads), so no argument
+// The argument tables are built on the host for every group, step and phase
+// and read by the kernel from device memory (uniform loads), so no argument
 // structure is ever built in per-lane memory.
-struct PersistArgs {
+struct GroupInfo {
   const GemmArgs* gtab;    // [T][6 + 4L]
   const AttnArgs* atab;    // [T][1 + L]
   const SymArgs* stab;     // [T]
-  int T, L;
+  int T;                   // steps of the group's frames
+  int nblocks;             // blocks serving the group
+  unsigned* bar;           // the group's barrier arrivals (zeroed before each launch)
+};
+
+struct PersistArgs {
+  const GroupInfo* groups;
+  const int* block_map;    // [grid]: (group << 16) | rank of the block in its group
+  int L;
   int t_begin, t_end;      // global steps run by this launch (0, T for a decode)
-  unsigned* bar;           // barrier arrivals (zeroed before each launch)
   int* abort_flag;         // set when a barrier wait exceeds spin_limit
   long spin_limit;
-  long long* trace;        // optional: wall clock after each barrier (block 0)
+  long long* trace;        // optional: wall clock after each barrier (group 0, rank 0)
   int trace_len;
 };
 

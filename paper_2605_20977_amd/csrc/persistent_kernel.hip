@@ -1,18 +1,19 @@
-// Persistent wavefront decode kernel: one launch walks every diagonal of a batch of
-// frames (of any sizes, I and P mixed). At global step t the rows are the
-// union over frames of their diagonal t; each phase of the network (see
-// network.h) is spread over the grid's blocks as GEMM tiles or attention
-// items, and blocks meet at a grid barrier between dependent phases.
+// Persistent wavefront decode kernel: one launch walks every diagonal of a
+// batch of frames (of any sizes, I and P mixed). The frames are split into
+// groups, each served by its own blocks; at step t a group's rows are the
+// union of its frames' diagonal t, each phase of the network (see network.h)
+// is spread over the group's blocks as GEMM tiles or attention items, and the
+// group's blocks meet at the group's barrier between dependent phases.
 //
 // The barrier is a monotonic arrival counter in device memory: a block's
 // leader adds one arrival with release semantics (publishing the block's
 // writes) and spins with acquire loads, a bounded number of times, until
-// every block has arrived. Its cost grows with the number of blocks (about
-// 1 us at 16 blocks and 10 us at 256 on MI355X), so the grid is kept small
-// and tuned. If the
-// bound is ever exceeded (a block that is not co-resident, say), the leader
-// raises the abort flag; every block leaves at its next barrier, so the
-// kernel always drains and the host reports the abort.
+// every block of the group has arrived. Its cost grows with the number of
+// blocks that share it (about 1 us at 16 blocks and 10 us at 256 on MI355X),
+// which is why groups are kept small. If the bound is ever exceeded (a block
+// that is not co-resident, say), the leader raises the abort flag; every
+// block leaves at its next barrier, so the kernel always drains and the host
+// reports the abort.
 //
 // This file is compiled once per instance: PSWA_PREC, PSWA_DH and PSWA_R
 // name the projection arithmetic, head size and row-tile height, and the
@@ -34,11 +35,13 @@ using namespace dev;
 
 namespace {
 
-__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned& target, int* abort_flag, long spin_limit) {
+// Barrier of the nb blocks of one group.
+__device__ __forceinline__ bool group_barrier(unsigned* bar, unsigned& target, int nb,
+                                              int* abort_flag, long spin_limit) {
   __shared__ int s_ok;
   __syncthreads();
   if (threadIdx.x == 0) {
-    target += gridDim.x;
+    target += nb;
     // release: this block's writes become visible before its arrival counts
     __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     int ok = 1;
@@ -63,14 +66,15 @@ __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned& target, in
 }
 
 template <int AK, bool RMS, int EPI, int PREC, int R>
-__device__ __forceinline__ void gemm_phase(const GemmArgs& a, float4* smem4, float* rstd) {
+__device__ __forceinline__ void gemm_phase(const GemmArgs& a, float4* smem4, float* rstd,
+                                           int rank, int nb) {
   __shared__ float rmul[kMBq];
   if (PREC != PSWA_PREC_F32) {
     // tiles in row-tile-major order: a block re-stages A only when its next
     // tile starts a new row tile
     const int ct = qgemm_col_tiles(a.N, EPI), rt = qgemm_row_tiles(a.M, R);
     int staged = -1;
-    for (int t = blockIdx.x; t < ct * rt; t += gridDim.x) {
+    for (int t = rank; t < ct * rt; t += nb) {
       const int r = t / ct;
       gemm_tile_q<AK, RMS, EPI, PREC, R>(a, t % ct, r, reinterpret_cast<uint8_t*>(smem4), rstd,
                                          rmul, r != staged);
@@ -79,21 +83,20 @@ __device__ __forceinline__ void gemm_phase(const GemmArgs& a, float4* smem4, flo
     return;
   }
   const int ct = gemm_col_tiles(a.N, EPI), rt = gemm_row_tiles(a.M);
-  for (int t = blockIdx.x; t < ct * rt; t += gridDim.x)
+  for (int t = rank; t < ct * rt; t += nb)
     gemm_tile_any<AK, RMS, EPI>(a, t % ct, t / ct, smem4, rstd);
 }
 
 template <int DH>
-__device__ __forceinline__ void attn_phase(const AttnArgs& a, float* smem) {
+__device__ __forceinline__ void attn_phase(const AttnArgs& a, float* smem, int rank, int nb) {
   const int groups = (a.M * a.heads + kWaves - 1) / kWaves;
-  for (int g = blockIdx.x; g < groups; g += gridDim.x)
+  for (int g = rank; g < groups; g += nb)
     attn_item<DH>(a, g * kWaves + (threadIdx.x >> 6), true, smem);
 }
 
-__device__ __forceinline__ void symbol_phase(const SymArgs& c) {
+__device__ __forceinline__ void symbol_phase(const SymArgs& c, int rank, int nb) {
   const long n = (long)c.M * c.C;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (long)gridDim.x * blockDim.x) {
+  for (long i = (long)rank * blockDim.x + threadIdx.x; i < n; i += (long)nb * blockDim.x) {
     gather_item(c.ysrc, c.src_compact, c.gpos, c.C, c.ydec, i);
     bits_item(c.gpos, c.C, c.ydec, c.mean, c.scale, c.bits, i);
   }
@@ -107,48 +110,52 @@ __global__ void __launch_bounds__(kThreads) k_persistent(PersistArgs P) {
   extern __shared__ float4 smem4[];
   __shared__ float rstd[kMBq];
   float* smem = reinterpret_cast<float*>(smem4);
+  const int bm = P.block_map[blockIdx.x];
+  const GroupInfo& G = P.groups[bm >> 16];
+  const int rank = bm & 0xffff, nb = G.nblocks;
+  const bool tracer = P.trace && bm == 0 && threadIdx.x == 0;
   const int L = P.L, ng = 6 + 4 * L, na = 1 + L;
+  const int t_end = min(P.t_end, G.T);
   unsigned target = 0;
   int nsync = 0;
 #define PSWA_SYNC                                                                  \
-  if (!grid_barrier(P.bar, target, P.abort_flag, P.spin_limit)) return;            \
-  if (P.trace && blockIdx.x == 0 && threadIdx.x == 0 && nsync < P.trace_len)       \
-    P.trace[nsync] = wall_clock64();                                              \
+  if (!group_barrier(G.bar, target, nb, P.abort_flag, P.spin_limit)) return;      \
+  if (tracer && nsync < P.trace_len) P.trace[nsync] = wall_clock64();             \
   ++nsync;
 
-  for (int t = P.t_begin; t < P.t_end; ++t) {
-    const SymArgs& sy = P.stab[t];
-    if (sy.M == 0) continue;  // same for every block
-    const GemmArgs* g = P.gtab + (size_t)t * ng;
-    const AttnArgs* at = P.atab + (size_t)t * na;
+  for (int t = P.t_begin; t < t_end; ++t) {
+    const SymArgs& sy = G.stab[t];
+    if (sy.M == 0) continue;  // same for every block of the group
+    const GemmArgs* g = G.gtab + (size_t)t * ng;
+    const AttnArgs* at = G.atab + (size_t)t * na;
 
-    gemm_phase<A_FLOAT, true, EPI_STORE, PREC, R>(g[0], smem4, rstd);
+    gemm_phase<A_FLOAT, true, EPI_STORE, PREC, R>(g[0], smem4, rstd, rank, nb);
     PSWA_SYNC
-    attn_phase<DH>(at[0], smem);
+    attn_phase<DH>(at[0], smem, rank, nb);
     PSWA_SYNC
-    gemm_phase<A_FLOAT, false, EPI_RESID, PREC, R>(g[1], smem4, rstd);
+    gemm_phase<A_FLOAT, false, EPI_RESID, PREC, R>(g[1], smem4, rstd, rank, nb);
     PSWA_SYNC
     for (int l = 0; l < L; ++l) {
-      gemm_phase<A_FLOAT, true, EPI_QKV, PREC, R>(g[2 + 4 * l], smem4, rstd);
+      gemm_phase<A_FLOAT, true, EPI_QKV, PREC, R>(g[2 + 4 * l], smem4, rstd, rank, nb);
       PSWA_SYNC
-      attn_phase<DH>(at[1 + l], smem);
+      attn_phase<DH>(at[1 + l], smem, rank, nb);
       PSWA_SYNC
-      gemm_phase<A_FLOAT, false, EPI_RESID, PREC, R>(g[3 + 4 * l], smem4, rstd);
+      gemm_phase<A_FLOAT, false, EPI_RESID, PREC, R>(g[3 + 4 * l], smem4, rstd, rank, nb);
       PSWA_SYNC
-      gemm_phase<A_FLOAT, true, EPI_SWIGLU, PREC, R>(g[4 + 4 * l], smem4, rstd);
+      gemm_phase<A_FLOAT, true, EPI_SWIGLU, PREC, R>(g[4 + 4 * l], smem4, rstd, rank, nb);
       PSWA_SYNC
-      gemm_phase<A_FLOAT, false, EPI_RESID, PREC, R>(g[5 + 4 * l], smem4, rstd);
+      gemm_phase<A_FLOAT, false, EPI_RESID, PREC, R>(g[5 + 4 * l], smem4, rstd, rank, nb);
       PSWA_SYNC
     }
-    gemm_phase<A_FLOAT, true, EPI_SILU, PREC, R>(g[2 + 4 * L], smem4, rstd);
+    gemm_phase<A_FLOAT, true, EPI_SILU, PREC, R>(g[2 + 4 * L], smem4, rstd, rank, nb);
     PSWA_SYNC
-    gemm_phase<A_FLOAT, false, EPI_HEAD, PREC, R>(g[3 + 4 * L], smem4, rstd);
+    gemm_phase<A_FLOAT, false, EPI_HEAD, PREC, R>(g[3 + 4 * L], smem4, rstd, rank, nb);
     PSWA_SYNC
-    symbol_phase(sy);
+    symbol_phase(sy, rank, nb);
     PSWA_SYNC
-    gemm_phase<A_INT, false, EPI_STORE, PREC, R>(g[4 + 4 * L], smem4, rstd);
+    gemm_phase<A_INT, false, EPI_STORE, PREC, R>(g[4 + 4 * L], smem4, rstd, rank, nb);
     PSWA_SYNC
-    gemm_phase<A_FLOAT, true, EPI_STORE, PREC, R>(g[5 + 4 * L], smem4, rstd);
+    gemm_phase<A_FLOAT, true, EPI_STORE, PREC, R>(g[5 + 4 * L], smem4, rstd, rank, nb);
     PSWA_SYNC
   }
 #undef PSWA_SYNC

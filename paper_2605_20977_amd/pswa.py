@@ -88,7 +88,10 @@ def _load():
         "pswa_batch_trace": (i32, [vp, vp, i32]),
         "pswa_batch_set_rtile": (i32, [vp, i32]),
         "pswa_batch_rtile": (i32, [vp]),
-        "pswa_batch_autotune": (i32, [vp, C.c_char_p, i32, vp, P(i32), P(i32), P(C.c_float)]),
+        "pswa_batch_autotune": (i32, [vp, C.c_char_p, i32, vp, P(i32), P(i32), P(i32),
+                                      P(C.c_float)]),
+        "pswa_batch_set_groups": (i32, [vp, i32, i32, vp]),
+        "pswa_batch_groups": (i32, [vp, P(i32), P(i32), P(i32)]),
         "pswa_batch_capture": (i32, [vp, vp]),
         "pswa_batch_destroy": (None, [vp]),
         "pswa_quantize": (i32, [i32, vp, sz, vp, P(C.c_float)]),
@@ -116,7 +119,8 @@ EXPORTED = ("pswa_model_blob_floats", "pswa_model_device_bytes", "pswa_model_cre
             "pswa_batch_max_rows", "pswa_batch_grid", "pswa_batch_max_grid",
             "pswa_batch_set_grid", "pswa_batch_set_spin_limit", "pswa_batch_destroy",
             "pswa_quantize", "pswa_batch_trace", "pswa_batch_set_rtile", "pswa_batch_rtile",
-            "pswa_batch_autotune", "pswa_batch_capture")
+            "pswa_batch_autotune", "pswa_batch_capture", "pswa_batch_set_groups",
+            "pswa_batch_groups")
 
 
 def lib():
@@ -413,12 +417,25 @@ class Batch:
         _check(_lib.pswa_batch_set_rtile(self.handle, int(r)))
 
     def autotune(self, cache_path=None, reps=3):
-        """Pick (grid, row tile) by timing; returns (grid, rtile, est_ms)."""
-        g, r, ms = C.c_int(), C.c_int(), C.c_float()
+        """Pick the grouping and row tile by timing; returns (frames per
+        group, blocks per group, rtile, estimated ms per run)."""
+        f, g, r, ms = C.c_int(), C.c_int(), C.c_int(), C.c_float()
         _check(_lib.pswa_batch_autotune(self.handle,
                                         cache_path.encode() if cache_path else None, reps,
-                                        _stream(), C.byref(g), C.byref(r), C.byref(ms)))
-        return g.value, r.value, ms.value
+                                        _stream(), C.byref(f), C.byref(g), C.byref(r),
+                                        C.byref(ms)))
+        return f.value, g.value, r.value, ms.value
+
+    def set_groups(self, frames_per_group, blocks_per_group):
+        _check(_lib.pswa_batch_set_groups(self.handle, int(frames_per_group),
+                                          int(blocks_per_group), _stream()))
+
+    @property
+    def groups(self):
+        """(frames per group, blocks per group, number of groups)."""
+        f, g, n = C.c_int(), C.c_int(), C.c_int()
+        _check(_lib.pswa_batch_groups(self.handle, C.byref(f), C.byref(g), C.byref(n)))
+        return f.value, g.value, n.value
 
     def capture(self):
         """Record one run into a HIP graph; later run() calls replay it."""

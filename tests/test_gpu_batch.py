@@ -150,18 +150,41 @@ def test_batch_row_tile_and_autotune_keep_outputs(P, prec, tmp_path):
             for k in range(len(fr)):
                 _assert_same(b.outputs(k), ref[k], f"{prec} rtile {r} grid {g} frame {k}")
     cache = str(tmp_path / "tune.jsonl")
-    g1, r1, ms1 = b.autotune(cache, reps=2)
-    assert 1 <= g1 <= b.max_grid and r1 in (16, 32) and ms1 > 0
-    assert (b.grid, b.rtile) == (g1, r1)
+    f1, g1, r1, ms1 = b.autotune(cache, reps=2)
+    assert 1 <= f1 <= len(fr) and r1 in (16, 32) and ms1 > 0
+    ng = -(-len(fr) // f1)
+    assert 1 <= ng * g1 <= b.max_grid
+    assert b.groups == (f1, g1, ng) and b.rtile == r1
     lines = open(cache).read().splitlines()
-    assert len(lines) == 1 and f'"grid": {g1}' in lines[0]
+    assert len(lines) == 1 and f'"blocks_per_group": {g1}' in lines[0]
     b.set_grid(1)
-    g2, r2, ms2 = b.autotune(cache, reps=2)          # answered from the cache
-    assert (g2, r2) == (g1, r1) and len(open(cache).read().splitlines()) == 1
+    f2, g2, r2, ms2 = b.autotune(cache, reps=2)          # answered from the cache
+    assert (f2, g2, r2) == (f1, g1, r1) and len(open(cache).read().splitlines()) == 1
     b.run()
     b.check()
     for k in range(len(fr)):
         _assert_same(b.outputs(k), ref[k], f"{prec} autotuned frame {k}")
+
+
+def test_batch_groupings_keep_outputs(P, tiny):
+    """Frames split over groups with their own blocks and barriers decode
+    exactly as one group does."""
+    cfg, Wt, model = tiny
+    sizes = [(7, 9, 0), (16, 16, 2), (5, 13, 0), (12, 4, 2), (1, 1, 0), (3, 30, 2), (9, 9, 0)]
+    fr = _frames(cfg, sizes, 1200)
+    ref = [_per_frame(P, model, f) for f in fr]
+    b = P.Batch(model, fr)
+    for fpg, bpg in ((1, 1), (1, 4), (2, 8), (3, 2), (4, 16), (7, 5)):
+        print(f"case grouping {fpg} frames x {bpg} blocks", flush=True)
+        b.set_groups(fpg, bpg)
+        ng = -(-len(fr) // fpg)
+        assert b.groups == (fpg, bpg, ng) and b.grid == ng * bpg
+        b.run()
+        b.check()
+        for k in range(len(fr)):
+            _assert_same(b.outputs(k), ref[k], f"groups {fpg}x{bpg} frame {k}")
+    with pytest.raises(P.PswaError):
+        b.set_groups(1, b.max_grid)          # 7 groups of max_grid blocks cannot fit
 
 
 def test_batch_fp32_rejects_short_row_tile(P, tiny):
