@@ -11,5 +11,8 @@ Submodules:
              order-parameterised sequential form of the context model.
   entropy -- discretized-Gaussian likelihood, bits, integer CDF tables and
              the per-symbol table selection.
+  train   -- the student's distillation step: the same forward restated in
+             torch float64, loss, autograd gradients and AdamW (imported on
+             its own: `from oracle import train`).
 """
 from . import model, entropy  # noqa: F401
