@@ -266,6 +266,50 @@ pswa_status pswa_batch_set_spin_limit(pswa_batch* batch, int64_t spins);
 pswa_status pswa_batch_trace(pswa_batch* batch, int64_t* d_trace, int n);
 void pswa_batch_destroy(pswa_batch* batch);
 
+/* ------------------------------------------------ student distillation */
+
+/* Training of a (student) context model to reproduce another model's mean
+ * and log-scale: FP32, hand-written kernels, parallel form (teacher
+ * forcing). Loss = mean over symbols of (mu - mu_t)^2 + (lsig - lsig_t)^2,
+ * lsig the clamped log-scale (no gradient where the clamp is active);
+ * AdamW with beta1 0.9, beta2 0.999, eps 1e-8 and decoupled weight decay on
+ * the linear weights only. The trainer holds weights, gradients and moments
+ * in caller-owned device memory; crops are frames of their own (borders
+ * masked). */
+typedef struct pswa_trainer pswa_trainer;
+
+/* Workspace for batches of up to max_crops crops of H x W (0 if invalid;
+ * the model must be FP32 and max_crops * H * W <= 2^22). */
+size_t pswa_train_workspace_bytes(const pswa_model_desc* student, int max_crops, int H, int W);
+/* Initial weights from a host blob in the documented order (see
+ * pswa_model_create). Waits for the upload. */
+pswa_status pswa_train_create(const pswa_model_desc* student, const float* h_blob,
+                              size_t blob_floats, int max_crops, int H, int W, void* d_ws,
+                              size_t ws_bytes, void* stream, pswa_trainer** out);
+/* One step on B crops (B <= max_crops): device int32 latents [B][H][W][C],
+ * hyperpriors [B][ceil(H/4)][ceil(W/4)][Ch], previous latents
+ * [B][2][H][W][C] when n_prev = 2 (else NULL), and the targets mu_t and
+ * lsig_t [B][H][W][C] (float). Computes the loss and every gradient; with
+ * update != 0 also applies one AdamW step (lr, weight_decay). h_loss gets
+ * the loss. Waits. */
+pswa_status pswa_train_step(pswa_trainer* trainer, int B, int n_prev, const int32_t* d_latents,
+                            const int32_t* d_hyper, const int32_t* d_prev, const float* d_mu_t,
+                            const float* d_lsig_t, float lr, float weight_decay, int update,
+                            double* h_loss, void* stream);
+/* Copy the current weights (what = 0) or the last step's gradients
+ * (what = 1) into a host blob in the documented order. Waits. */
+pswa_status pswa_train_read(pswa_trainer* trainer, int what, float* h_blob, size_t blob_floats,
+                            void* stream);
+int pswa_train_num_steps(const pswa_trainer* trainer);  /* AdamW steps taken */
+void pswa_train_destroy(pswa_trainer* trainer);
+
+/* Per-frame fallback: 1 when a frame coded with the student (bits_student,
+ * from pswa_encode_params with the student model) stays within
+ * max_overhead (a fraction, e.g. 0.01) of the full model's bits, else 0 (code
+ * the frame with the full model; the choice is one flag in the stream). Any
+ * negative or NaN argument gives 0. */
+int pswa_student_accept(double bits_student, double bits_full, double max_overhead);
+
 /* ---------------------------------------------------------- entropy side */
 
 /* Table selection of n symbols from their mean and log-scale (float32

@@ -282,6 +282,15 @@ EncodeWs plan_encode(const NetDims& x, const pswa_frame_desc& f, void* base) {
 
 }  // namespace
 
+namespace pswa {
+bool model_desc_valid(const pswa_model_desc* d, std::string* why) { return valid_desc(d, why); }
+NetDims model_dims(const pswa_model_desc& d) { return dims_of(d); }
+size_t model_blob_spans(const NetDims& x, size_t align,
+                        std::vector<std::pair<size_t, size_t>>* spans) {
+  return blob_layout(x, nullptr, nullptr, align, spans);
+}
+}  // namespace pswa
+
 // ------------------------------------------------------------ decode state
 struct pswa_state {
   const pswa_model* model;

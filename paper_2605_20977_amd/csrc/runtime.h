@@ -44,6 +44,12 @@ struct Layout {
 };
 
 bool valid_frame(const pswa_frame_desc* f, std::string* why);
+bool model_desc_valid(const pswa_model_desc* d, std::string* why);
+NetDims model_dims(const pswa_model_desc& d);
+// (offset, floats) of every tensor of the weight blob, in blob order, each
+// tensor starting at a multiple of `align` floats; returns the total floats.
+size_t model_blob_spans(const NetDims& x, size_t align,
+                        std::vector<std::pair<size_t, size_t>>* spans);
 inline int steps_of(int H, int W, int s) { return (W - 1) + s * (H - 1) + 1; }
 int diag_len(int H, int W, int s, int t);
 

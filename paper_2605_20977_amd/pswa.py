@@ -91,6 +91,14 @@ def _load():
         "pswa_batch_autotune": (i32, [vp, C.c_char_p, i32, vp, P(i32), P(i32), P(i32),
                                       P(C.c_float)]),
         "pswa_batch_set_groups": (i32, [vp, i32, i32, vp]),
+        "pswa_train_workspace_bytes": (sz, [P(ModelDesc), i32, i32, i32]),
+        "pswa_train_create": (i32, [P(ModelDesc), vp, sz, i32, i32, i32, vp, sz, vp, P(vp)]),
+        "pswa_train_step": (i32, [vp, i32, i32, vp, vp, vp, vp, vp, C.c_float, C.c_float, i32,
+                                  P(C.c_double), vp]),
+        "pswa_train_read": (i32, [vp, i32, vp, sz, vp]),
+        "pswa_train_num_steps": (i32, [vp]),
+        "pswa_train_destroy": (None, [vp]),
+        "pswa_student_accept": (i32, [C.c_double, C.c_double, C.c_double]),
         "pswa_batch_groups": (i32, [vp, P(i32), P(i32), P(i32)]),
         "pswa_batch_capture": (i32, [vp, vp]),
         "pswa_batch_destroy": (None, [vp]),
@@ -120,7 +128,9 @@ EXPORTED = ("pswa_model_blob_floats", "pswa_model_device_bytes", "pswa_model_cre
             "pswa_batch_set_grid", "pswa_batch_set_spin_limit", "pswa_batch_destroy",
             "pswa_quantize", "pswa_batch_trace", "pswa_batch_set_rtile", "pswa_batch_rtile",
             "pswa_batch_autotune", "pswa_batch_capture", "pswa_batch_set_groups",
-            "pswa_batch_groups")
+            "pswa_batch_groups", "pswa_train_workspace_bytes", "pswa_train_create",
+            "pswa_train_step", "pswa_train_read", "pswa_train_num_steps", "pswa_train_destroy",
+            "pswa_student_accept")
 
 
 def lib():
@@ -157,21 +167,44 @@ def frame_desc(H, W, n_prev=0) -> FrameDesc:
     return FrameDesc(H, W, -(-H // 4), -(-W // 4), n_prev)
 
 
+def blob_shapes(cfg) -> list[tuple[str, tuple]]:
+    """(name, shape) of every parameter in the blob order the header
+    documents; linear weights are [out_features][in_features]."""
+    d, C, Ch, F, h, r = cfg.d, cfg.C, cfg.Ch, cfg.mlp_ratio * cfg.d, cfg.heads, (cfg.window - 1) // 2
+    n_acc = 2 * r * (r + 1)
+    n_lay = n_acc + 1 + 2 * (2 * r + 1) ** 2
+    out = [("hyper.W", (d, Ch)), ("hyper.P4", (16, d)), ("in.g", (C,)), ("in.W", (d, C)),
+           ("acc.gq", (d,)), ("acc.Wq", (d, d)), ("acc.gkv", (d,)), ("acc.Wkv", (2 * d, d)),
+           ("acc.knull", (d,)), ("acc.vnull", (d,)), ("acc.bias", (h, n_acc)),
+           ("acc.Wo", (d, d))]
+    for l in range(cfg.L):
+        p = f"layer{l}."
+        out += [(p + "g1", (d,)), (p + "Wqkv", (3 * d, d)), (p + "bias", (h, n_lay)),
+                (p + "Wo", (d, d)), (p + "g2", (d,)), (p + "Wgate", (F, d)),
+                (p + "Wup", (F, d)), (p + "Wdown", (d, F))]
+    out += [("head.g", (d,)), ("head.W1", (d, d)), ("head.W2", (2 * C, d)),
+            ("head.gmu", (C,)), ("head.bmu", (C,)), ("head.gsig", (C,)), ("head.bsig", (C,))]
+    return out
+
+
 def blob_order(cfg) -> list[str]:
     """Parameter names in the blob order the header documents."""
-    names = ["hyper.W", "hyper.P4", "in.g", "in.W", "acc.gq", "acc.Wq", "acc.gkv",
-             "acc.Wkv", "acc.knull", "acc.vnull", "acc.bias", "acc.Wo"]
-    for l in range(cfg.L):
-        names += [f"layer{l}.{n}" for n in
-                  ("g1", "Wqkv", "bias", "Wo", "g2", "Wgate", "Wup", "Wdown")]
-    names += ["head.g", "head.W1", "head.W2", "head.gmu", "head.bmu", "head.gsig",
-              "head.bsig"]
-    return names
+    return [n for n, _ in blob_shapes(cfg)]
 
 
 def pack_blob(cfg, weights) -> np.ndarray:
     return np.concatenate([np.asarray(weights[n], dtype=np.float32).ravel()
                            for n in blob_order(cfg)])
+
+
+def unpack_blob(cfg, blob) -> dict:
+    """Inverse of pack_blob: {name: float32 array of its shape}."""
+    out, off = {}, 0
+    for name, shape in blob_shapes(cfg):
+        n = int(np.prod(shape))
+        out[name] = np.asarray(blob[off:off + n], dtype=np.float32).reshape(shape).copy()
+        off += n
+    return out
 
 
 # ------------------------------------------------------------------- model
@@ -195,7 +228,7 @@ class Model:
         self.handle = h
 
     def close(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and _lib is not None:
             _lib.pswa_model_destroy(self.handle)
             self.handle = None
 
@@ -272,7 +305,7 @@ class State:
         self.T = _lib.pswa_num_steps(handle)
 
     def close(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and _lib is not None:
             _lib.pswa_state_destroy(self.handle)
             self.handle = None
 
@@ -470,7 +503,7 @@ class Batch:
         return out
 
     def close(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and _lib is not None:
             _lib.pswa_batch_destroy(self.handle)
             self.handle = None
 
@@ -570,3 +603,63 @@ def pswa_profile_read():
             out[name.value.decode()] = {"ms": ms.value, "launches": n.value,
                                         "bytes": by.value, "flops": fl.value}
     return out
+
+
+# ---------------------------------------------------------------- training
+
+class Trainer:
+    """Distillation trainer of a (student) model: FP32 weights, gradients
+    and AdamW moments in a torch-owned device region; crops of H x W."""
+
+    def __init__(self, cfg, weights, max_crops, H, W, device="cuda"):
+        import torch
+        self.cfg, self.H, self.W, self.max_crops = cfg, H, W, max_crops
+        self.desc = model_desc(cfg, "fp32")
+        blob = pack_blob(cfg, weights)
+        nb = _lib.pswa_train_workspace_bytes(C.byref(self.desc), max_crops, H, W)
+        if nb == 0:
+            raise PswaError(-2, "invalid trainer shape")
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=device)
+        h = C.c_void_p()
+        _check(_lib.pswa_train_create(C.byref(self.desc), blob.ctypes.data, blob.size, max_crops,
+                                      H, W, _ptr(self.ws), nb, _stream(), C.byref(h)))
+        self.handle = h
+        self.blob_floats = blob.size
+
+    def step(self, latents, hyper, mu_t, lsig_t, prev=None, lr=1e-3, weight_decay=0.0,
+             update=True):
+        """One step on device tensors latents [B][H][W][C] (int32), hyper
+        [B][Hh][Wh][Ch] (int32), prev [B][2][H][W][C] or None, targets
+        [B][H][W][C] (float32). Returns the loss."""
+        B = latents.shape[0]
+        loss = C.c_double()
+        _check(_lib.pswa_train_step(self.handle, B, 2 if prev is not None else 0,
+                                    _ptr(latents), _ptr(hyper), _ptr(prev), _ptr(mu_t),
+                                    _ptr(lsig_t), float(lr), float(weight_decay),
+                                    1 if update else 0, C.byref(loss), _stream()))
+        return loss.value
+
+    def read(self, what="weights"):
+        blob = np.empty(self.blob_floats, dtype=np.float32)
+        _check(_lib.pswa_train_read(self.handle, 0 if what == "weights" else 1,
+                                    blob.ctypes.data, blob.size, _stream()))
+        return unpack_blob(self.cfg, blob)
+
+    @property
+    def steps(self):
+        return _lib.pswa_train_num_steps(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.pswa_train_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+
+def pswa_student_accept(bits_student, bits_full, max_overhead=0.01):
+    """True when a frame keeps the student: its bits exceed the full model's
+    by at most max_overhead (a fraction)."""
+    return bool(_lib.pswa_student_accept(float(bits_student), float(bits_full),
+                                         float(max_overhead)))

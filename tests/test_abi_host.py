@@ -157,3 +157,25 @@ def test_frame_encode_uses_wavefront_order():
     cs = np.concatenate([c[i, j] for i, j in seq])
     xs = np.concatenate([idx[i, j] for i, j in seq])
     assert data == P.pswa_range_encode_seq(ys, cs, xs)
+
+
+def test_blob_shapes_round_trip():
+    """The binding's blob layout matches the generator's weight list, and
+    unpack_blob inverts pack_blob (the trainer reads weights back this way)."""
+    import numpy as np
+    import synth
+    from paper_2605_20977_amd import pswa
+    for cfg in (synth.TINY, synth.FULL, synth.STUDENT):
+        assert pswa.blob_shapes(cfg) == synth.weight_shapes(cfg)
+        W = synth.model_weights(cfg, 3)
+        u = pswa.unpack_blob(cfg, pswa.pack_blob(cfg, W))
+        assert all(np.array_equal(u[k], W[k]) for k in W)
+
+
+def test_student_accept_rule():
+    from paper_2605_20977_amd import pswa
+    assert pswa.pswa_student_accept(101.0, 100.0, 0.01)
+    assert not pswa.pswa_student_accept(101.01, 100.0, 0.01)
+    assert pswa.pswa_student_accept(90.0, 100.0, 0.0)
+    assert not pswa.pswa_student_accept(float("nan"), 100.0, 0.01)
+    assert not pswa.pswa_student_accept(-1.0, 100.0, 0.01)

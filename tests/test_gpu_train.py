@@ -1,0 +1,140 @@
+"""GPU tests of the student distillation kernels, through the C ABI.
+
+* loss and every parameter gradient of the hand-written FP32 training
+  kernels against the FP64 oracle (torch autograd of the oracle forward),
+  for I- and P-frame batches;
+* the AdamW kernel against the oracle's AdamW fed the same gradients;
+* a short distillation of the student from the full model lowers the loss
+  and the student's bits overhead (what the trained network gains).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import model as om
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_20977_amd import pswa
+    return pswa
+
+
+def _crops(cfg, teacher, n, H, W, n_prev, seed0):
+    out = []
+    for k in range(n):
+        y, z, prev = synth.frame_inputs(cfg, synth.FrameCfg(H, W, n_prev), seed0 + k)
+        o = om.forward(cfg, teacher, y, z, prev)
+        out.append({"latents": y, "hyper": z, "prev": prev, "mu_t": o["mu"],
+                    "lsig_t": o["lsig"]})
+    return out
+
+
+def _dev(crops, key, dtype):
+    if crops[0][key] is None:
+        return None
+    return torch.as_tensor(np.stack([c[key] for c in crops])).to("cuda", dtype).contiguous()
+
+
+def _step(tr, crops, **kw):
+    return tr.step(_dev(crops, "latents", torch.int32), _dev(crops, "hyper", torch.int32),
+                   _dev(crops, "mu_t", torch.float32), _dev(crops, "lsig_t", torch.float32),
+                   prev=_dev(crops, "prev", torch.int32), **kw)
+
+
+@pytest.mark.parametrize("n_prev", [0, 2])
+def test_gradients_match_oracle(P, n_prev):
+    from oracle import train as ot
+    cfg = synth.TINY
+    teacher = synth.model_weights(cfg, 5)
+    student = synth.model_weights(cfg, 6)
+    crops = _crops(cfg, teacher, 2, 9, 11, n_prev, 100 + 10 * n_prev)
+    print(f"case train grads tiny 2x9x11 P={n_prev}", flush=True)
+    tr = P.Trainer(cfg, student, max_crops=2, H=9, W=11)
+    loss = _step(tr, crops, update=False)
+    G = tr.read("grads")
+    ref_loss, ref = ot.loss_and_grads(cfg, {k: v.astype(np.float64) for k, v in student.items()},
+                                      crops)
+    print(f"loss gpu {loss:.9g} oracle {ref_loss:.9g}", flush=True)
+    assert abs(loss - ref_loss) <= 1e-5 * ref_loss
+    worst = 0.0
+    for k, g in ref.items():
+        nrm = np.linalg.norm(g)
+        err = np.linalg.norm(G[k].astype(np.float64) - g)
+        rel = err / max(nrm, 1e-30)
+        worst = max(worst, rel if nrm > 1e-8 else 0.0)
+        assert err <= 2e-4 * nrm + 1e-9, (k, rel, nrm)
+    print(f"worst relative gradient error {worst:.3e}", flush=True)
+
+
+def test_adamw_matches_oracle(P):
+    from oracle import train as ot
+    cfg = synth.TINY
+    teacher = synth.model_weights(cfg, 5)
+    student = synth.model_weights(cfg, 7)
+    crops = _crops(cfg, teacher, 2, 8, 8, 0, 300)
+    tr = P.Trainer(cfg, student, max_crops=2, H=8, W=8)
+    W = {k: v.astype(np.float64) for k, v in student.items()}
+    m = {k: np.zeros_like(v) for k, v in W.items()}
+    v = {k: np.zeros_like(x) for k, x in W.items()}
+    for t in (1, 2, 3):
+        _step(tr, crops, lr=1e-3, weight_decay=0.1, update=True)
+        G = tr.read("grads")
+        W, m, v = ot.adamw_step(W, G, m, v, t, lr=1e-3, wd=0.1)
+        Wg = tr.read("weights")
+        for k in W:
+            assert np.allclose(Wg[k], W[k], rtol=1e-6, atol=1e-7), (t, k)
+    assert tr.steps == 3
+
+
+def test_distillation_gains(P):
+    """Distil the student from the full model on generated crops; the loss
+    falls and the student's bits overhead against the full model on
+    held-out crops shrinks compared with the untrained student."""
+    full, stud = synth.FULL, synth.STUDENT
+    teacher = synth.model_weights(full, synth.CONFIG_SEEDS["4k_student"][1])
+    init = synth.model_weights(stud, 51)
+    H = W = 24
+    fm = P.Model(full, teacher)
+
+    def labelled(seed0, n, n_prev):
+        out = []
+        for k in range(n):
+            y, z, prev = synth.frame_inputs(full, synth.FrameCfg(H, W, n_prev), seed0 + k)
+            o = P.pswa_encode_params(fm, y, z, prev)
+            out.append({"latents": y, "hyper": z, "prev": prev,
+                        "mu_t": o["mean"].cpu().numpy(),
+                        "lsig_t": np.log(o["scale"].cpu().numpy().astype(np.float64)),
+                        "bits_full": float(o["bits"].double().sum())})
+        return out
+    train_i = labelled(1000, 32, 0)
+    train_p = labelled(1100, 32, 2)
+    held = labelled(5000, 4, 0) + labelled(5100, 4, 2)
+    tr = P.Trainer(stud, init, max_crops=8, H=H, W=W)
+    first = last = None
+    for it in range(120):
+        src = train_i if it % 2 == 0 else train_p
+        k0 = (it // 2 * 8) % len(src)
+        loss = _step(tr, src[k0:k0 + 8], lr=2e-3, weight_decay=0.01)
+        first = loss if first is None else first
+        last = loss
+    print(f"distillation loss {first:.4f} -> {last:.4f}", flush=True)
+    assert last < 0.5 * first
+
+    def overhead(weights):
+        sm = P.Model(stud, weights)
+        tot_s = tot_f = 0.0
+        for c in held:
+            o = P.pswa_encode_params(sm, c["latents"], c["hyper"], c["prev"])
+            tot_s += float(o["bits"].double().sum())
+            tot_f += c["bits_full"]
+        return tot_s / tot_f - 1.0
+    ov0, ov1 = overhead(init), overhead(tr.read("weights"))
+    print(f"student bits overhead vs full model: untrained {100 * ov0:+.2f} %, "
+          f"trained {100 * ov1:+.2f} %", flush=True)
+    assert ov1 < ov0
