@@ -255,14 +255,20 @@ pswa_status pswa_batch_autotune(pswa_batch* batch, const char* cache_path, int r
  * Changing the grouping, row tile, spin limit or trace buffer drops the
  * graph. The capture uses a private stream; the kernel timer must be off. */
 pswa_status pswa_batch_capture(pswa_batch* batch, void* stream);
+/* Barrier form (on by default): a group whose workgroups all run on one XCD
+ * (checked by the kernel at every launch from the hardware XCD id) meets at
+ * a barrier that keeps the XCD's shared L2 and only invalidates each CU's
+ * L1; off, or for groups that span XCDs, every barrier is device-scope
+ * (L2 written back and invalidated). Both give the same results. */
+pswa_status pswa_batch_set_xcd_barrier(pswa_batch* batch, int on);
 /* Bound on the spin count of one barrier wait before the launch aborts
  * (default about a second of waiting). Lowering it forces the abort path. */
 pswa_status pswa_batch_set_spin_limit(pswa_batch* batch, int64_t spins);
 /* Phase timeline (a profiling aid): while d_trace is set, one thread of the
  * persistent kernel (rank 0 of group 0) writes the device wall clock
- * (100 MHz) after each of the first n barriers of its group in a run to
- * d_trace[0..n) (device int64). Barriers per step: 3 + 5 L + 5. n = 0 turns
- * the trace off. */
+ * (100 MHz) when it reaches and when it leaves each of its group's barriers:
+ * d_trace[2k] and d_trace[2k + 1] for barrier k, for 2k + 1 < n (device
+ * int64). Barriers per step: 3 + 5 L + 5. n = 0 turns the trace off. */
 pswa_status pswa_batch_trace(pswa_batch* batch, int64_t* d_trace, int n);
 void pswa_batch_destroy(pswa_batch* batch);
 

@@ -47,7 +47,9 @@ struct pswa_batch {
   const pswa_model* model = nullptr;
   std::vector<pswa_batch_frame> frames;
   std::vector<FrameInfo> finfo;
-  int HWt = 0, T = 0, Mmax = 0, max_grid = 0;
+  int HWt = 0, T = 0, Mmax = 0;
+  int max_grid_r16 = 0, max_grid_r32 = 0;  // co-resident blocks per row tile
+  int max_grid() const { return rtile == 16 ? max_grid_r16 : max_grid_r32; }
   int fpg = 1, bpg = 1, grid = 0;       // frames and blocks per group, total blocks
   std::vector<GroupPlan> groups;
   size_t rows_cap = 0, steps_cap = 0;   // worst case over groupings
@@ -74,6 +76,8 @@ struct pswa_batch {
   int* bars = nullptr;  // [frames][kBarStride]: group barrier counters
   GroupInfo* d_groups = nullptr;
   int* block_map = nullptr;
+  int* xcd_tab = nullptr;
+  int xcd_local = 1;
   GemmArgs* gtab = nullptr;  // per-group, per-step argument tables
   AttnArgs* atab = nullptr;
   SymArgs* stab = nullptr;
@@ -141,6 +145,7 @@ void lay_out(const NetDims& x, const Plan& p, int n, void* base, pswa_batch* b) 
   b->bars = L.take<int>((size_t)n * kBarStride);
   b->d_groups = L.take<GroupInfo>(n);
   b->block_map = L.take<int>(kMaxBlocks);
+  b->xcd_tab = L.take<int>(kMaxBlocks);
   b->sum = L.take<float>(64);
   b->gtab = L.take<GemmArgs>(p.steps_cap * gemm_phases(x.L));
   b->atab = L.take<AttnArgs>(p.steps_cap * attn_phases(x.L));
@@ -237,6 +242,8 @@ PersistArgs persist_args(const pswa_batch* b) {
   P.spin_limit = b->spin_limit;
   P.trace = b->trace;
   P.trace_len = b->trace_len;
+  P.xcd_tab = b->xcd_tab;
+  P.xcd_local = b->xcd_local;
   return P;
 }
 
@@ -262,9 +269,9 @@ pswa_status apply_groups(pswa_batch* b, int fpg, int bpg, hipStream_t st) {
   if (fpg < 1 || bpg < 1) return fail(PSWA_E_ARG, "frames and blocks per group must be >= 1");
   fpg = std::min(fpg, n);
   const int ng = (n + fpg - 1) / fpg;
-  if ((long)ng * bpg > b->max_grid || (long)ng * bpg > kMaxBlocks)
+  if ((long)ng * bpg > b->max_grid() || (long)ng * bpg > kMaxBlocks)
     return fail(PSWA_E_ARG, "%d groups of %d blocks exceed the co-resident limit %d", ng, bpg,
-                b->max_grid);
+                b->max_grid());
   std::vector<int> order(n);
   for (int f = 0; f < n; ++f) order[f] = f;
   std::stable_sort(order.begin(), order.end(), [&](int u, int v) {
@@ -449,19 +456,23 @@ pswa_status pswa_batch_create(const pswa_model* model, int n, const pswa_batch_f
   b->rows_cap = p.rows_cap;
   b->steps_cap = p.steps_cap;
   b->any_p = p.any_p;
-  b->max_grid = std::min(persistent_max_grid(model->x, model->w.prec), kMaxBlocks);
-  if (b->max_grid <= 0) return fail(PSWA_E_HIP, "cannot size the persistent grid");
+  b->max_grid_r32 = std::min(persistent_max_grid(model->x, model->w.prec, 32), kMaxBlocks);
+  b->max_grid_r16 = model->w.prec == PSWA_PREC_F32
+                        ? b->max_grid_r32
+                        : std::min(persistent_max_grid(model->x, model->w.prec, 16), kMaxBlocks);
+  if (b->max_grid_r32 <= 0 || b->max_grid_r16 <= 0)
+    return fail(PSWA_E_HIP, "cannot size the persistent grid");
   hipStream_t st = static_cast<hipStream_t>(stream);
   PSWA_HIP_TRY(hipMemcpyAsync(b->d_frames, p.finfo.data(), n * sizeof(FrameInfo),
                               hipMemcpyHostToDevice, st));
   int fpg, bpg;
   if (grid > 0) {  // one group of `grid` blocks
     fpg = n;
-    bpg = std::min(grid, b->max_grid);
+    bpg = std::min(grid, b->max_grid());
   } else {         // about 8 to 32 blocks per group, as many groups as fit
     bpg = 8;
-    while (bpg < 32 && (long)n * bpg * 2 <= b->max_grid) bpg *= 2;
-    const int ng = std::max(1, std::min(n, b->max_grid / bpg));
+    while (bpg < 32 && (long)n * bpg * 2 <= b->max_grid()) bpg *= 2;
+    const int ng = std::max(1, std::min(n, b->max_grid() / bpg));
     fpg = (n + ng - 1) / ng;
   }
   const pswa_status gs = apply_groups(b.get(), fpg, bpg, st);
@@ -473,12 +484,12 @@ pswa_status pswa_batch_create(const pswa_model* model, int n, const pswa_batch_f
 int pswa_batch_num_steps(const pswa_batch* b) { return b ? b->T : -1; }
 int pswa_batch_max_rows(const pswa_batch* b) { return b ? b->Mmax : -1; }
 int pswa_batch_grid(const pswa_batch* b) { return b ? b->grid : -1; }
-int pswa_batch_max_grid(const pswa_batch* b) { return b ? b->max_grid : -1; }
+int pswa_batch_max_grid(const pswa_batch* b) { return b ? b->max_grid() : -1; }
 
 pswa_status pswa_batch_set_grid(pswa_batch* b, int grid) {
   if (!b) return fail(PSWA_E_ARG, "batch is null");
-  if (grid < 1 || grid > b->max_grid)
-    return fail(PSWA_E_ARG, "grid %d outside [1, %d]", grid, b->max_grid);
+  if (grid < 1 || grid > b->max_grid())
+    return fail(PSWA_E_ARG, "grid %d outside [1, %d]", grid, b->max_grid());
   return apply_groups(b, (int)b->finfo.size(), grid, nullptr);
 }
 
@@ -502,6 +513,10 @@ pswa_status pswa_batch_set_rtile(pswa_batch* b, int rtile) {
   if (rtile != 16 && rtile != 32) return fail(PSWA_E_ARG, "row tile must be 16 or 32");
   if (rtile == 16 && b->model->w.prec == PSWA_PREC_F32)
     return fail(PSWA_E_UNSUPPORTED, "FP32 models use 16-row FP32 tiles only");
+  const int lim = rtile == 16 ? b->max_grid_r16 : b->max_grid_r32;
+  if (b->grid > lim)
+    return fail(PSWA_E_ARG, "the current %d blocks exceed the %d co-resident with %d-row tiles; "
+                "regroup first", b->grid, lim, rtile);
   b->rtile = rtile;
   drop_graph(b);
   return PSWA_OK;
@@ -563,9 +578,13 @@ pswa_status pswa_batch_autotune(pswa_batch* b, const char* cache_path, int reps,
                       ", \"frames_per_group\": %d, \"blocks_per_group\": %d, \"rtile\": %d, "
                       "\"ms\": %f", &f, &g, &r, &ms) == 4 &&
           (r == 16 || r == 32) && (r == 32 || m->w.prec)) {
-        const pswa_status s2 = apply_groups(b, f, g, st);
-        if (s2 != PSWA_OK) continue;  // a stale entry (another device limit): retune
+        const int r_old = b->rtile;
         b->rtile = r;
+        const pswa_status s2 = apply_groups(b, f, g, st);
+        if (s2 != PSWA_OK) {  // a stale entry (another device limit): retune
+          b->rtile = r_old;
+          continue;
+        }
         *out_fpg = b->fpg;
         *out_bpg = b->bpg;
         *out_rtile = r;
@@ -604,41 +623,44 @@ pswa_status pswa_batch_autotune(pswa_batch* b, const char* cache_path, int reps,
     return PSWA_OK;
   };
   // (frames per group, blocks per group): powers of two (and all frames),
-  // using at least a sixteenth of the co-resident blocks
+  // using at least a sixteenth of the co-resident blocks, for each row tile
   std::vector<int> fpgs;
   for (int f = 1; f < n; f *= 2) fpgs.push_back(f);
   fpgs.push_back(n);
   float best = 1e30f;
-  int bf = b->fpg, bb = b->bpg, br = 32;
-  for (int f : fpgs)
-    for (int g = 2; g <= b->max_grid; g *= 2) {
-      const int ng = (n + f - 1) / f;
-      if ((long)ng * g > b->max_grid || ng * g < std::min(16, b->max_grid / 16)) continue;
-      if (apply_groups(b, f, g, st) != PSWA_OK) continue;
-      float med = 0;
-      const pswa_status ts = time_it(32, &med);
-      if (ts != PSWA_OK) return ts;
-      if (med < best) {
-        best = med;
-        bf = f;
-        bb = g;
+  int bf = b->fpg, bb = b->bpg, br = b->rtile;
+  const std::vector<int> rts = m->w.prec == PSWA_PREC_F32 ? std::vector<int>{32}
+                                                          : std::vector<int>{32, 16};
+  for (int r : rts) {
+    const int lim = r == 16 ? b->max_grid_r16 : b->max_grid_r32;
+    // regroup within the limit of this row tile before switching to it
+    if (b->grid > lim && apply_groups(b, n, std::min(lim, 8), st) != PSWA_OK) continue;
+    b->rtile = r;
+    for (int f : fpgs)
+      for (int g = 2; g <= lim; g *= 2) {
+        const int ng = (n + f - 1) / f;
+        if ((long)ng * g > lim || ng * g < std::min(16, lim / 16)) continue;
+        if (apply_groups(b, f, g, st) != PSWA_OK) continue;
+        float med = 0;
+        const pswa_status ts = time_it(r, &med);
+        if (ts != PSWA_OK) return ts;
+        if (med < best) {
+          best = med;
+          bf = f;
+          bb = g;
+          br = r;
+        }
       }
-    }
+  }
+  // the winner (a grouping valid for its row tile)
+  if (b->grid > (br == 16 ? b->max_grid_r16 : b->max_grid_r32))
+    (void)apply_groups(b, n, 1, st);
+  b->rtile = br;
   pswa_status gs = apply_groups(b, bf, bb, st);
   if (gs != PSWA_OK) return gs;
-  if (m->w.prec != PSWA_PREC_F32) {
-    float med = 0;
-    const pswa_status ts = time_it(16, &med);
-    if (ts != PSWA_OK) return ts;
-    if (med < best) {
-      best = med;
-      br = 16;
-    }
-  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (best >= 1e30f) return fail(PSWA_E_HIP, "autotune: every candidate aborted");
-  b->rtile = br;
   drop_graph(b);
   *out_fpg = bf;
   *out_bpg = bb;
@@ -699,6 +721,13 @@ pswa_status pswa_batch_set_spin_limit(pswa_batch* b, int64_t spins) {
   if (!b) return fail(PSWA_E_ARG, "batch is null");
   if (spins < 0) return fail(PSWA_E_ARG, "spin limit must be >= 0");
   b->spin_limit = long(spins);
+  drop_graph(b);
+  return PSWA_OK;
+}
+
+pswa_status pswa_batch_set_xcd_barrier(pswa_batch* b, int on) {
+  if (!b) return fail(PSWA_E_ARG, "batch is null");
+  b->xcd_local = on ? 1 : 0;
   drop_graph(b);
   return PSWA_OK;
 }

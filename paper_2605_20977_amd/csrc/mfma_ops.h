@@ -43,14 +43,15 @@ __host__ __device__ inline int qgemm_col_tiles(int N, int epi) {
   return (N + per - 1) / per;
 }
 constexpr int kKchunk = 16;  // k-steps whose weight loads are issued together
+constexpr int kStageLoads = 16;  // A loads per thread in flight while staging
 __host__ __device__ inline int qgemm_row_tiles(int M, int R = kMBq) { return (M + R - 1) / R; }
 // element pitch of a staged row: K plus a 16-byte skew
 __host__ __device__ inline int qgemm_pitch(int K, int prec) { return K + (prec == PSWA_PREC_BF16 ? 8 : 16); }
 // LDS of a tile: the staged A tile (kQRedBytes is a spare prefix kept for
 // alignment of the tile).
 constexpr size_t kQRedBytes = 256;
-__host__ __device__ inline size_t qgemm_lds_bytes(int K, int prec) {
-  return kQRedBytes + (size_t)kMBq * qgemm_pitch(K, prec) * (prec == PSWA_PREC_BF16 ? 2 : 1);
+__host__ __device__ inline size_t qgemm_lds_bytes(int K, int prec, int R = kMBq) {
+  return kQRedBytes + (size_t)R * qgemm_pitch(K, prec) * (prec == PSWA_PREC_BF16 ? 2 : 1);
 }
 
 __device__ __forceinline__ uint16_t bf16_rne(float f) {
@@ -139,10 +140,10 @@ __device__ __forceinline__ void gemm_tile_q(const GemmArgs& a, int bx, int by, u
   // rows past the end of A are zeros (their results are dropped)
   if (stage) {
     const int total = R * K4;
-    for (int base = 0; base < total; base += 16 * kThreads) {
-      float4 xv[16];
+    for (int base = 0; base < total; base += kStageLoads * kThreads) {
+      float4 xv[kStageLoads];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
+      for (int u = 0; u < kStageLoads; ++u) {
         const int e = base + u * kThreads + tid;
         xv[u] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (e < total && e / K4 < rows) {
@@ -157,7 +158,7 @@ __device__ __forceinline__ void gemm_tile_q(const GemmArgs& a, int bx, int by, u
         }
       }
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
+      for (int u = 0; u < kStageLoads; ++u) {
         const int e = base + u * kThreads + tid;
         if (e >= total) continue;
         const int m = e / K4, c = e % K4;

@@ -50,6 +50,8 @@ struct PersistArgs {
   long spin_limit;
   long long* trace;        // optional: wall clock after each barrier (group 0, rank 0)
   int trace_len;
+  int* xcd_tab;            // [grid]: XCD of each block, by (group, rank)
+  int xcd_local;           // allow the one-XCD barrier for groups that qualify
 };
 
 // Kernel instances: (projection arithmetic, head size, row tile). Each is
@@ -68,9 +70,9 @@ struct PersistArgs {
 inline int gemm_phases(int L) { return 6 + 4 * L; }
 inline int attn_phases(int L) { return 1 + L; }
 
-size_t persistent_lds_bytes(const NetDims& x, int prec);
+size_t persistent_lds_bytes(const NetDims& x, int prec, int rtile);
 // Largest grid whose blocks can all be resident at once (0 on error).
-int persistent_max_grid(const NetDims& x, int prec);
+int persistent_max_grid(const NetDims& x, int prec, int rtile);
 void launch_persistent(const PersistArgs& P, const NetDims& x, int prec, int rtile, int grid,
                        hipStream_t s);
 void zero_ints(int* p, int n, hipStream_t s);

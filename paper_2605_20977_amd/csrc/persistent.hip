@@ -25,10 +25,10 @@ __global__ void k_zero_ints(int* p, int n) {
 
 }  // namespace
 
-size_t persistent_lds_bytes(const NetDims& x, int prec) {
+size_t persistent_lds_bytes(const NetDims& x, int prec, int rtile) {
   size_t b = attn_lds_bytes(x.dh);
   for (int K : {x.F, x.d, x.C}) {
-    const size_t g = prec ? qgemm_lds_bytes(K, prec) : gemm_lds_bytes(K);
+    const size_t g = prec ? qgemm_lds_bytes(K, prec, rtile) : gemm_lds_bytes(K);
     b = b > g ? b : g;
   }
   return b;
@@ -45,15 +45,16 @@ const void* persistent_fn(int prec, int dh, int rtile) {
   return nullptr;
 }
 
-int persistent_max_grid(const NetDims& x, int prec) {
-  const void* fn = persistent_fn(prec, x.dh, kMBq);
+int persistent_max_grid(const NetDims& x, int prec, int rtile) {
+  const void* fn = persistent_fn(prec, x.dh, rtile);
   if (!fn || !allow_big_lds(fn)) return 0;
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads,
-                                                   persistent_lds_bytes(x, prec)) != hipSuccess)
+                                                   persistent_lds_bytes(x, prec, rtile)) !=
+      hipSuccess)
     return 0;
   return cus * per_cu;
 }
@@ -76,7 +77,8 @@ void launch_persistent(const PersistArgs& P, const NetDims& x, int prec, int rti
   }();
   (void)attr;
   void* args[] = {const_cast<PersistArgs*>(&P)};
-  (void)hipLaunchKernel(fn, dim3(grid), dim3(kThreads), args, persistent_lds_bytes(x, prec), s);
+  (void)hipLaunchKernel(fn, dim3(grid), dim3(kThreads), args,
+                        persistent_lds_bytes(x, prec, prec ? rtile : kMBq), s);
 }
 
 }  // namespace pswa

@@ -35,19 +35,36 @@ using namespace dev;
 
 namespace {
 
-// Barrier of the nb blocks of one group.
+// Barrier of the nb blocks of one group. Two forms of the same arrival
+// counter (bounded spin, abort flag):
+//  * device scope (any placement): the arrival is a release and the poll an
+//    acquire at agent scope, which write the XCD's L2 back and invalidate it;
+//  * one XCD (every block of the group verified to run on the same XCD):
+//    each wave waits until its stores have reached the shared L2 (no L2
+//    write-back), the arrival and the poll are relaxed, and after the wait
+//    the vector caches are invalidated at device scope.
 __device__ __forceinline__ bool group_barrier(unsigned* bar, unsigned& target, int nb,
-                                              int* abort_flag, long spin_limit) {
+                                              int* abort_flag, long spin_limit, bool one_xcd) {
   __shared__ int s_ok;
+  if (one_xcd) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   if (threadIdx.x == 0) {
     target += nb;
-    // release: this block's writes become visible before its arrival counts
-    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (one_xcd) {
+      __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      // release: this block's writes become visible before its arrival counts
+      __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
     int ok = 1;
     long spins = 0;
-    // acquire: once every arrival is seen, every block's writes are visible
-    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    for (;;) {
+      // acquire (device form): once every arrival is seen, every block's
+      // writes are visible
+      const unsigned seen = one_xcd
+          ? __hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+          : __hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      if (seen >= target) break;
       if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
         ok = 0;
         break;
@@ -62,7 +79,15 @@ __device__ __forceinline__ bool group_barrier(unsigned* bar, unsigned& target, i
     s_ok = ok;
   }
   __syncthreads();
+  if (one_xcd) asm volatile("buffer_inv sc1" ::: "memory");
   return s_ok != 0;
+}
+
+// Hardware id of the XCD running this wave.
+__device__ __forceinline__ int xcd_id() {
+  unsigned v;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+  return int(v & 0xf);
 }
 
 template <int AK, bool RMS, int EPI, int PREC, int R>
@@ -118,9 +143,28 @@ __global__ void __launch_bounds__(kThreads) k_persistent(PersistArgs P) {
   const int t_end = min(P.t_end, G.T);
   unsigned target = 0;
   int nsync = 0;
-#define PSWA_SYNC                                                                  \
-  if (!group_barrier(G.bar, target, nb, P.abort_flag, P.spin_limit)) return;      \
-  if (tracer && nsync < P.trace_len) P.trace[nsync] = wall_clock64();             \
+  // Placement check: every block records its XCD; after a device-scope
+  // barrier the group uses the one-XCD barrier if all its blocks agree.
+  bool one_xcd = false;
+  {
+    __shared__ int s_same;
+    const int slot = (bm >> 16) * nb + rank;
+    if (threadIdx.x == 0) P.xcd_tab[slot] = xcd_id();
+    if (!group_barrier(G.bar, target, nb, P.abort_flag, P.spin_limit, false)) return;
+    if (threadIdx.x == 0) s_same = 1;
+    __syncthreads();
+    const int base = (bm >> 16) * nb;
+    for (int k = threadIdx.x; k < nb; k += blockDim.x)
+      if (__hip_atomic_load(P.xcd_tab + base + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) !=
+          __hip_atomic_load(P.xcd_tab + base, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        s_same = 0;
+    __syncthreads();
+    one_xcd = P.xcd_local && s_same;
+  }
+#define PSWA_SYNC                                                                    \
+  if (tracer && 2 * nsync + 1 < P.trace_len) P.trace[2 * nsync] = wall_clock64();   \
+  if (!group_barrier(G.bar, target, nb, P.abort_flag, P.spin_limit, one_xcd)) return; \
+  if (tracer && 2 * nsync + 1 < P.trace_len) P.trace[2 * nsync + 1] = wall_clock64(); \
   ++nsync;
 
   for (int t = P.t_begin; t < t_end; ++t) {

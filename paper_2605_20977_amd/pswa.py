@@ -91,6 +91,7 @@ def _load():
         "pswa_batch_autotune": (i32, [vp, C.c_char_p, i32, vp, P(i32), P(i32), P(i32),
                                       P(C.c_float)]),
         "pswa_batch_set_groups": (i32, [vp, i32, i32, vp]),
+        "pswa_batch_set_xcd_barrier": (i32, [vp, i32]),
         "pswa_train_workspace_bytes": (sz, [P(ModelDesc), i32, i32, i32]),
         "pswa_train_create": (i32, [P(ModelDesc), vp, sz, i32, i32, i32, vp, sz, vp, P(vp)]),
         "pswa_train_step": (i32, [vp, i32, i32, vp, vp, vp, vp, vp, C.c_float, C.c_float, i32,
@@ -130,7 +131,7 @@ EXPORTED = ("pswa_model_blob_floats", "pswa_model_device_bytes", "pswa_model_cre
             "pswa_batch_autotune", "pswa_batch_capture", "pswa_batch_set_groups",
             "pswa_batch_groups", "pswa_train_workspace_bytes", "pswa_train_create",
             "pswa_train_step", "pswa_train_read", "pswa_train_num_steps", "pswa_train_destroy",
-            "pswa_student_accept")
+            "pswa_student_accept", "pswa_batch_set_xcd_barrier")
 
 
 def lib():
@@ -458,6 +459,9 @@ class Batch:
                                         _stream(), C.byref(f), C.byref(g), C.byref(r),
                                         C.byref(ms)))
         return f.value, g.value, r.value, ms.value
+
+    def set_xcd_barrier(self, on):
+        _check(_lib.pswa_batch_set_xcd_barrier(self.handle, 1 if on else 0))
 
     def set_groups(self, frames_per_group, blocks_per_group):
         _check(_lib.pswa_batch_set_groups(self.handle, int(frames_per_group),

@@ -231,3 +231,21 @@ def test_batch_graph_replays_match_eager(P, prec):
     b.run()
     b.check()
     _assert_same(b.outputs(0), ref_b, f"{prec} eager after drop")
+
+
+def test_batch_barrier_forms_agree(P, tiny):
+    """Groups on one XCD (one-XCD barrier) and the device-scope barrier
+    give the same bits; groups that span XCDs fall back by themselves."""
+    cfg, Wt, model = tiny
+    fr = _frames(cfg, [(16, 16, 2), (9, 13, 0), (12, 7, 2), (5, 5, 0)], 1500)
+    ref = [_per_frame(P, model, f) for f in fr]
+    b = P.Batch(model, fr)
+    for fpg, bpg in ((1, 4), (1, 8), (2, 16), (4, 64)):
+        for on in (True, False):
+            print(f"case barrier one_xcd={on} groups {fpg}x{bpg}", flush=True)
+            b.set_groups(fpg, bpg)
+            b.set_xcd_barrier(on)
+            b.run()
+            b.check()
+            for k in range(len(fr)):
+                _assert_same(b.outputs(k), ref[k], f"one_xcd={on} {fpg}x{bpg} frame {k}")
