@@ -277,17 +277,21 @@ __device__ __forceinline__ void gemm_tile_any(const GemmArgs& a, int bx, int by,
 // and runs an online softmax over them, loading each key's K and V rows
 // together. The lanes are then merged: common max and rescaled exp-sum by
 // wave reductions, the rescaled value vectors summed lane 0..63 in order
-// through LDS. All four waves of the block must call this together (it
-// synchronises the block); `live` marks waves with a real item.
+// through the wave's own LDS region. Waves work independently (no block
+// synchronisation); a wave with `live` false or an item past the end
+// returns at once. Every lane loads the query row itself, together with its
+// first key, so one memory round trip serves both.
 // Key positions: a row's frame (fid, else the single frame0) gives its grid
 // and its offset in the global position space; temporal K/V of frame
 // position g in previous frame tau is at (tau * HWt + g) * 2d.
 template <int DH>
 __device__ __forceinline__ void attn_item(const AttnArgs& a, int item, bool live, float* tr_all) {
+  // each wave works alone in its own LDS region: no block-wide sync
   float* tr = tr_all + (threadIdx.x >> 6) * (DH * 65);
   const int lane = threadIdx.x & 63;
   live = live && item < a.M * a.heads;
-  const int m = live ? item / a.heads : 0, hd = live ? item % a.heads : 0;
+  if (!live) return;
+  const int m = item / a.heads, hd = item % a.heads;
   const int gp = map_row(a.pos, m);
   const FrameInfo fi = a.fid ? a.frames[a.fid[m]] : a.frame0;
   const int lp = gp - fi.off;
@@ -297,23 +301,24 @@ __device__ __forceinline__ void attn_item(const AttnArgs& a, int item, bool live
   const int n_sp = n_causal + (a.include_self ? 1 : 0);
   const bool temporal = a.tkv && fi.n_prev > 0;
   const int n_tm = temporal ? 2 * k1 * k1 : 0;
-  const int n_keys = live ? n_sp + (a.knull ? 1 : 0) + n_tm : 0;
+  const int n_keys = n_sp + (a.knull ? 1 : 0) + n_tm;
   const int d = a.d;
   const float scale = 1.0f / sqrtf(float(DH));
-  __syncthreads();  // the block's previous items are done with the LDS
 
-  // the query sits in LDS, read by every lane as a broadcast
-  float* qs = tr_all + kWaves * (DH * 65) + (threadIdx.x >> 6) * DH;
-  if (lane < DH) qs[lane] = a.q[(size_t)m * a.ldq + hd * DH + lane];
-  __syncthreads();
+  // the query: every lane loads the whole row (the same addresses, served
+  // once), issued together with the first key's loads
+  const float* qp = a.q + (size_t)m * a.ldq + hd * DH;
+  float4 q4[DH / 4];
+#pragma unroll
+  for (int e = 0; e < DH / 4; ++e) q4[e] = *reinterpret_cast<const float4*>(qp + 4 * e);
 
   float mx = -INFINITY, sum = 0.f;
   float o[DH];
 #pragma unroll
   for (int e = 0; e < DH; ++e) o[e] = 0.f;
 
-  // one key per iteration: its K and V rows are the lane's only loads in
-  // flight (most lanes own a single key)
+  // one key per iteration: its K and V rows are the lane's loads in flight
+  // (most lanes own a single key)
 #pragma unroll 1
   for (int u = 0; u < kMaxKeys / 64; ++u) {
     const int kk = lane + 64 * u;
@@ -358,8 +363,7 @@ __device__ __forceinline__ void attn_item(const AttnArgs& a, int item, bool live
     }
     float dot = 0.f;
 #pragma unroll
-    for (int e = 0; e < DH / 4; ++e)
-      dot = dot4(*reinterpret_cast<const float4*>(qs + 4 * e), kr[e], dot);
+    for (int e = 0; e < DH / 4; ++e) dot = dot4(q4[e], kr[e], dot);
     const float lg = dot * scale + b;
     const float mn = fmaxf(mx, lg);
     const float c_old = expf(mx - mn);  // 0 for the first key (mx = -inf)
@@ -378,19 +382,26 @@ __device__ __forceinline__ void attn_item(const AttnArgs& a, int item, bool live
   const float gmx = wave_max(mx);
   const float f = mx == -INFINITY ? 0.f : expf(mx - gmx);
   const float tot = wave_sum(sum * f);
+  // lanes' rescaled value vectors summed lane 0..63 in order, through LDS
 #pragma unroll
   for (int e = 0; e < DH; ++e) tr[e * 65 + lane] = o[e] * f;
-  __syncthreads();
-  if (live && lane < DH) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (lane < DH) {
     float v = 0.f;
 #pragma unroll
     for (int l = 0; l < 64; ++l) v += tr[lane * 65 + l];
     a.out[(size_t)m * a.ldo + hd * DH + lane] = v / tot;
   }
+  // the region is reused by this wave's next item
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 __host__ __device__ inline size_t attn_lds_bytes(int dh) {
-  return (size_t)kWaves * dh * 66 * sizeof(float);  // transpose buffer + query
+  return (size_t)kWaves * dh * 65 * sizeof(float);  // one transpose buffer per wave
 }
 
 template <int DH_dummy = 0>

@@ -60,6 +60,66 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
   return uint16_t(u >> 16);
 }
 
+// Row statistics of rows m0 .. m0+rows-1 of A: 1/rms (RMS) and the FP8
+// input scale 448 / max|x g| (FP8). Lane l accumulates chunks l, l+64, ...
+// of a row in order, then a fixed xor tree sums the lanes. CPR = chunks per
+// lane and row; 16 / CPR rows per wave are loaded together.
+template <int AK, bool RMS, int PREC, int CPR>
+__device__ __forceinline__ void row_stats(const GemmArgs& a, int m0, int rows, float* rstd,
+                                          float* rmul) {
+  constexpr int RPB = 16 / CPR;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int K = a.K, K4 = a.K / 4;
+  for (int mb = 0; mb < rows; mb += RPB * kWaves) {
+    float4 xs[RPB][CPR];
+#pragma unroll
+    for (int j = 0; j < RPB; ++j) {
+      const int mm = min(mb + wave + kWaves * j, rows - 1);
+      const size_t off = (size_t)map_row(a.xrow, m0 + mm) * a.ldx;
+#pragma unroll
+      for (int it = 0; it < CPR; ++it) {
+        const int c = lane + 64 * it;
+        xs[j][it] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (c < K4) {
+          if (AK == A_INT) {
+            const int4 xi = *reinterpret_cast<const int4*>(a.Xi + off + 4 * c);
+            xs[j][it] = make_float4(float(xi.x), float(xi.y), float(xi.z), float(xi.w));
+          } else {
+            xs[j][it] = *reinterpret_cast<const float4*>(a.X + off + 4 * c);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < RPB; ++j) {
+      float ss = 0.f, mx = 0.f;
+#pragma unroll
+      for (int it = 0; it < CPR; ++it) {
+        const int c = lane + 64 * it;
+        if (c < K4) {
+          const float4 x = xs[j][it];
+          if (RMS) ss = dot4(x, x, ss);
+          if (PREC == PSWA_PREC_FP8) {
+            float4 g = make_float4(1.f, 1.f, 1.f, 1.f);
+            if (RMS) g = *reinterpret_cast<const float4*>(a.gain + 4 * c);
+            if (AK == A_INT) g = *reinterpret_cast<const float4*>(a.xscale + 4 * c);
+            mx = fmaxf(mx, fmaxf(fmaxf(fabsf(x.x * g.x), fabsf(x.y * g.y)),
+                                 fmaxf(fabsf(x.z * g.z), fabsf(x.w * g.w))));
+          }
+        }
+      }
+      if (RMS) ss = wave_sum(ss);
+      if (PREC == PSWA_PREC_FP8) mx = wave_max(mx);
+      const int mm = mb + wave + kWaves * j;
+      if (lane == 0 && mm < rows) {
+        rstd[mm] = RMS ? 1.0f / sqrtf(ss / float(K) + kEps) : 1.0f;
+        // FP8 rows are stored as value * (448 / max); a zero row stays zero
+        rmul[mm] = PREC == PSWA_PREC_FP8 ? (mx > 0.f ? kFp8Max / mx : 1.0f) : 1.0f;
+      }
+    }
+  }
+}
+
 // R = A rows per tile (16 or 32, one or two 16-row MFMA blocks); a row
 // always sits at position (row % 16) of its MFMA block, so R changes which
 // tile computes a row, never how. stage = false reuses the A tile (and its
@@ -77,57 +137,17 @@ __device__ __forceinline__ void gemm_tile_q(const GemmArgs& a, int bx, int by, u
   const int rows = min(R, a.M - m0);
   __syncthreads();  // the previous tile of this block is done with the LDS
 
-  // 1. row statistics (two rows per wave at a time, every chunk in flight)
+  // 1. row statistics: every row's chunks in flight at once, as many rows
+  // per wave as 16 loads per lane allow (a row's arithmetic is the same
+  // whatever the batching)
   if (!stage) {
     // A tile and statistics kept from the previous tile
   } else if (RMS || PREC == PSWA_PREC_FP8) {
-    for (int m = wave; m < rows; m += 2 * kWaves) {
-      float4 xs[2][8];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int mm = min(m + h * kWaves, rows - 1);
-        const size_t off = (size_t)map_row(a.xrow, m0 + mm) * a.ldx;
-#pragma unroll
-        for (int it = 0; it < 8; ++it) {
-          const int c = lane + 64 * it;
-          if (c < K4) {
-            if (AK == A_INT) {
-              const int4 xi = *reinterpret_cast<const int4*>(a.Xi + off + 4 * c);
-              xs[h][it] = make_float4(float(xi.x), float(xi.y), float(xi.z), float(xi.w));
-            } else {
-              xs[h][it] = *reinterpret_cast<const float4*>(a.X + off + 4 * c);
-            }
-          }
-        }
-      }
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        float ss = 0.f, mx = 0.f;
-#pragma unroll
-        for (int it = 0; it < 8; ++it) {
-          const int c = lane + 64 * it;
-          if (c < K4) {
-            const float4 x = xs[h][it];
-            if (RMS) ss = dot4(x, x, ss);
-            if (PREC == PSWA_PREC_FP8) {
-              float4 g = make_float4(1.f, 1.f, 1.f, 1.f);
-              if (RMS) g = *reinterpret_cast<const float4*>(a.gain + 4 * c);
-              if (AK == A_INT) g = *reinterpret_cast<const float4*>(a.xscale + 4 * c);
-              mx = fmaxf(mx, fmaxf(fmaxf(fabsf(x.x * g.x), fabsf(x.y * g.y)),
-                                   fmaxf(fabsf(x.z * g.z), fabsf(x.w * g.w))));
-            }
-          }
-        }
-        if (RMS) ss = wave_sum(ss);
-        if (PREC == PSWA_PREC_FP8) mx = wave_max(mx);
-        const int mm = m + h * kWaves;
-        if (lane == 0 && mm < rows) {
-          rstd[mm] = RMS ? 1.0f / sqrtf(ss / float(K) + kEps) : 1.0f;
-          // FP8 rows are stored as value * (448 / max); a zero row stays zero
-          rmul[mm] = PREC == PSWA_PREC_FP8 ? (mx > 0.f ? kFp8Max / mx : 1.0f) : 1.0f;
-        }
-      }
-    }
+    const int cpr = (K4 + 63) / 64;  // float4 chunks per row and lane
+    if (cpr <= 1) row_stats<AK, RMS, PREC, 1>(a, m0, rows, rstd, rmul);
+    else if (cpr <= 2) row_stats<AK, RMS, PREC, 2>(a, m0, rows, rstd, rmul);
+    else if (cpr <= 4) row_stats<AK, RMS, PREC, 4>(a, m0, rows, rstd, rmul);
+    else row_stats<AK, RMS, PREC, 8>(a, m0, rows, rstd, rmul);
   } else {
     if (tid < R) {
       rstd[tid] = 1.0f;
