@@ -10,6 +10,9 @@ frame); inputs resident in HBM, symbols read from device memory. Paths
   mixed<N>:<prec>  -- N frames of the mixed batch (15x20, 34x60, 45x80 and
                       68x120 in equal numbers, I- and P-frames alternating)
                       in one persistent launch;
+  student4k:<prec> -- one 4K-shaped I-frame and one P-frame (135x240x192)
+                      decoded by the 2-layer d=128 student model (weights
+                      at initialization: the rate does not depend on them);
 with <prec> one of fp32, bf16, fp8. Persistent paths split their frames into
 groups that run behind their own barriers; the library's autotuner picks the
 grouping and row tile, and runs replay a captured HIP graph, unless told not
@@ -44,7 +47,7 @@ ROLE_KERNEL = {
     "o_gemm": "k_gemm<0, false, 1, 2> (residual epilogue, K=384)",
     "layer_attention": "k_attn<48>",
 }
-DEFAULT_PATHS = "plain:fp32,batch32:bf16,batch32:fp8,mixed32:bf16"
+DEFAULT_PATHS = "plain:fp32,batch32:bf16,batch32:fp8,mixed32:bf16,student4k:bf16"
 
 
 def parse():
@@ -162,9 +165,16 @@ def roofline(pswa, fn, steps, prec, workload):
 
 
 def batch_frames(synth, cfg, kind, n, dseed):
-    """Inputs of a batch path: n 1080p I-frames, or n frames of the mixed
-    batch (sizes in equal numbers, I- and P-frames alternating per size)."""
+    """Inputs of a batch path: n 1080p I-frames, n frames of the mixed batch
+    (sizes in equal numbers, I- and P-frames alternating per size), or the
+    4K-shaped I- and P-frame of the student workload."""
     frames = []
+    if kind == "student4k":
+        s0 = synth.CONFIG_SEEDS["4k_student"][0]
+        for k, n_prev in enumerate((0, 2)):
+            y, z, pv = synth.frame_inputs(synth.STUDENT, synth.FrameCfg(135, 240, n_prev), s0 + k)
+            frames.append({"latents": y, "hyper": z, "prev": pv})
+        return frames
     for k in range(n):
         if kind == "batch":
             fc, seed = synth.FrameCfg(68, 120), dseed + 1000 * k
@@ -204,15 +214,17 @@ def main():
     sym_frame = H * W * cfg.C
     models = {}
 
-    def model_for(prec):
-        if prec not in models:
-            models[prec] = pswa.Model(cfg, Wt, prec)
-        return models[prec]
+    def model_for(prec, student=False):
+        key = (prec, student)
+        if key not in models:
+            models[key] = (pswa.Model(synth.STUDENT, synth.model_weights(synth.STUDENT, 51), prec)
+                           if student else pswa.Model(cfg, Wt, prec))
+        return models[key]
 
     paths, runners, keep = {}, {}, []
     for spec in args.paths.split(","):
         kind, prec = spec.split(":")
-        model = model_for(prec)
+        model = model_for(prec, student=kind == "student4k")
         if kind == "plain":
             mem = torch.empty(pswa.pswa_state_bytes(model, H, W), dtype=torch.uint8,
                               device="cuda")
@@ -229,8 +241,11 @@ def main():
                            "value": sym_frame * args.steps / dt}
             runners[spec] = plain
         else:
-            base = "batch" if kind.startswith("batch") else "mixed"
-            n = int(kind[len(base):])
+            if kind == "student4k":
+                base, n = "student4k", 2
+            else:
+                base = "batch" if kind.startswith("batch") else "mixed"
+                n = int(kind[len(base):])
             frames = batch_frames(synth, cfg, base, n, dseed)
             nsym = sum(f["latents"].size for f in frames)
             b = pswa.Batch(model, frames)
@@ -268,8 +283,9 @@ def main():
     base = paths.get("plain:fp32", {}).get("value")
     for p in paths.values():
         p["vs_plain_fp32"] = (p["value"] / base) if base else None
-    # the headline is a 1080p-shaped path (the mixed batch is reported beside it)
-    cand = [k for k in paths if not k.startswith("mixed")] or list(paths)
+    # the headline is a 1080p-shaped path (the mixed batch and the student's
+    # 4K frames are reported beside it)
+    cand = [k for k in paths if k.split(":")[0].startswith(("plain", "batch"))] or list(paths)
     best = max(cand, key=lambda k: paths[k]["value"])
     hp = paths[best]
     kind, prec = best.split(":")

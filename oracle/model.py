@@ -106,6 +106,57 @@ def cyclic_step(i, j, s: int = 4):
     return (np.asarray(i) % s + np.asarray(j) % s) % s
 
 
+def full_window(r: int) -> list[tuple[int, int]]:
+    """Offsets of the full (2r+1) x (2r+1) window in raster order (the query
+    itself at index r(2r+1) + r): the cyclic schedule's spatial slots."""
+    return [(a, b) for a in range(-r, r + 1) for b in range(-r, r + 1)]
+
+
+def schedule_step(cfg, i, j):
+    """Decoding step of position (i, j): j + s i (wavefront, s = r + 1), or
+    (i + j) mod cycle (the paper's cyclic pattern, Fig. 2a)."""
+    if cfg.cycle:
+        return cyclic_step(i, j, cfg.cycle)
+    return step_index(np.asarray(i), np.asarray(j), wavefront_slope(cfg.r))
+
+
+def acc_slots(cfg) -> list[tuple[int, int]]:
+    """Spatial key slots of the accumulator: the causal window (wavefront),
+    or the full window masked to strictly earlier steps (cyclic)."""
+    return full_window(cfg.r) if cfg.cycle else causal_window(cfg.r)
+
+
+def layer_slots(cfg) -> list[tuple[int, int]]:
+    """Spatial key slots of a layer: the causal window plus the query
+    (wavefront), or the full window masked to steps up to the query's own
+    (cyclic: same-step positions see each other in the layers, Fig. 2b)."""
+    return full_window(cfg.r) if cfg.cycle else layer_window(cfg.r)
+
+
+def schedule_groups(cfg, H: int, W: int) -> list[np.ndarray]:
+    """Positions decoded together, step by step: the diagonals of the
+    wavefront, or for the cyclic schedule every position of one step (in
+    raster order)."""
+    if not cfg.cycle:
+        return diagonals(H, W, wavefront_slope(cfg.r))
+    ii, jj = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    st = cyclic_step(ii, jj, cfg.cycle)
+    return [np.argwhere(st == t).reshape(-1, 2) for t in range(cfg.cycle)]
+
+
+def _step_mask(cfg, H, W, a, b, strict):
+    """Whether the key at offset (a, b) is decoded early enough for each
+    query: always, in the wavefront's causal windows; step(key) < step(p)
+    (strict, accumulator) or <= (layers) for the cyclic schedule. Out-of-
+    frame keys are masked separately."""
+    if not cfg.cycle:
+        return np.ones((H, W), dtype=bool)
+    ii, jj = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    sp = cyclic_step(ii, jj, cfg.cycle)
+    sq = cyclic_step(ii + a, jj + b, cfg.cycle)
+    return sq < sp if strict else sq <= sp
+
+
 # --------------------------------------------------------------------------
 # Building blocks
 # --------------------------------------------------------------------------
@@ -218,10 +269,10 @@ def forward(cfg, Wt, y, z, prev=None, keep=False):
     q = linear(rmsnorm(h, _w(Wt, "acc.gq")), _w(Wt, "acc.Wq"))
     bias = _w(Wt, "acc.bias")
     slots = []
-    for n, (a, b) in enumerate(causal_window(r)):
+    for n, (a, b) in enumerate(acc_slots(cfg)):
         Ks, valid = _shift(K, a, b)
         Vs, _ = _shift(V, a, b)
-        slots.append((Ks, Vs, valid, bias[:, n]))
+        slots.append((Ks, Vs, valid & _step_mask(cfg, H, W, a, b, True), bias[:, n]))
     knull = np.broadcast_to(_w(Wt, "acc.knull"), (H, W, d))
     vnull = np.broadcast_to(_w(Wt, "acc.vnull"), (H, W, d))
     slots.append((knull, vnull, np.ones((H, W), bool), np.zeros(heads)))
@@ -233,7 +284,7 @@ def forward(cfg, Wt, y, z, prev=None, keep=False):
     if prev is not None:
         e_prev = [latent_embed(Wt, prev[t]) for t in range(2)]
 
-    n_sp = len(layer_window(r))
+    n_sp = len(layer_slots(cfg))
     for l in range(cfg.L):
         p = f"layer{l}."
         u = rmsnorm(x, _w(Wt, p + "g1"))
@@ -241,10 +292,10 @@ def forward(cfg, Wt, y, z, prev=None, keep=False):
         q, k, v = qkv[..., :d], qkv[..., d:2 * d], qkv[..., 2 * d:]
         bias = _w(Wt, p + "bias")
         slots = []
-        for n, (a, b) in enumerate(layer_window(r)):
+        for n, (a, b) in enumerate(layer_slots(cfg)):
             Ks, valid = _shift(k, a, b)
             Vs, _ = _shift(v, a, b)
-            slots.append((Ks, Vs, valid, bias[:, n]))
+            slots.append((Ks, Vs, valid & _step_mask(cfg, H, W, a, b, False), bias[:, n]))
         if e_prev is not None:
             tkv = [temporal_keys_values(Wt, l, e_prev[t]) for t in range(2)]
             for n, (tau, a, b) in enumerate(temporal_window(r)):
@@ -283,9 +334,10 @@ def forward_sequential(cfg, Wt, y, z, groups, prev=None):
     """Decode in the given order and return dict(mu, sigma, lsig).
 
     groups: list of int arrays [n, 2] of (i, j). Each group is predicted at
-    once from caches filled by earlier groups only; every W-(p) cell of a
-    group member must have been decoded in an earlier group (checked), and
-    each group's own latents are read only after its prediction.
+    once from caches filled by earlier groups only; every cell the
+    accumulator may see must have been decoded in an earlier group, and
+    every cell a layer may see must be decoded or in the same group
+    (checked); each group's own latents are read only after its prediction.
     This is the decoder's view: it never touches y of undecoded positions."""
     H, W, C = y.shape
     d, heads, r, L = cfg.d, cfg.heads, cfg.r, cfg.L
@@ -302,7 +354,16 @@ def forward_sequential(cfg, Wt, y, z, groups, prev=None):
         tkv = [[temporal_keys_values(Wt, l, e_prev[t]) for t in range(2)]
                for l in range(L)]
 
-    cw, lw, tw = causal_window(r), layer_window(r), temporal_window(r)
+    cw, lw, tw = acc_slots(cfg), layer_slots(cfg), temporal_window(r)
+
+    def seen(i, j, a, b, strict):
+        # in the frame and, for the cyclic schedule, decoded early enough
+        if not (0 <= i + a < H and 0 <= j + b < W):
+            return False
+        if not cfg.cycle:
+            return True
+        sp, sq = cyclic_step(i, j, cfg.cycle), cyclic_step(i + a, j + b, cfg.cycle)
+        return sq < sp if strict else sq <= sp
 
     def attend(qv, keys, vals, biases):
         # qv [d]; keys/vals [n, d]; biases [n, heads]
@@ -317,10 +378,16 @@ def forward_sequential(cfg, Wt, y, z, groups, prev=None):
 
     for grp in groups:
         grp = np.asarray(grp).reshape(-1, 2)
+        in_grp = np.zeros((H, W), dtype=bool)
+        in_grp[grp[:, 0], grp[:, 1]] = True
         for i, j in grp:
             for a, b in cw:
-                if 0 <= i + a < H and 0 <= j + b < W:
+                if seen(i, j, a, b, True):
                     assert decoded[i + a, j + b], "order violates the mask"
+            for a, b in lw:
+                if seen(i, j, a, b, False):
+                    assert decoded[i + a, j + b] or in_grp[i + a, j + b], \
+                        "order violates the layer mask"
         n = len(grp)
         gi, gj = grp[:, 0], grp[:, 1]
         h = h_all[gi, gj]
@@ -331,7 +398,7 @@ def forward_sequential(cfg, Wt, y, z, groups, prev=None):
         for g, (i, j) in enumerate(grp):
             ks, vs, bs = [], [], []
             for s_, (a, b) in enumerate(cw):
-                if 0 <= i + a < H and 0 <= j + b < W:
+                if seen(i, j, a, b, True):
                     ks.append(acc_cache[i + a, j + b, :d])
                     vs.append(acc_cache[i + a, j + b, d:])
                     bs.append(bias[:, s_])
@@ -349,7 +416,7 @@ def forward_sequential(cfg, Wt, y, z, groups, prev=None):
             for g, (i, j) in enumerate(grp):
                 ks, vs, bs = [], [], []
                 for s_, (a, b) in enumerate(lw):
-                    if 0 <= i + a < H and 0 <= j + b < W:
+                    if seen(i, j, a, b, False):
                         ks.append(kv_cache[l, i + a, j + b, :d])
                         vs.append(kv_cache[l, i + a, j + b, d:])
                         bs.append(bias[:, s_])

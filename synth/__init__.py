@@ -33,15 +33,17 @@ __all__ = [
     "ModelCfg", "FrameCfg", "TINY", "FULL", "STUDENT",
     "bias_sizes", "weight_shapes", "model_weights",
     "latent_frame", "hyper_frame", "prev_frames", "frame_inputs",
-    "BATCH_MIX", "CONFIG_SEEDS",
+    "BATCH_MIX", "CONFIG_SEEDS", "CYCLIC", "TINY_CYCLIC",
 ]
 
 
 @dataclasses.dataclass(frozen=True)
 class ModelCfg:
     """Shape of a context model: L layers of width d with `heads` heads,
-    causal window k x k, SwiGLU hidden width mlp_ratio * d, C latent
-    channels and Ch hyperprior channels."""
+    window k x k, SwiGLU hidden width mlp_ratio * d, C latent channels and
+    Ch hyperprior channels. cycle = 0: wavefront schedule t = j + s i with
+    the causal half-window; cycle = s >= 2: the cyclic schedule
+    step = (i + j) mod s with the full window masked by step."""
     L: int
     d: int
     heads: int
@@ -49,6 +51,7 @@ class ModelCfg:
     mlp_ratio: int
     C: int
     Ch: int
+    cycle: int = 0
 
     @property
     def dh(self) -> int:
@@ -87,6 +90,11 @@ FULL = ModelCfg(L=6, d=384, heads=8, window=9, mlp_ratio=4, C=192, Ch=128)
 # Distilled student: 2 layers, d = 128, 4 heads, causal 9x9 window.
 STUDENT = ModelCfg(L=2, d=128, heads=4, window=9, mlp_ratio=4, C=192, Ch=128)
 
+# The cyclic schedule of the paper (full 7x7 window, s = 4 steps per frame)
+# on the 1080p model's widths, and its tiny counterpart.
+CYCLIC = ModelCfg(L=6, d=384, heads=8, window=7, mlp_ratio=4, C=192, Ch=128, cycle=4)
+TINY_CYCLIC = ModelCfg(L=2, d=64, heads=4, window=5, mlp_ratio=4, C=32, Ch=16, cycle=4)
+
 # Batched decode mix: 8 frames of each grid size, I and P alternating.
 BATCH_MIX = [(15, 20), (34, 60), (45, 80), (68, 120)]
 
@@ -97,17 +105,22 @@ CONFIG_SEEDS = {
     "1080p_P": (20, 11),
     "batch": (30, 11),
     "4k_student": (40, 11),
+    "1080p_cyclic": (50, 12),
 }
 
 
 def bias_sizes(cfg: ModelCfg) -> tuple[int, int, int]:
     """Number of relative-bias slots: (accumulator, spatial layer, temporal
-    layer). The causal window holds r rows of 2r+1 above and r to the left
-    (2r(r+1) cells); the layer window adds the query itself; the temporal
+    layer). Wavefront schedule: the causal window holds r rows of 2r+1 above
+    and r to the left (2r(r+1) cells) and the layer window adds the query
+    itself. Cyclic schedule: both use the full (2r+1)^2 window. The temporal
     window is (2r+1)^2 cells in each of two previous frames."""
     r = cfg.r
+    k2 = (2 * r + 1) ** 2
+    if cfg.cycle:
+        return k2, k2, 2 * k2
     n_acc = 2 * r * (r + 1)
-    return n_acc, n_acc + 1, 2 * (2 * r + 1) ** 2
+    return n_acc, n_acc + 1, 2 * k2
 
 
 def weight_shapes(cfg: ModelCfg) -> list[tuple[str, tuple[int, ...]]]:

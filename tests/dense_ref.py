@@ -40,10 +40,25 @@ def bias_slot(da, db, r):
     return 2 * r * (r + 1)
 
 
-def temporal_slot(tau, da, db, r):
-    n_sp = 2 * r * (r + 1) + 1
+def temporal_slot(tau, da, db, r, n_sp=None):
+    n_sp = 2 * r * (r + 1) + 1 if n_sp is None else n_sp
     k = 2 * r + 1
     return n_sp + (tau - 1) * k * k + (da + r) * k + (db + r)
+
+
+# The cyclic schedule (cycle c): key k is visible to the accumulator of query
+# p when it lies in the full window and ((i_k + j_k) mod c) < ((i_p + j_p)
+# mod c); to a layer when the step is <=. Bias slot: raster index in the
+# (2r+1)^2 window.
+def cyc_visible(ip, jp, ik, jk, r, c, strict):
+    if abs(ik - ip) > r or abs(jk - jp) > r:
+        return False
+    sp, sk = (ip + jp) % c, (ik + jk) % c
+    return sk < sp if strict else sk <= sp
+
+
+def cyc_slot(da, db, r):
+    return (da + r) * (2 * r + 1) + (db + r)
 
 
 def _rms(x, g):
@@ -75,12 +90,16 @@ def dense_forward(cfg, Wt, y, z, prev=None):
     K = torch.cat([kv[:, :d], w["acc.knull"][None]], 0)
     V = torch.cat([kv[:, d:], w["acc.vnull"][None]], 0)
     q = F.linear(_rms(h, w["acc.gq"]), w["acc.Wq"])
+    cyc = getattr(cfg, "cycle", 0)
     mask = torch.full((nh, N, N + 1), -math.inf, dtype=torch.float64)
     mask[:, :, N] = 0.0
     for p in range(N):
         for k in range(N):
             da, db = int(ii[k] - ii[p]), int(jj[k] - jj[p])
-            if acc_visible(da, db, r):
+            if cyc:
+                if cyc_visible(int(ii[p]), int(jj[p]), int(ii[k]), int(jj[k]), r, cyc, True):
+                    mask[:, p, k] = w["acc.bias"][:, cyc_slot(da, db, r)]
+            elif acc_visible(da, db, r):
                 mask[:, p, k] = w["acc.bias"][:, bias_slot(da, db, r)]
     a = F.scaled_dot_product_attention(heads_(q), heads_(K), heads_(V),
                                        attn_mask=mask)
@@ -105,14 +124,18 @@ def dense_forward(cfg, Wt, y, z, prev=None):
         V = torch.cat(Vs, 0)
         mask = torch.full((nh, N, K.shape[0]), -math.inf, dtype=torch.float64)
         b = w[p_ + "bias"]
+        n_sp = (2 * r + 1) ** 2 if cyc else None
         for p in range(N):
             for k in range(N):
                 da, db = int(ii[k] - ii[p]), int(jj[k] - jj[p])
-                if acc_visible(da, db, r) or (da == 0 and db == 0):
+                if cyc:
+                    if cyc_visible(int(ii[p]), int(jj[p]), int(ii[k]), int(jj[k]), r, cyc, False):
+                        mask[:, p, k] = b[:, cyc_slot(da, db, r)]
+                elif acc_visible(da, db, r) or (da == 0 and db == 0):
                     mask[:, p, k] = b[:, bias_slot(da, db, r)]
                 if e_prev is not None and abs(da) <= r and abs(db) <= r:
                     for t in range(2):
-                        mask[:, p, (t + 1) * N + k] = b[:, temporal_slot(t + 1, da, db, r)]
+                        mask[:, p, (t + 1) * N + k] = b[:, temporal_slot(t + 1, da, db, r, n_sp)]
         a = F.scaled_dot_product_attention(heads_(q), heads_(K), heads_(V),
                                            attn_mask=mask)
         yr = x + F.linear(a.transpose(0, 1).reshape(N, d), w[p_ + "Wo"])
