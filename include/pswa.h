@@ -69,7 +69,12 @@ enum { PSWA_SRC_DEVICE = 0, PSWA_SRC_BITSTREAM = 1 };
  * <= 256; Ch <= 512. Other shapes are rejected with PSWA_E_ARG. */
 typedef struct {
   int32_t L, d, heads, window, mlp_ratio, C, Ch;
-  int32_t prec; /* pswa_precision */
+  int32_t prec;  /* pswa_precision */
+  int32_t cycle; /* decoding schedule: 0 = wavefront t = j + s i with the causal
+                    half-window (s = r + 1); c in [2, 16] = the cyclic pattern
+                    step = (i + j) mod c over the full window, the accumulator
+                    seeing strictly earlier steps and the layers steps up to
+                    the query's own (Sec. 3.2, Fig. 2) */
 } pswa_model_desc;
 
 /* Frame shape. Hh = ceil(H/4), Wh = ceil(W/4) (the hyperprior is at a
@@ -285,7 +290,8 @@ void pswa_batch_destroy(pswa_batch* batch);
 typedef struct pswa_trainer pswa_trainer;
 
 /* Workspace for batches of up to max_crops crops of H x W (0 if invalid;
- * the model must be FP32 and max_crops * H * W <= 2^22). */
+ * the model must be FP32 with the wavefront schedule (cycle 0) and
+ * max_crops * H * W <= 2^22). */
 size_t pswa_train_workspace_bytes(const pswa_model_desc* student, int max_crops, int H, int W);
 /* Initial weights from a host blob in the documented order (see
  * pswa_model_create). Waits for the upload. */
@@ -338,14 +344,15 @@ pswa_status pswa_cdf_select(const float* d_mean, const float* d_log_scale, size_
 pswa_status pswa_cdf_tables(uint32_t* h_radius, uint32_t* h_offset, uint16_t* h_freq,
                             size_t freq_cap);
 
-/* Range-code a frame's symbols in decode order (steps t = 0..T-1, rows i
- * ascending within a step, channels 0..C-1), each with its table: symbol
- * v is coded as bin v - c + R when |v - c| <= R, else as the escape bin
- * followed by the sign and an order-0 Exp-Golomb code of |v - c| - R - 1
- * in equiprobable bits. All arrays are host [H][W][C]. window is the
- * model's window (it fixes the slope s). Writes at most cap bytes to out. */
+/* Range-code a frame's symbols in decode order (steps t = 0..T-1; within a
+ * step rows i ascending for the wavefront, raster order for the cyclic
+ * schedule; channels 0..C-1), each with its table: symbol v is coded as bin
+ * v - c + R when |v - c| <= R, else as the escape bin followed by the sign
+ * and an order-0 Exp-Golomb code of |v - c| - R - 1 in equiprobable bits.
+ * All arrays are host [H][W][C]. window and cycle are the model's (they fix
+ * the schedule). Writes at most cap bytes to out. */
 pswa_status pswa_range_encode(const pswa_frame_desc* frame, int32_t C, int32_t window,
-                              const int32_t* h_symbols, const int32_t* h_center,
+                              int32_t cycle, const int32_t* h_symbols, const int32_t* h_center,
                               const uint16_t* h_index, uint8_t* out, size_t cap,
                               size_t* out_bytes);
 

@@ -105,18 +105,18 @@ Plan make_plan(const NetDims& x, int n, const pswa_batch_frame* fr) {
     const pswa_frame_desc& d = fr[f].frame;
     p.finfo.push_back(FrameInfo{d.H, d.W, off, d.n_prev});
     off += d.H * d.W;
-    const int T = steps_of(d.H, d.W, x.s);
+    const int T = sched_steps(x, d.H, d.W);
     p.T = std::max(p.T, T);
     p.steps_cap += T;
     int mf = 0;
-    for (int t = 0; t < T; ++t) mf = std::max(mf, diag_len(d.H, d.W, x.s, t));
+    for (int t = 0; t < T; ++t) mf = std::max(mf, sched_len(x, d.H, d.W, t));
     p.rows_cap += mf;
     p.any_p = p.any_p || d.n_prev > 0;
   }
   p.HWt = off;
   for (int t = 0; t < p.T; ++t) {
     int cnt = 0;
-    for (int f = 0; f < n; ++f) cnt += diag_len(fr[f].frame.H, fr[f].frame.W, x.s, t);
+    for (int f = 0; f < n; ++f) cnt += sched_len(x, fr[f].frame.H, fr[f].frame.W, t);
     p.Mmax = std::max(p.Mmax, cnt);
   }
   return p;
@@ -283,7 +283,7 @@ pswa_status apply_groups(pswa_batch* b, int fpg, int bpg, hipStream_t st) {
   size_t row_off = 0, tab_off = 0;
   for (GroupPlan& g : groups) {
     std::sort(g.frames.begin(), g.frames.end());
-    for (int f : g.frames) g.T = std::max(g.T, steps_of(b->finfo[f].H, b->finfo[f].W, x.s));
+    for (int f : g.frames) g.T = std::max(g.T, sched_steps(x, b->finfo[f].H, b->finfo[f].W));
     g.row_off = row_off;
     g.tab_off = tab_off;
     g.pos_off = gpos.size();
@@ -292,13 +292,11 @@ pswa_status apply_groups(pswa_batch* b, int fpg, int bpg, hipStream_t st) {
       int cnt = 0;
       for (int f : g.frames) {
         const FrameInfo& fi = b->finfo[f];
-        for (int i = 0; i < fi.H; ++i) {
-          const int j = t - x.s * i;
-          if (j < 0 || j >= fi.W) continue;
+        sched_for_each(x, fi.H, fi.W, t, [&](int i, int j) {
           gpos.push_back(fi.off + i * fi.W + j);
           fid.push_back(f);
           ++cnt;
-        }
+        });
       }
       g.row_start[t + 1] = g.row_start[t] + cnt;
       g.Mmax = std::max(g.Mmax, cnt);
@@ -411,9 +409,7 @@ void count_work(pswa_batch* b, const std::vector<GemmArgs>& gt,
     for (int k = 0; k < na; ++k) {
       const AttnArgs& a = at[(size_t)t * na + k];
       by += attn_alg_bytes(a);
-      const int k1 = 2 * a.r + 1;
-      const double keys = 2.0 * a.r * (a.r + 1) + (a.include_self ? 1 : 0) +
-                          (a.knull ? 1 : 0) + (a.tkv ? 2.0 * k1 * k1 : 0.0);
+      const double keys = attn_slots(a);
       fl += double(a.M) * a.heads * keys * 4.0 * a.dh;
     }
     by += 16.0 * stb[t].M * x.C + 4.0 * stb[t].M;  // symbols and bits

@@ -298,7 +298,8 @@ __device__ __forceinline__ void attn_item(const AttnArgs& a, int item, bool live
   const int pi = lp / fi.W, pj = lp % fi.W;
   const int r = a.r, k1 = 2 * r + 1;
   const int n_causal = 2 * r * (r + 1);
-  const int n_sp = n_causal + (a.include_self ? 1 : 0);
+  const int n_sp = a.cycle ? k1 * k1 : n_causal + (a.include_self ? 1 : 0);
+  const int step_p = a.cycle ? (pi + pj) % a.cycle : 0;
   const bool temporal = a.tkv && fi.n_prev > 0;
   const int n_tm = temporal ? 2 * k1 * k1 : 0;
   const int n_keys = n_sp + (a.knull ? 1 : 0) + n_tm;
@@ -328,7 +329,7 @@ __device__ __forceinline__ void attn_item(const AttnArgs& a, int item, bool live
     float b = 0.f;
     if (kk < n_sp) {
       int da, db;
-      if (kk < r * k1) {
+      if (a.cycle || kk < r * k1) {  // cyclic: the full window in raster order
         da = kk / k1 - r;
         db = kk % k1 - r;
       } else if (kk < n_causal) {
@@ -340,6 +341,10 @@ __device__ __forceinline__ void attn_item(const AttnArgs& a, int item, bool live
       }
       const int ki = pi + da, kj = pj + db;
       if (ki < 0 || ki >= fi.H || kj < 0 || kj >= fi.W) continue;
+      if (a.cycle) {  // decoded early enough: strictly (accumulator) or not
+        const int step_k = (ki + kj) % a.cycle;
+        if (a.include_self ? step_k > step_p : step_k >= step_p) continue;
+      }
       kp = a.kv + (size_t)(fi.off + ki * fi.W + kj) * 2 * d + hd * DH;
       vp = kp + d;
       b = a.bias[hd * a.nbias + kk];

@@ -102,16 +102,6 @@ __global__ void k_cdf_select(const float* mean, const float* lsig, size_t n, flo
 // Wavefront order of all positions: step t = j + s*i, rows ascending within
 // a step. Position (i, j) lands at start(t) + (i - i_lo(t)), where start(t)
 // counts the positions of earlier steps and i_lo(t) is the first row on t.
-__global__ void k_fill_positions(int H, int W, int s, int* pos_all) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= H * W) return;
-  const int i = p / W, j = p % W;
-  const int t = j + s * i;
-  long start = 0;
-  for (int ii = 0; ii < H; ++ii) start += min(max(t - s * ii, 0), W);
-  const int i_lo = max(0, (t - W + s) / s);
-  pos_all[start + (i - i_lo)] = p;
-}
 
 inline unsigned blocks_for(long n, int t) { return unsigned((n + t - 1) / t); }
 
@@ -191,9 +181,9 @@ double gemm_alg_bytes(const GemmArgs& a, Epi epi) {
 }
 
 double attn_alg_bytes(const AttnArgs& a) {
-  const int k1 = 2 * a.r + 1;
-  const double keys = 2.0 * a.r * (a.r + 1) + (a.include_self ? 1 : 0) + (a.knull ? 1 : 0) +
-                      (a.tkv ? 2.0 * k1 * k1 : 0.0);
+  // every slot's K and V rows (for the cyclic schedule an upper bound: the
+  // step mask hides part of the window)
+  const double keys = attn_slots(a);
   // K and V rows of every window slot, the query and the output
   return double(a.M) * (keys * 2.0 * a.d * 4.0 + 2.0 * a.d * 4.0);
 }
@@ -212,9 +202,7 @@ void attention_f32(const AttnArgs& a, hipStream_t s) {
   const int ev = prof_begin(s);
   attention_dispatch(a, s);
   if (ev >= 0) {
-    const int k1 = 2 * a.r + 1;
-    const double keys = 2.0 * a.r * (a.r + 1) + (a.include_self ? 1 : 0) + (a.knull ? 1 : 0) +
-                        (a.tkv ? 2.0 * k1 * k1 : 0.0);
+    const double keys = attn_slots(a);
     prof_end(ev, s, a.role, attn_alg_bytes(a), double(a.M) * a.heads * keys * 4.0 * a.dh);
   }
 }
@@ -258,9 +246,5 @@ void cdf_select(const float* mean, const float* lsig, size_t n, float ln_smin, f
                      n, ln_smin, inv_delta, center, index);
 }
 
-void fill_positions(int H, int W, int s, int* pos_all, hipStream_t st) {
-  hipLaunchKernelGGL(k_fill_positions, dim3(blocks_for((long)H * W, 256)), dim3(256), 0, st, H,
-                     W, s, pos_all);
-}
 
 }  // namespace pswa

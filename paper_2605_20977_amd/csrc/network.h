@@ -40,6 +40,7 @@ struct DevWeights {
 
 struct NetDims {
   int L, d, heads, dh, r, s, F, C, Ch, n_acc, n_sp, n_tm;
+  int cycle;  // 0: wavefront schedule; c: cyclic schedule of c steps
   float ln_smin, ln_smax, inv_delta;
 };
 
@@ -106,6 +107,7 @@ __host__ __device__ inline AttnArgs attn_base(const NetDims& x, const PassCtx& c
   a.frame0 = c.frame0;
   a.HWt = c.HWt;
   a.r = x.r;
+  a.cycle = x.cycle;
   a.heads = x.heads;
   a.dh = x.dh;
   a.d = x.d;

@@ -52,14 +52,6 @@ bool valid_frame(const pswa_frame_desc* f, std::string* why) {
   return true;
 }
 
-int diag_len(int H, int W, int s, int t) {
-  int n = 0;
-  for (int i = 0; i < H; ++i) {
-    const int j = t - s * i;
-    if (j >= 0 && j < W) ++n;
-  }
-  return n;
-}
 
 Acts take_acts(Layout& L, const NetDims& x, size_t rows) {
   Acts a;
@@ -135,6 +127,8 @@ bool valid_desc(const pswa_model_desc* d, std::string* why) {
   if (d->Ch < 1 || d->Ch > 512) return *why = "Ch out of range [1, 512]", false;
   if (d->prec != PSWA_FP32 && d->prec != PSWA_BF16 && d->prec != PSWA_FP8_E4M3)
     return *why = "unknown precision", false;
+  if (d->cycle != 0 && (d->cycle < 2 || d->cycle > 16))
+    return *why = "cycle must be 0 (wavefront) or in [2, 16]", false;
   return true;
 }
 
@@ -145,13 +139,15 @@ NetDims dims_of(const pswa_model_desc& m) {
   x.heads = m.heads;
   x.dh = m.d / m.heads;
   x.r = (m.window - 1) / 2;
-  x.s = x.r + 1;
+  x.cycle = m.cycle;
+  x.s = m.cycle ? m.cycle : x.r + 1;
   x.F = m.mlp_ratio * m.d;
   x.C = m.C;
   x.Ch = m.Ch;
-  x.n_acc = 2 * x.r * (x.r + 1);
-  x.n_sp = x.n_acc + 1;
-  x.n_tm = 2 * (2 * x.r + 1) * (2 * x.r + 1);
+  const int k2 = (2 * x.r + 1) * (2 * x.r + 1);
+  x.n_acc = m.cycle ? k2 : 2 * x.r * (x.r + 1);
+  x.n_sp = m.cycle ? k2 : x.n_acc + 1;
+  x.n_tm = 2 * k2;
   x.ln_smin = ln_sigma_min_f32();
   x.ln_smax = float(std::log(kSigmaMax));
   x.inv_delta = inv_delta_f32();
@@ -331,9 +327,9 @@ namespace {
 void plan_state(const NetDims& x, const pswa_frame_desc& f, void* base, pswa_state* st) {
   Layout L(base);
   const size_t HW = (size_t)f.H * f.W;
-  // n_t never exceeds min(H, ceil(W/s)): one position per row, s-spaced columns.
-  const int nmax = std::min(f.H, (f.W + x.s - 1) / x.s);
-  st->T = steps_of(f.H, f.W, x.s);
+  st->T = sched_steps(x, f.H, f.W);
+  int nmax = 1;
+  for (int t = 0; t < st->T; ++t) nmax = std::max(nmax, sched_len(x, f.H, f.W, t));
   st->nmax = nmax;
   st->h = L.take<float>(HW * x.d);
   st->acc_kv = L.take<float>(HW * 2 * x.d);
@@ -579,7 +575,7 @@ pswa_status pswa_decode_begin(const pswa_model* model, const pswa_frame_desc* fr
   const NetDims& x = model->x;
   S->start.assign(S->T + 1, 0);
   for (int t = 0; t < S->T; ++t)
-    S->start[t + 1] = S->start[t] + diag_len(frame->H, frame->W, x.s, t);
+    S->start[t + 1] = S->start[t] + sched_len(x, frame->H, frame->W, t);
   if (symbol_source == PSWA_SRC_DEVICE) {
     S->d_src = static_cast<const int32_t*>(src);
   } else {
@@ -594,7 +590,15 @@ pswa_status pswa_decode_begin(const pswa_model* model, const pswa_frame_desc* fr
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int HW = frame->H * frame->W;
   zero_ints(S->flag, 1, st);
-  fill_positions(frame->H, frame->W, x.s, S->pos_all, st);
+  {  // positions in decode order (step by step)
+    std::vector<int> pos;
+    pos.reserve(HW);
+    for (int t = 0; t < S->T; ++t)
+      sched_for_each(x, frame->H, frame->W, t, [&](int i, int j) { pos.push_back(i * frame->W + j); });
+    PSWA_HIP_TRY(hipMemcpyAsync(S->pos_all, pos.data(), pos.size() * sizeof(int),
+                                hipMemcpyHostToDevice, st));
+    PSWA_HIP_TRY(hipStreamSynchronize(st));
+  }
   hyper_embed(d_hyper, frame->Hh, frame->Wh, x.Ch, model->w.hyperW, model->w.P4, frame->H,
               frame->W, x.d, S->h, st);
   if (frame->n_prev) {
@@ -735,28 +739,37 @@ pswa_status pswa_range_decode_seq(const uint8_t* in, size_t in_bytes, size_t n,
 }
 
 pswa_status pswa_range_encode(const pswa_frame_desc* frame, int32_t C, int32_t window,
-                              const int32_t* h_symbols, const int32_t* h_center,
+                              int32_t cycle, const int32_t* h_symbols, const int32_t* h_center,
                               const uint16_t* h_index, uint8_t* out, size_t cap,
                               size_t* out_bytes) {
   if (!frame || !h_symbols || !h_center || !h_index || !out_bytes || (cap && !out))
     return fail(PSWA_E_ARG, "null pointer argument");
   if (C < 1 || window < 3 || window % 2 == 0 || frame->H < 1 || frame->W < 1)
     return fail(PSWA_E_SHAPE, "invalid C, window or frame size");
-  const int s = (window - 1) / 2 + 1;
+  if (cycle != 0 && (cycle < 2 || cycle > 16))
+    return fail(PSWA_E_ARG, "cycle must be 0 or in [2, 16]");
+  NetDims x{};
+  x.r = (window - 1) / 2;
+  x.cycle = cycle;
+  x.s = cycle ? cycle : x.r + 1;
   const int H = frame->H, W = frame->W;
   RangeEncoder enc(out, cap);
-  const int T = steps_of(H, W, s);
-  for (int t = 0; t < T; ++t)
-    for (int i = 0; i < H; ++i) {
-      const int j = t - s * i;
-      if (j < 0 || j >= W) continue;
+  const int T = sched_steps(x, H, W);
+  bool bad = false;
+  uint16_t bad_index = 0;
+  for (int t = 0; t < T && !bad; ++t)
+    sched_for_each(x, H, W, t, [&](int i, int j) {
       const size_t base = ((size_t)i * W + j) * C;
-      for (int c = 0; c < C; ++c) {
-        if (h_index[base + c] >= kTables)
-          return fail(PSWA_E_ARG, "table index %u out of range", h_index[base + c]);
+      for (int c = 0; c < C && !bad; ++c) {
+        if (h_index[base + c] >= kTables) {
+          bad = true;
+          bad_index = h_index[base + c];
+          return;
+        }
         enc.symbol(h_symbols[base + c], h_center[base + c], h_index[base + c]);
       }
-    }
+    });
+  if (bad) return fail(PSWA_E_ARG, "table index %u out of range", bad_index);
   enc.finish();
   *out_bytes = enc.bytes();
   if (enc.overflow()) return fail(PSWA_E_ARG, "output capacity %zu < %zu bytes", cap, enc.bytes());

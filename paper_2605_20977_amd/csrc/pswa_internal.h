@@ -108,8 +108,16 @@ struct AttnArgs {
   const float* knull;          // accumulator null slot (null in layer mode)
   const float* vnull;
   int include_self;            // layer mode: the query's own key
+  int cycle;                   // 0: causal half-window; c: full window, masked by
+                               // step (i + j) mod c (< for the accumulator, <= for layers)
   float* out; int ldo;         // [M][d]
 };
+// Key slots an attention row scans: spatial window (+ self), null, temporal.
+__host__ __device__ inline int attn_slots(const AttnArgs& a) {
+  const int k1 = 2 * a.r + 1;
+  const int sp = a.cycle ? k1 * k1 : 2 * a.r * (a.r + 1) + (a.include_self ? 1 : 0);
+  return sp + (a.knull ? 1 : 0) + (a.tkv ? 2 * k1 * k1 : 0);
+}
 void attention_f32(const AttnArgs& a, hipStream_t s);
 double attn_alg_bytes(const AttnArgs& a);
 
@@ -126,7 +134,6 @@ void symbol_bits(const int* pos, int M, int C, const int32_t* ydec, const float*
 void sum_f32(const float* v, size_t n, float* out, hipStream_t s);
 void cdf_select(const float* mean, const float* lsig, size_t n, float ln_smin,
                 float inv_delta, int32_t* center, uint16_t* index, hipStream_t s);
-void fill_positions(int H, int W, int s, int* pos_all, hipStream_t st);
 
 // -------------------------------------------------------- entropy coder
 constexpr int kScales = 64;

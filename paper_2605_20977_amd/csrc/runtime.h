@@ -50,8 +50,30 @@ NetDims model_dims(const pswa_model_desc& d);
 // tensor starting at a multiple of `align` floats; returns the total floats.
 size_t model_blob_spans(const NetDims& x, size_t align,
                         std::vector<std::pair<size_t, size_t>>* spans);
-inline int steps_of(int H, int W, int s) { return (W - 1) + s * (H - 1) + 1; }
-int diag_len(int H, int W, int s, int t);
+// Decoding schedule of a model. Wavefront (cycle 0): step t holds the
+// positions (i, t - s i), i ascending, s = r + 1, and a frame takes
+// (W - 1) + s (H - 1) + 1 steps. Cyclic (cycle c): step t holds every
+// (i, j) with (i + j) mod c = t, in raster order, and a frame takes c steps.
+inline int sched_steps(const NetDims& x, int H, int W) {
+  return x.cycle ? x.cycle : (W - 1) + x.s * (H - 1) + 1;
+}
+template <class F>
+void sched_for_each(const NetDims& x, int H, int W, int t, F f) {
+  if (x.cycle) {
+    for (int i = 0; i < H; ++i)
+      for (int j = ((t - i) % x.cycle + x.cycle) % x.cycle; j < W; j += x.cycle) f(i, j);
+  } else {
+    for (int i = 0; i < H; ++i) {
+      const int j = t - x.s * i;
+      if (j >= 0 && j < W) f(i, j);
+    }
+  }
+}
+inline int sched_len(const NetDims& x, int H, int W, int t) {
+  int n = 0;
+  sched_for_each(x, H, W, t, [&](int, int) { ++n; });
+  return n;
+}
 
 // Row activations for `rows` rows.
 struct Acts {

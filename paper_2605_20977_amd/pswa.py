@@ -33,7 +33,7 @@ class PswaError(RuntimeError):
 
 class ModelDesc(C.Structure):
     _fields_ = [(n, C.c_int32) for n in
-                ("L", "d", "heads", "window", "mlp_ratio", "C", "Ch", "prec")]
+                ("L", "d", "heads", "window", "mlp_ratio", "C", "Ch", "prec", "cycle")]
 
 
 class FrameDesc(C.Structure):
@@ -69,8 +69,8 @@ def _load():
         "pswa_state_destroy": (None, [vp]),
         "pswa_cdf_select": (i32, [vp, vp, sz, vp, vp, vp]),
         "pswa_cdf_tables": (i32, [vp, vp, vp, sz]),
-        "pswa_range_encode": (i32, [P(FrameDesc), C.c_int32, C.c_int32, vp, vp, vp, vp, sz,
-                                    P(sz)]),
+        "pswa_range_encode": (i32, [P(FrameDesc), C.c_int32, C.c_int32, C.c_int32, vp, vp, vp,
+                                    vp, sz, P(sz)]),
         "pswa_range_encode_seq": (i32, [sz, vp, vp, vp, vp, sz, P(sz)]),
         "pswa_range_decode_seq": (i32, [vp, sz, sz, vp, vp, vp]),
         "pswa_last_error": (C.c_char_p, []),
@@ -161,7 +161,8 @@ def _stream():
 
 def model_desc(cfg, prec="fp32") -> ModelDesc:
     return ModelDesc(cfg.L, cfg.d, cfg.heads, cfg.window, cfg.mlp_ratio, cfg.C, cfg.Ch,
-                     PRECISIONS[prec] if isinstance(prec, str) else int(prec))
+                     PRECISIONS[prec] if isinstance(prec, str) else int(prec),
+                     getattr(cfg, "cycle", 0))
 
 
 def frame_desc(H, W, n_prev=0) -> FrameDesc:
@@ -172,8 +173,12 @@ def blob_shapes(cfg) -> list[tuple[str, tuple]]:
     """(name, shape) of every parameter in the blob order the header
     documents; linear weights are [out_features][in_features]."""
     d, C, Ch, F, h, r = cfg.d, cfg.C, cfg.Ch, cfg.mlp_ratio * cfg.d, cfg.heads, (cfg.window - 1) // 2
-    n_acc = 2 * r * (r + 1)
-    n_lay = n_acc + 1 + 2 * (2 * r + 1) ** 2
+    k2 = (2 * r + 1) ** 2
+    if getattr(cfg, "cycle", 0):   # full window for the cyclic schedule
+        n_acc, n_lay = k2, k2 + 2 * k2
+    else:
+        n_acc = 2 * r * (r + 1)
+        n_lay = n_acc + 1 + 2 * k2
     out = [("hyper.W", (d, Ch)), ("hyper.P4", (16, d)), ("in.g", (C,)), ("in.W", (d, C)),
            ("acc.gq", (d,)), ("acc.Wq", (d, d)), ("acc.gkv", (d,)), ("acc.Wkv", (2 * d, d)),
            ("acc.knull", (d,)), ("acc.vnull", (d,)), ("acc.bias", (h, n_acc)),
@@ -540,7 +545,9 @@ def _u8cap(n_symbols):
     return 64 + 8 * n_symbols
 
 
-def pswa_range_encode(H, W, Cc, window, symbols, center, index) -> bytes:
+def pswa_range_encode(H, W, Cc, window, symbols, center, index, cycle=0) -> bytes:
+    """Range-code [H][W][C] symbols in the decode order of the schedule
+    (window and cycle of the model)."""
     fd = frame_desc(H, W, 0)
     sy = np.ascontiguousarray(symbols, dtype=np.int32)
     ce = np.ascontiguousarray(center, dtype=np.int32)
@@ -548,8 +555,9 @@ def pswa_range_encode(H, W, Cc, window, symbols, center, index) -> bytes:
     cap = _u8cap(sy.size)
     out = np.empty(cap, np.uint8)
     nb = C.c_size_t(0)
-    _check(_lib.pswa_range_encode(C.byref(fd), Cc, window, sy.ctypes.data, ce.ctypes.data,
-                                  ix.ctypes.data, out.ctypes.data, cap, C.byref(nb)))
+    _check(_lib.pswa_range_encode(C.byref(fd), Cc, window, int(cycle), sy.ctypes.data,
+                                  ce.ctypes.data, ix.ctypes.data, out.ctypes.data, cap,
+                                  C.byref(nb)))
     return out[:nb.value].tobytes()
 
 

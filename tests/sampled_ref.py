@@ -2,11 +2,13 @@
 
 The prediction at p = (i, j) depends only on a cone of positions: the last
 layer reads W(p), each layer below one window further, and the accumulator
-one causal window beyond that, so nothing farther than R = (L + 1) r rows
-above or columns aside matters; previous frames add rows down to i + r. The
-oracle run on the crop rows [i0, i + 1 (+ r for P-frames)), columns
-[j0, j + R + 1), with i0, j0 the multiples of 4 at or below i - R and j - R
-(so the hyperprior cells and sub-positions line up), therefore gives exactly
+one window beyond that, so nothing farther than R = (L + 1) r rows above or
+columns aside matters; previous frames add rows down to i + r, and the
+cyclic schedule (full windows) rows down to i + R. The oracle run on the crop
+rows [i0, i + 1 (+ r for P-frames, + R cyclic)), columns [j0, j + R + 1),
+with i0, j0 the multiples of 4 at or below i - R and j - R (so the
+hyperprior cells and sub-positions line up; for the cyclic schedule also
+i0 + j0 = 0 mod cycle, so every step index is kept), therefore gives exactly
 the full-frame value at p. tests/test_sampled_ref.py checks this against
 whole-frame oracle runs.
 """
@@ -19,11 +21,17 @@ def oracle_at(cfg, Wt, y, z, prev, positions):
     """{(i, j): dict(mu, sigma, lsig) [C]} from per-position crops."""
     H, W, _ = y.shape
     R = (cfg.L + 1) * cfg.r
+    cyc = getattr(cfg, "cycle", 0)
     out = {}
     for i, j in positions:
         i0 = max(0, i - R) // 4 * 4
         j0 = max(0, j - R) // 4 * 4
-        i1 = min(H, i + 1 + (cfg.r if prev is not None else 0))
+        if cyc:
+            while (i0 + j0) % cyc:
+                j0 -= 4
+            assert j0 >= 0, "crop origin cannot keep the step index"
+        below = R if cyc else (cfg.r if prev is not None else 0)
+        i1 = min(H, i + 1 + below)
         j1 = min(W, j + R + 1)
         yc = y[i0:i1, j0:j1]
         zc = z[i0 // 4:-(-i1 // 4), j0 // 4:-(-j1 // 4)]

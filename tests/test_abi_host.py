@@ -179,3 +179,19 @@ def test_student_accept_rule():
     assert pswa.pswa_student_accept(90.0, 100.0, 0.0)
     assert not pswa.pswa_student_accept(float("nan"), 100.0, 0.01)
     assert not pswa.pswa_student_accept(-1.0, 100.0, 0.01)
+
+
+def test_frame_encode_uses_cyclic_order():
+    """Cyclic schedule: steps t = 0..c-1, each in raster order."""
+    rng = np.random.default_rng(11)
+    H, W, Cc, k, cyc = 6, 7, 2, 7, 4
+    y, c, idx = _random_symbols(rng, H * W * Cc, 0.0)
+    y, c, idx = (a.reshape(H, W, Cc) for a in (y, c, idx))
+    data = P.pswa_range_encode(H, W, Cc, k, y, c, idx, cycle=cyc)
+    seq = [(i, j) for t in range(cyc) for i in range(H) for j in range(W) if (i + j) % cyc == t]
+    ys = np.concatenate([y[i, j] for i, j in seq])
+    cs = np.concatenate([c[i, j] for i, j in seq])
+    xs = np.concatenate([idx[i, j] for i, j in seq])
+    assert data == P.pswa_range_encode_seq(ys, cs, xs)
+    with pytest.raises(P.PswaError):
+        P.pswa_range_encode(H, W, Cc, k, y, c, idx, cycle=1)
