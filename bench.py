@@ -10,6 +10,9 @@ frame); inputs resident in HBM, symbols read from device memory. Paths
   mixed<N>:<prec>  -- N frames of the mixed batch (15x20, 34x60, 45x80 and
                       68x120 in equal numbers, I- and P-frames alternating)
                       in one persistent launch;
+  cyclic<N>:<prec>  -- N 1080p I-frames decoded with the paper's cyclic
+                      schedule (step = (i + j) mod 4, full 7x7 window: 4
+                      steps per frame) by a model of the same widths;
   student4k:<prec> -- one 4K-shaped I-frame and one P-frame (135x240x192)
                       decoded by the 2-layer d=128 student model (weights
                       at initialization: the rate does not depend on them);
@@ -47,7 +50,8 @@ ROLE_KERNEL = {
     "o_gemm": "k_gemm<0, false, 1, 2> (residual epilogue, K=384)",
     "layer_attention": "k_attn<48>",
 }
-DEFAULT_PATHS = "plain:fp32,batch32:bf16,batch32:fp8,mixed32:bf16,student4k:bf16"
+DEFAULT_PATHS = ("plain:fp32,batch32:bf16,batch32:fp8,mixed32:bf16,student4k:bf16,"
+                 "cyclic32:bf16")
 
 
 def parse():
@@ -176,7 +180,7 @@ def batch_frames(synth, cfg, kind, n, dseed):
             frames.append({"latents": y, "hyper": z, "prev": pv})
         return frames
     for k in range(n):
-        if kind == "batch":
+        if kind in ("batch", "cyclic"):
             fc, seed = synth.FrameCfg(68, 120), dseed + 1000 * k
         else:
             H, W = synth.BATCH_MIX[(k * len(synth.BATCH_MIX)) // n]
@@ -214,17 +218,25 @@ def main():
     sym_frame = H * W * cfg.C
     models = {}
 
-    def model_for(prec, student=False):
-        key = (prec, student)
+    def model_for(prec, kind="full"):
+        key = (prec, kind)
         if key not in models:
-            models[key] = (pswa.Model(synth.STUDENT, synth.model_weights(synth.STUDENT, 51), prec)
-                           if student else pswa.Model(cfg, Wt, prec))
+            if kind == "student":
+                models[key] = pswa.Model(synth.STUDENT, synth.model_weights(synth.STUDENT, 51),
+                                         prec)
+            elif kind == "cyclic":
+                models[key] = pswa.Model(
+                    synth.CYCLIC,
+                    synth.model_weights(synth.CYCLIC, synth.CONFIG_SEEDS["1080p_cyclic"][1]), prec)
+            else:
+                models[key] = pswa.Model(cfg, Wt, prec)
         return models[key]
 
     paths, runners, keep = {}, {}, []
     for spec in args.paths.split(","):
         kind, prec = spec.split(":")
-        model = model_for(prec, student=kind == "student4k")
+        model = model_for(prec, "student" if kind == "student4k"
+                          else "cyclic" if kind.startswith("cyclic") else "full")
         if kind == "plain":
             mem = torch.empty(pswa.pswa_state_bytes(model, H, W), dtype=torch.uint8,
                               device="cuda")
@@ -244,7 +256,7 @@ def main():
             if kind == "student4k":
                 base, n = "student4k", 2
             else:
-                base = "batch" if kind.startswith("batch") else "mixed"
+                base = next(b_ for b_ in ("batch", "mixed", "cyclic") if kind.startswith(b_))
                 n = int(kind[len(base):])
             frames = batch_frames(synth, cfg, base, n, dseed)
             nsym = sum(f["latents"].size for f in frames)
@@ -259,6 +271,7 @@ def main():
                 f, g = (int(v) for v in args.groups.split("x"))
                 b.set_groups(f, g)
             if not args.grid and not args.rtile and not args.groups:
+                print(f"{spec}: autotuning", file=sys.stderr, flush=True)
                 f, g, r, est = b.autotune(args.tune_cache, reps=2)
                 tuned = {"frames_per_group": f, "blocks_per_group": g, "rtile": r,
                          "est_ms": round(est, 2)}

@@ -595,6 +595,7 @@ pswa_status pswa_batch_autotune(pswa_batch* b, const char* cache_path, int reps,
   hipEvent_t e0, e1;
   PSWA_HIP_TRY(hipEventCreate(&e0));
   PSWA_HIP_TRY(hipEventCreate(&e1));
+  float best = 1e30f;
   auto time_it = [&](int r, float* med) -> pswa_status {
     PersistArgs P = persist_args(b);
     P.t_begin = t0;
@@ -611,6 +612,11 @@ pswa_status pswa_batch_autotune(pswa_batch* b, const char* cache_path, int reps,
       float ms = 0;
       PSWA_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
       if (i > 0) t.push_back(ms);  // the first run warms up
+      // a candidate already 3x slower than the best is not timed further
+      if (ms > 3.0f * best) {
+        if (t.empty()) t.push_back(ms);
+        break;
+      }
     }
     int ab = 0;
     PSWA_HIP_TRY(hipMemcpy(&ab, b->ctl + 1, sizeof ab, hipMemcpyDeviceToHost));
@@ -623,7 +629,6 @@ pswa_status pswa_batch_autotune(pswa_batch* b, const char* cache_path, int reps,
   std::vector<int> fpgs;
   for (int f = 1; f < n; f *= 2) fpgs.push_back(f);
   fpgs.push_back(n);
-  float best = 1e30f;
   int bf = b->fpg, bb = b->bpg, br = b->rtile;
   const std::vector<int> rts = m->w.prec == PSWA_PREC_F32 ? std::vector<int>{32}
                                                           : std::vector<int>{32, 16};
@@ -633,7 +638,7 @@ pswa_status pswa_batch_autotune(pswa_batch* b, const char* cache_path, int reps,
     if (b->grid > lim && apply_groups(b, n, std::min(lim, 8), st) != PSWA_OK) continue;
     b->rtile = r;
     for (int f : fpgs)
-      for (int g = 2; g <= lim; g *= 2) {
+      for (int g = lim; g >= 2; g /= 2) {
         const int ng = (n + f - 1) / f;
         if ((long)ng * g > lim || ng * g < std::min(16, lim / 16)) continue;
         if (apply_groups(b, f, g, st) != PSWA_OK) continue;
