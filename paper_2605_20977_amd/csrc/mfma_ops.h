@@ -135,7 +135,10 @@ __device__ __forceinline__ void gemm_tile_q(const GemmArgs& a, int bx, int by, u
   const int pitch = qgemm_pitch(K, PREC);
   const int m0 = by * R;
   const int rows = min(R, a.M - m0);
-  __syncthreads();  // the previous tile of this block is done with the LDS
+  // a tile that stages waits until the block's previous tile is done with
+  // the LDS; one that reuses the staged rows writes nothing shared, so its
+  // waves run on without a block barrier
+  if (stage) __syncthreads();
 
   // 1. row statistics: every row's chunks in flight at once, as many rows
   // per wave as 16 loads per lane allow (a row's arithmetic is the same
@@ -154,7 +157,7 @@ __device__ __forceinline__ void gemm_tile_q(const GemmArgs& a, int bx, int by, u
       rmul[tid] = 1.0f;
     }
   }
-  __syncthreads();
+  if (stage) __syncthreads();
 
   // 2. stage the scaled rows as BF16 / FP8, 16 loads per thread in flight;
   // rows past the end of A are zeros (their results are dropped)
@@ -203,8 +206,8 @@ __device__ __forceinline__ void gemm_tile_q(const GemmArgs& a, int bx, int by, u
         }
       }
     }
+    __syncthreads();
   }
-  __syncthreads();
 
   // 3. MFMA over K for this wave's 16 weight rows
   const int col = lane & 15, kg = lane >> 4;
