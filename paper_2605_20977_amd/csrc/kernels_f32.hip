@@ -23,6 +23,14 @@ __global__ void __launch_bounds__(kThreads) k_gemm(GemmArgs a) {
   gemm_tile<AK, RMS, EPI, KC>(a, blockIdx.x, blockIdx.y, smem4, rstd);
 }
 
+template <int AK, bool RMS, int EPI, int PREC, int R, int CB>
+__global__ void __launch_bounds__(kThreads) k_gemm_qb(GemmArgs a) {
+  extern __shared__ float4 smem4[];
+  __shared__ float rstd[R], rmul[R];
+  gemm_tile_qb<AK, RMS, EPI, PREC, R, CB>(a, blockIdx.x, blockIdx.y,
+                                          reinterpret_cast<uint8_t*>(smem4), rstd, rmul);
+}
+
 template <int AK, bool RMS, int EPI>
 __global__ void __launch_bounds__(kThreads) k_gemm_q(GemmArgs a) {
   extern __shared__ float4 smem4[];
@@ -105,8 +113,37 @@ __global__ void k_cdf_select(const float* mean, const float* lsig, size_t n, flo
 
 inline unsigned blocks_for(long n, int t) { return unsigned((n + t - 1) / t); }
 
+// Large-M launch of a low-precision GEMM: 128-row tiles when the staged rows
+// fit (K <= 512), else 32-row tiles; 4 or 2 groups of 16 weight rows per
+// wave by the width of the output.
+template <int AK, bool RMS, int EPI, int PREC, int R, int CB>
+void launch_big(const GemmArgs& a, hipStream_t s) {
+  const void* fn = reinterpret_cast<const void*>(&k_gemm_qb<AK, RMS, EPI, PREC, R, CB>);
+  static const bool attr_set = allow_big_lds(fn);
+  (void)attr_set;
+  dim3 grid(qgemm_big_col_tiles(a.N, EPI, CB), qgemm_row_tiles(a.M, R));
+  hipLaunchKernelGGL((k_gemm_qb<AK, RMS, EPI, PREC, R, CB>), grid, dim3(kThreads),
+                     qgemm_lds_bytes(a.K, PREC, R), s, a);
+}
+
+template <int AK, bool RMS, int EPI, int PREC>
+void launch_big_any(const GemmArgs& a, hipStream_t s) {
+  const bool tall = a.K <= 512, wide = a.N >= 1024;
+  if (tall && wide) launch_big<AK, RMS, EPI, PREC, 128, 4>(a, s);
+  else if (tall) launch_big<AK, RMS, EPI, PREC, 128, 2>(a, s);
+  else if (wide) launch_big<AK, RMS, EPI, PREC, 32, 4>(a, s);
+  else launch_big<AK, RMS, EPI, PREC, 32, 2>(a, s);
+}
+
+constexpr int kBigM = 256;  // rows from which the large tile pays
+
 template <int AK, bool RMS, int EPI>
 void launch_gemm(const GemmArgs& a, hipStream_t s) {
+  if (a.prec != PSWA_PREC_F32 && a.M >= kBigM) {
+    if (a.prec == PSWA_PREC_BF16) launch_big_any<AK, RMS, EPI, PSWA_PREC_BF16>(a, s);
+    else launch_big_any<AK, RMS, EPI, PSWA_PREC_FP8>(a, s);
+    return;
+  }
   if (a.prec != PSWA_PREC_F32) {
     static const bool attr_set =
         allow_big_lds(reinterpret_cast<const void*>(&k_gemm_q<AK, RMS, EPI>));

@@ -120,32 +120,20 @@ __device__ __forceinline__ void row_stats(const GemmArgs& a, int m0, int rows, f
   }
 }
 
-// R = A rows per tile (16 or 32, one or two 16-row MFMA blocks); a row
-// always sits at position (row % 16) of its MFMA block, so R changes which
-// tile computes a row, never how. stage = false reuses the A tile (and its
-// row statistics) this block staged for the same row tile just before.
-template <int AK, bool RMS, int EPI, int PREC, int R = kMBq>
-__device__ __forceinline__ void gemm_tile_q(const GemmArgs& a, int bx, int by, uint8_t* lds, float* rstd,
-                            float* rmul, bool stage = true) {
-  uint8_t* smem = lds + kQRedBytes;
-  constexpr bool PAIRED = paired_epi(EPI);
+// Steps 1 and 2 of a low-precision tile: row statistics of rows m0 ..
+// m0+rows-1 and the staged BF16 / FP8 rows [R][pitch] in LDS (rows past the
+// end are zeros). Ends with a block barrier.
+template <int AK, bool RMS, int PREC, int R>
+__device__ __forceinline__ void stage_a(const GemmArgs& a, int m0, int rows, uint8_t* smem,
+                                        float* rstd, float* rmul) {
   constexpr int EB = PREC == PSWA_PREC_BF16 ? 2 : 1;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int K = a.K, K4 = a.K / 4;
-  const int pitch = qgemm_pitch(K, PREC);
-  const int m0 = by * R;
-  const int rows = min(R, a.M - m0);
-  // a tile that stages waits until the block's previous tile is done with
-  // the LDS; one that reuses the staged rows writes nothing shared, so its
-  // waves run on without a block barrier
-  if (stage) __syncthreads();
-
+  const int tid = threadIdx.x;
+  const int K4 = a.K / 4;
+  const int pitch = qgemm_pitch(a.K, PREC);
   // 1. row statistics: every row's chunks in flight at once, as many rows
   // per wave as 16 loads per lane allow (a row's arithmetic is the same
   // whatever the batching)
-  if (!stage) {
-    // A tile and statistics kept from the previous tile
-  } else if (RMS || PREC == PSWA_PREC_FP8) {
+  if (RMS || PREC == PSWA_PREC_FP8) {
     const int cpr = (K4 + 63) / 64;  // float4 chunks per row and lane
     if (cpr <= 1) row_stats<AK, RMS, PREC, 1>(a, m0, rows, rstd, rmul);
     else if (cpr <= 2) row_stats<AK, RMS, PREC, 2>(a, m0, rows, rstd, rmul);
@@ -157,11 +145,11 @@ __device__ __forceinline__ void gemm_tile_q(const GemmArgs& a, int bx, int by, u
       rmul[tid] = 1.0f;
     }
   }
-  if (stage) __syncthreads();
+  __syncthreads();
 
   // 2. stage the scaled rows as BF16 / FP8, 16 loads per thread in flight;
   // rows past the end of A are zeros (their results are dropped)
-  if (stage) {
+  {
     const int total = R * K4;
     for (int base = 0; base < total; base += kStageLoads * kThreads) {
       float4 xv[kStageLoads];
@@ -208,6 +196,29 @@ __device__ __forceinline__ void gemm_tile_q(const GemmArgs& a, int bx, int by, u
     }
     __syncthreads();
   }
+
+}
+
+// R = A rows per tile (16 or 32, one or two 16-row MFMA blocks); a row
+// always sits at position (row % 16) of its MFMA block, so R changes which
+// tile computes a row, never how. stage = false reuses the A tile (and its
+// row statistics) this block staged for the same row tile just before.
+template <int AK, bool RMS, int EPI, int PREC, int R = kMBq>
+__device__ __forceinline__ void gemm_tile_q(const GemmArgs& a, int bx, int by, uint8_t* lds, float* rstd,
+                            float* rmul, bool stage = true) {
+  uint8_t* smem = lds + kQRedBytes;
+  constexpr bool PAIRED = paired_epi(EPI);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int K = a.K;
+  const int pitch = qgemm_pitch(K, PREC);
+  const int m0 = by * R;
+  const int rows = min(R, a.M - m0);
+  // a tile that stages waits until the block's previous tile is done with
+  // the LDS; one that reuses the staged rows writes nothing shared, so its
+  // waves run on without a block barrier
+  if (stage) __syncthreads();
+
+  if (stage) stage_a<AK, RMS, PREC, R>(a, m0, rows, smem, rstd, rmul);
 
   // 3. MFMA over K for this wave's 16 weight rows
   const int col = lane & 15, kg = lane >> 4;
@@ -283,6 +294,123 @@ __device__ __forceinline__ void gemm_tile_q(const GemmArgs& a, int bx, int by, u
       epilogue<EPI>(a, row, n, v, v2);
     }
   }
+}
+
+// Large-M tile: R A rows x (kWaves * CB * 16) weight rows per block. Each
+// wave computes all R rows for CB groups of 16 weight rows (8 W and 8 W2
+// rows per group for the paired epilogues), every A fragment read from LDS
+// once for its CB groups. Per output the arithmetic is exactly the small
+// tile's: the same MFMA chain over the k-steps in order from zero, the same
+// row statistics, scales and epilogue, so results never depend on which
+// tile computed them.
+template <int AK, bool RMS, int EPI, int PREC, int R, int CB>
+__device__ __forceinline__ void gemm_tile_qb(const GemmArgs& a, int bx, int by, uint8_t* lds,
+                                             float* rstd, float* rmul) {
+  uint8_t* smem = lds + kQRedBytes;
+  constexpr bool PAIRED = paired_epi(EPI);
+  constexpr int RB = R / 16;
+  constexpr int KC = 4;  // k-steps whose weight loads are issued together
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int K = a.K;
+  const int pitch = qgemm_pitch(K, PREC);
+  const int m0 = by * R;
+  const int rows = min(R, a.M - m0);
+  stage_a<AK, RMS, PREC, R>(a, m0, rows, smem, rstd, rmul);
+
+  const int col = lane & 15, kg = lane >> 4;
+  const int per_wave = (PAIRED ? 8 : 16) * CB;
+  const int nbase = bx * kWaves * per_wave + wave * per_wave;
+  int wn[CB];
+  const void* wb[CB];
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    if (PAIRED) {
+      wn[c] = min(nbase + 8 * c + (col & 7), a.N - 1);
+      wb[c] = col < 8 ? a.Wq : a.W2q;
+    } else {
+      wn[c] = min(nbase + 16 * c + col, a.N - 1);
+      wb[c] = a.Wq;
+    }
+  }
+  f32x4 acc[RB][CB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int c = 0; c < CB; ++c) acc[rb][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int ksteps = K / 32;
+  for (int k0 = 0; k0 < ksteps; k0 += KC) {
+    if (PREC == PSWA_PREC_BF16) {
+      bf16x8 b[KC][CB];
+#pragma unroll
+      for (int u = 0; u < KC; ++u)
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+          if (k0 + u < ksteps)
+            b[u][c] = *reinterpret_cast<const bf16x8*>(static_cast<const uint16_t*>(wb[c]) +
+                                                       (size_t)wn[c] * K + 8 * kg + 32 * (k0 + u));
+#pragma unroll
+      for (int u = 0; u < KC; ++u) {
+        if (k0 + u >= ksteps) continue;
+        const int k = 32 * (k0 + u) + 8 * kg;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          const bf16x8 af =
+              *reinterpret_cast<const bf16x8*>(smem + (size_t)((16 * rb + col) * pitch + k) * 2);
+#pragma unroll
+          for (int c = 0; c < CB; ++c)
+            acc[rb][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, b[u][c], acc[rb][c], 0, 0, 0);
+        }
+      }
+    } else {
+      long b[KC][CB];
+#pragma unroll
+      for (int u = 0; u < KC; ++u)
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+          if (k0 + u < ksteps)
+            b[u][c] = *reinterpret_cast<const long*>(static_cast<const uint8_t*>(wb[c]) +
+                                                     (size_t)wn[c] * K + 8 * kg + 32 * (k0 + u));
+#pragma unroll
+      for (int u = 0; u < KC; ++u) {
+        if (k0 + u >= ksteps) continue;
+        const int k = 32 * (k0 + u) + 8 * kg;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          const long af = *reinterpret_cast<const long*>(smem + (size_t)((16 * rb + col) * pitch + k));
+#pragma unroll
+          for (int c = 0; c < CB; ++c)
+            acc[rb][c] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(af, b[u][c], acc[rb][c], 0, 0, 0);
+        }
+      }
+    }
+  }
+
+  const float wsc = (PAIRED && col >= 8) ? a.w2scale : a.wscale;
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int mr = 16 * rb + 4 * kg + i;
+        const int mrc = min(mr, rows - 1);
+        float v = acc[rb][c][i] * wsc;
+        if (PREC == PSWA_PREC_FP8) v = v / rmul[mrc];
+        if (RMS) v *= rstd[mrc];
+        const float v2 = PAIRED ? __shfl(v, (lane & ~15) | ((col + 8) & 15), 64) : 0.f;
+        if (mr >= rows) continue;
+        if (PAIRED && col >= 8) continue;
+        const int n = PAIRED ? nbase + 8 * c + col : nbase + 16 * c + col;
+        if (n >= a.N) continue;
+        epilogue<EPI>(a, m0 + mr, n, v, v2);
+      }
+    }
+  }
+}
+
+__host__ __device__ inline int qgemm_big_col_tiles(int N, int epi, int cb) {
+  const int per = kWaves * (paired_epi(epi) ? 8 : 16) * cb;
+  return (N + per - 1) / per;
 }
 
 template <int AK, bool RMS, int EPI, int R = kMBq>
