@@ -110,7 +110,9 @@ size_t pswa_model_device_bytes(const pswa_model_desc* desc);
 /* Upload a blob into caller-owned device memory d_mem (>= device_bytes,
  * 256-byte aligned). Waits for the upload (the blob may be freed on return).
  * For PSWA_BF16 / PSWA_FP8_E4M3 the projection and MLP weights are rounded
- * once (RNE; FP8 saturating, one static scale per tensor). */
+ * once (RNE; FP8 saturating, one static scale per tensor) and stored in the
+ * matrix-core fragment order (private to the library; the FP32 weights stay
+ * row-major). */
 pswa_status pswa_model_create(const pswa_model_desc* desc, const float* h_blob,
                               size_t blob_floats, void* d_mem, size_t d_bytes,
                               void* stream, pswa_model** out);

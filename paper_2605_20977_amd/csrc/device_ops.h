@@ -22,7 +22,57 @@ constexpr int kMB = 16;     // A rows per GEMM tile
 constexpr int kMaxKeys = 256;
 constexpr int kThreads = 256;
 
-__device__ __forceinline__ int map_row(const int* idx, int m) { return idx ? idx[m] : m; }
+// Global-memory accesses through generic pointers. Pointers that device code
+// reads from argument tables in device memory are generic, and generic
+// (flat) accesses also count against the LDS wait counter, so every block
+// barrier and every LDS wait would also wait for them. These accessors
+// address global memory directly (HIP's float4 / int4 go through native
+// vectors: a class type in another address space is copied with flat
+// accesses).
+template <typename T> using gptr = __attribute__((address_space(1))) T*;
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+typedef int i32x4v __attribute__((ext_vector_type(4)));
+template <typename T>
+__device__ __forceinline__ T ldg(const T* p) {
+  return *(gptr<const T>)p;
+}
+__device__ __forceinline__ float4 ldg(const float4* p) {
+  const f32x4v v = *(gptr<const f32x4v>)(const void*)p;
+  return make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ int4 ldg(const int4* p) {
+  const i32x4v v = *(gptr<const i32x4v>)(const void*)p;
+  return make_int4(v[0], v[1], v[2], v[3]);
+}
+template <typename T>
+__device__ __forceinline__ void stg(T* p, T v) {
+  *(gptr<T>)p = v;
+}
+__device__ __forceinline__ float4 ldg4(const float* p) {
+  return ldg(reinterpret_cast<const float4*>(p));
+}
+__device__ __forceinline__ int4 ldg4(const int32_t* p) {
+  return ldg(reinterpret_cast<const int4*>(p));
+}
+
+// A struct from a read-only table in device memory at a wave-uniform address,
+// read with scalar loads into registers (the table is never written while a
+// kernel runs).
+template <typename S>
+__device__ __forceinline__ S load_uniform(const S* p) {
+  static_assert(sizeof(S) % 4 == 0, "table entries are whole words");
+  constexpr int kWords = sizeof(S) / 4;
+  typedef __attribute__((address_space(4))) const int* cptr;
+  const cptr src = (cptr)(const void*)p;
+  int w[kWords];
+#pragma unroll
+  for (int i = 0; i < kWords; ++i) w[i] = src[i];
+  S out;
+  __builtin_memcpy(&out, w, sizeof(S));
+  return out;
+}
+
+__device__ __forceinline__ int map_row(const int* idx, int m) { return idx ? ldg(idx + m) : m; }
 
 __device__ __forceinline__ float silu(float v) { return v / (1.0f + expf(-v)); }
 
@@ -87,36 +137,36 @@ __host__ __device__ inline size_t gemm_lds_bytes(int K) {
 template <int EPI>
 __device__ __forceinline__ void epilogue(const GemmArgs& a, int row, int n, float v, float v2) {
   if (EPI == EPI_STORE) {
-    a.Y[(size_t)map_row(a.yrow, row) * a.ldy + n] = v;
+    stg(a.Y + (size_t)map_row(a.yrow, row) * a.ldy + n, v);
   } else if (EPI == EPI_RESID) {
-    const float r = a.R[(size_t)map_row(a.rrow, row) * a.ldr + n];
-    a.Y[(size_t)map_row(a.yrow, row) * a.ldy + n] = r + v;
+    const float r = ldg(a.R + (size_t)map_row(a.rrow, row) * a.ldr + n);
+    stg(a.Y + (size_t)map_row(a.yrow, row) * a.ldy + n, r + v);
   } else if (EPI == EPI_QKV) {
     if (n < a.nsplit)
-      a.Y[(size_t)row * a.ldy + n] = v;
+      stg(a.Y + (size_t)row * a.ldy + n, v);
     else
-      a.Y2[(size_t)map_row(a.y2row, row) * a.ldy2 + (n - a.nsplit)] = v;
+      stg(a.Y2 + (size_t)map_row(a.y2row, row) * a.ldy2 + (n - a.nsplit), v);
   } else if (EPI == EPI_SILU) {
-    a.Y[(size_t)map_row(a.yrow, row) * a.ldy + n] = silu(v);
+    stg(a.Y + (size_t)map_row(a.yrow, row) * a.ldy + n, silu(v));
   } else if (EPI == EPI_SWIGLU) {
-    a.Y[(size_t)map_row(a.yrow, row) * a.ldy + n] = silu(v) * v2;
+    stg(a.Y + (size_t)map_row(a.yrow, row) * a.ldy + n, silu(v) * v2);
   } else if (EPI == EPI_HEAD) {
     const HeadOut& h = a.head;
-    const float mu = fmaf(h.gmu[n], v, h.bmu[n]);
-    const float raw = fmaf(h.gsig[n], v2, h.bsig[n]);
+    const float mu = fmaf(ldg(h.gmu + n), v, ldg(h.bmu + n));
+    const float raw = fmaf(ldg(h.gsig + n), v2, ldg(h.bsig + n));
     const float ls = fminf(h.ln_smax, fmaxf(h.ln_smin, raw));
     const float sg = expf(ls);
     const size_t o = (size_t)map_row(a.yrow, row) * a.N + n;
-    h.mean[o] = mu;
-    h.scale[o] = sg;
+    stg(h.mean + o, mu);
+    stg(h.scale + o, sg);
     int32_t c;
     uint16_t x;
     select_table(mu, ls, h.ln_smin, h.inv_delta, &c, &x);
-    h.center[o] = c;
-    h.index[o] = x;
+    stg(h.center + o, c);
+    stg(h.index + o, x);
     if (h.center_c) {
-      h.center_c[(size_t)row * a.N + n] = c;
-      h.index_c[(size_t)row * a.N + n] = x;
+      stg(h.center_c + (size_t)row * a.N + n, c);
+      stg(h.index_c + (size_t)row * a.N + n, x);
     }
     if (!(fabsf(mu) <= FLT_MAX) || !(fabsf(raw) <= FLT_MAX)) atomicOr(h.flag, 1);
   }
@@ -165,10 +215,10 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& a, int bx, int by, flo
     const bool in = c < K4;
 #pragma unroll
     for (int j = 0; j < kRowsW; ++j)
-      w[it][j] = in ? *reinterpret_cast<const float4*>(wrow[j] + 4 * c) : make_float4(0, 0, 0, 0);
+      w[it][j] = in ? ldg4(wrow[j] + 4 * c) : make_float4(0, 0, 0, 0);
     g[it] = make_float4(1.f, 1.f, 1.f, 1.f);
-    if (RMS && in) g[it] = *reinterpret_cast<const float4*>(a.gain + 4 * c);
-    if (AK == A_INT && in) g[it] = *reinterpret_cast<const float4*>(a.xscale + 4 * c);
+    if (RMS && in) g[it] = ldg4(a.gain + 4 * c);
+    if (AK == A_INT && in) g[it] = ldg4(a.xscale + 4 * c);
   }
 
   {
@@ -183,10 +233,10 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& a, int bx, int by, flo
           const int m = e / K4, c = e % K4;
           const size_t off = (size_t)map_row(a.xrow, m0 + m) * a.ldx + 4 * c;
           if (AK == A_INT) {
-            const int4 xi = *reinterpret_cast<const int4*>(a.Xi + off);
+            const int4 xi = ldg4(a.Xi + off);
             x[u] = make_float4(float(xi.x), float(xi.y), float(xi.z), float(xi.w));
           } else {
-            x[u] = *reinterpret_cast<const float4*>(a.X + off);
+            x[u] = ldg4(a.X + off);
           }
         }
       }
@@ -293,7 +343,12 @@ __device__ __forceinline__ void attn_item(const AttnArgs& a, int item, bool live
   if (!live) return;
   const int m = item / a.heads, hd = item % a.heads;
   const int gp = map_row(a.pos, m);
-  const FrameInfo fi = a.fid ? a.frames[a.fid[m]] : a.frame0;
+  FrameInfo fi = a.frame0;
+  if (a.fid) {
+    const int f = ldg(a.fid + m);
+    fi = FrameInfo{ldg(&a.frames[f].H), ldg(&a.frames[f].W), ldg(&a.frames[f].off),
+                   ldg(&a.frames[f].n_prev)};
+  }
   const int lp = gp - fi.off;
   const int pi = lp / fi.W, pj = lp % fi.W;
   const int r = a.r, k1 = 2 * r + 1;
@@ -311,7 +366,7 @@ __device__ __forceinline__ void attn_item(const AttnArgs& a, int item, bool live
   const float* qp = a.q + (size_t)m * a.ldq + hd * DH;
   float4 q4[DH / 4];
 #pragma unroll
-  for (int e = 0; e < DH / 4; ++e) q4[e] = *reinterpret_cast<const float4*>(qp + 4 * e);
+  for (int e = 0; e < DH / 4; ++e) q4[e] = ldg4(qp + 4 * e);
 
   float mx = -INFINITY, sum = 0.f;
   float o[DH];
@@ -347,7 +402,7 @@ __device__ __forceinline__ void attn_item(const AttnArgs& a, int item, bool live
       }
       kp = a.kv + (size_t)(fi.off + ki * fi.W + kj) * 2 * d + hd * DH;
       vp = kp + d;
-      b = a.bias[hd * a.nbias + kk];
+      b = ldg(a.bias + hd * a.nbias + kk);
     } else if (a.knull && kk == n_sp) {
       kp = a.knull + hd * DH;
       vp = a.vnull + hd * DH;
@@ -358,13 +413,13 @@ __device__ __forceinline__ void attn_item(const AttnArgs& a, int item, bool live
       if (ki < 0 || ki >= fi.H || kj < 0 || kj >= fi.W) continue;
       kp = a.tkv + ((size_t)tau * a.HWt + (size_t)(fi.off + ki * fi.W + kj)) * 2 * d + hd * DH;
       vp = kp + d;
-      b = a.bias[hd * a.nbias + n_sp + t];
+      b = ldg(a.bias + hd * a.nbias + n_sp + t);
     }
     float4 kr[DH / 4], vr[DH / 4];
 #pragma unroll
     for (int e = 0; e < DH / 4; ++e) {
-      kr[e] = *reinterpret_cast<const float4*>(kp + 4 * e);
-      vr[e] = *reinterpret_cast<const float4*>(vp + 4 * e);
+      kr[e] = ldg4(kp + 4 * e);
+      vr[e] = ldg4(vp + 4 * e);
     }
     float dot = 0.f;
 #pragma unroll
@@ -397,7 +452,7 @@ __device__ __forceinline__ void attn_item(const AttnArgs& a, int item, bool live
     float v = 0.f;
 #pragma unroll
     for (int l = 0; l < 64; ++l) v += tr[lane * 65 + l];
-    a.out[(size_t)m * a.ldo + hd * DH + lane] = v / tot;
+    stg(a.out + (size_t)m * a.ldo + hd * DH + lane, v / tot);
   }
   // the region is reused by this wave's next item
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -426,7 +481,7 @@ __device__ __forceinline__ void gather_item(const int32_t* src, int compact, con
                                             int32_t* ydec, long idx) {
   const int m = idx / C, c = idx % C;
   const int p = map_row(pos, m);
-  ydec[(size_t)p * C + c] = src[(size_t)(compact ? m : p) * C + c];
+  stg(ydec + (size_t)p * C + c, ldg(src + (size_t)(compact ? m : p) * C + c));
 }
 
 // bits[pos(m)][c] = -log2(max(P, 1e-9)) of ydec under N(mean, scale)
@@ -435,10 +490,10 @@ __device__ __forceinline__ void bits_item(const int* pos, int C, const int32_t* 
                                           long idx) {
   const int m = idx / C, c = idx % C;
   const size_t o = (size_t)map_row(pos, m) * C + c;
-  const float v = fabsf(float(ydec[o]) - mean[o]);
-  const float s2 = scale[o] * 1.41421356237309515f;
+  const float v = fabsf(float(ldg(ydec + o)) - ldg(mean + o));
+  const float s2 = ldg(scale + o) * 1.41421356237309515f;
   const float p = 0.5f * (erfcf((v - 0.5f) / s2) - erfcf((v + 0.5f) / s2));
-  bits[o] = -log2f(fmaxf(p, 1e-9f));
+  stg(bits + o, -log2f(fmaxf(p, 1e-9f)));
 }
 
 }  // namespace dev

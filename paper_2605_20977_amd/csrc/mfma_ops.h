@@ -15,14 +15,26 @@
 //      16-byte skew per row;
 //   3. each wave runs v_mfma_f32_16x16x32_{bf16,fp8_fp8} over k = 0, 32, ...
 //      in order for its 16 weight rows (16 k-steps of weight loads in flight
-//      at a time) against both row blocks: an output is one MFMA chain over K,
-//      whatever the tiling;
+//      at a time; the first of them issued before step 1, so the weight
+//      fetch overlaps the staging) against both row blocks: an output is one
+//      MFMA chain over K, whatever the tiling;
 //   4. the epilogue rescales (1/rms, row max / 448, 1 / weight scale) and
 //      applies the same epilogues as the FP32 tile.
 // A row's result depends only on that row, K and the weights: the same in
 // every launch shape, so encode and decode stay bit-identical.
 // Paired epilogues: columns 0-7 of a wave are W rows n..n+7 and columns 8-15
 // the W2 rows n..n+7; lane l (column < 8) takes its partner from lane l + 8.
+//
+// Weight layout (the library's BF16 / FP8 copies of a [N][K] weight; N a
+// multiple of 8, K of 32): units of 8 rows; inside a unit, blocks of one
+// k-step (32 columns) in k order; inside a block, 32 chunks of 8 consecutive
+// k values, chunk (8 * kg + row % 8) holding row (row % 8), columns
+// 8 kg .. 8 kg + 7 of the k-step. Element (n, k) sits at
+//   ((n / 8 * K / 32 + k / 32) * 32 + 8 * (k % 32 / 8) + n % 8) * 8 + k % 8.
+// A wave's load of one k-step for 16 rows (or 8 W and 8 W2 rows) is then
+// two contiguous 256-element blocks instead of 16 strided row pieces, and
+// rows 8u .. 8u + 7 keep the span of the row-major layout, so a weight that
+// starts at a row offset (a multiple of 8) is addressed the same way.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -54,6 +66,39 @@ __host__ __device__ inline size_t qgemm_lds_bytes(int K, int prec, int R = kMBq)
   return kQRedBytes + (size_t)R * qgemm_pitch(K, prec) * (prec == PSWA_PREC_BF16 ? 2 : 1);
 }
 
+// Operand types of the two MFMA forms: 8 BF16 or 8 FP8 values per lane
+// (FP32 instances of the tile templates exist but never run).
+template <int PREC> struct QOp {
+  typedef long T;
+  static constexpr int EB = 1;
+};
+template <> struct QOp<PSWA_PREC_BF16> {
+  typedef bf16x8 T;
+  static constexpr int EB = 2;
+};
+__device__ __forceinline__ f32x4 mfma_q(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mfma_q(long a, long b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
+}
+// 8 consecutive values at element offset e of a BF16 / FP8 array in global
+// memory (load_w8) or in LDS (load_s8)
+template <int PREC>
+__device__ __forceinline__ typename QOp<PREC>::T load_w8(const void* base, size_t e) {
+  return ldg(reinterpret_cast<const typename QOp<PREC>::T*>(static_cast<const uint8_t*>(base) +
+                                                             e * QOp<PREC>::EB));
+}
+template <int PREC>
+__device__ __forceinline__ typename QOp<PREC>::T load_s8(const uint8_t* lds, size_t e) {
+  return *reinterpret_cast<const typename QOp<PREC>::T*>(lds + e * QOp<PREC>::EB);
+}
+// Element offset, in the unit layout above, of lane chunk kg of weight row n
+// at k-step 0 (k-step s adds 256 s).
+__device__ __forceinline__ size_t wfrag_offset(int n, int kg, int ksteps) {
+  return ((size_t)(n >> 3) * ksteps) * 256 + (size_t)(8 * kg + (n & 7)) * 8;
+}
+
 __device__ __forceinline__ uint16_t bf16_rne(float f) {
   uint32_t u = __float_as_uint(f);
   u += 0x7fffu + ((u >> 16) & 1u);
@@ -82,10 +127,10 @@ __device__ __forceinline__ void row_stats(const GemmArgs& a, int m0, int rows, f
         xs[j][it] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (c < K4) {
           if (AK == A_INT) {
-            const int4 xi = *reinterpret_cast<const int4*>(a.Xi + off + 4 * c);
+            const int4 xi = ldg4(a.Xi + off + 4 * c);
             xs[j][it] = make_float4(float(xi.x), float(xi.y), float(xi.z), float(xi.w));
           } else {
-            xs[j][it] = *reinterpret_cast<const float4*>(a.X + off + 4 * c);
+            xs[j][it] = ldg4(a.X + off + 4 * c);
           }
         }
       }
@@ -101,8 +146,8 @@ __device__ __forceinline__ void row_stats(const GemmArgs& a, int m0, int rows, f
           if (RMS) ss = dot4(x, x, ss);
           if (PREC == PSWA_PREC_FP8) {
             float4 g = make_float4(1.f, 1.f, 1.f, 1.f);
-            if (RMS) g = *reinterpret_cast<const float4*>(a.gain + 4 * c);
-            if (AK == A_INT) g = *reinterpret_cast<const float4*>(a.xscale + 4 * c);
+            if (RMS) g = ldg4(a.gain + 4 * c);
+            if (AK == A_INT) g = ldg4(a.xscale + 4 * c);
             mx = fmaxf(mx, fmaxf(fmaxf(fabsf(x.x * g.x), fabsf(x.y * g.y)),
                                  fmaxf(fabsf(x.z * g.z), fabsf(x.w * g.w))));
           }
@@ -161,10 +206,10 @@ __device__ __forceinline__ void stage_a(const GemmArgs& a, int m0, int rows, uin
           const int m = e / K4, c = e % K4;
           const size_t off = (size_t)map_row(a.xrow, m0 + m) * a.ldx + 4 * c;
           if (AK == A_INT) {
-            const int4 xi = *reinterpret_cast<const int4*>(a.Xi + off);
+            const int4 xi = ldg4(a.Xi + off);
             xv[u] = make_float4(float(xi.x), float(xi.y), float(xi.z), float(xi.w));
           } else {
-            xv[u] = *reinterpret_cast<const float4*>(a.X + off);
+            xv[u] = ldg4(a.X + off);
           }
         }
       }
@@ -174,8 +219,8 @@ __device__ __forceinline__ void stage_a(const GemmArgs& a, int m0, int rows, uin
         if (e >= total) continue;
         const int m = e / K4, c = e % K4;
         float4 g = make_float4(1.f, 1.f, 1.f, 1.f);
-        if (RMS) g = *reinterpret_cast<const float4*>(a.gain + 4 * c);
-        if (AK == A_INT) g = *reinterpret_cast<const float4*>(a.xscale + 4 * c);
+        if (RMS) g = ldg4(a.gain + 4 * c);
+        if (AK == A_INT) g = ldg4(a.xscale + 4 * c);
         const float4 x = make_float4(xv[u].x * g.x, xv[u].y * g.y, xv[u].z * g.z, xv[u].w * g.w);
         if (PREC == PSWA_PREC_BF16) {
           uint2 v;
@@ -218,9 +263,9 @@ __device__ __forceinline__ void gemm_tile_q(const GemmArgs& a, int bx, int by, u
   // waves run on without a block barrier
   if (stage) __syncthreads();
 
-  if (stage) stage_a<AK, RMS, PREC, R>(a, m0, rows, smem, rstd, rmul);
-
-  // 3. MFMA over K for this wave's 16 weight rows
+  // 3. MFMA over K for this wave's 16 weight rows; the first chunk of
+  // weight loads is issued before the A rows are staged
+  typedef typename QOp<PREC>::T WT;
   const int col = lane & 15, kg = lane >> 4;
   int wn;                 // weight row this lane streams
   const void* wbase;
@@ -231,43 +276,29 @@ __device__ __forceinline__ void gemm_tile_q(const GemmArgs& a, int bx, int by, u
     wn = min(bx * kWaves * 16 + wave * 16 + col, a.N - 1);
     wbase = a.Wq;
   }
-  f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
   const int ksteps = K / 32;
+  const size_t wofs = wfrag_offset(wn, kg, ksteps);
+  WT b[kKchunk];
+#pragma unroll
+  for (int u = 0; u < kKchunk; ++u)
+    if (u < ksteps) b[u] = load_w8<PREC>(wbase, wofs + 256 * u);
+
+  if (stage) stage_a<AK, RMS, PREC, R>(a, m0, rows, smem, rstd, rmul);
+
+  f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
   for (int k0 = 0; k0 < ksteps; k0 += kKchunk) {
-    if (PREC == PSWA_PREC_BF16) {
-      const uint16_t* wr = static_cast<const uint16_t*>(wbase) + (size_t)wn * K + 8 * kg;
-      bf16x8 b[kKchunk];
+    if (k0 > 0) {
 #pragma unroll
       for (int u = 0; u < kKchunk; ++u)
-        if (k0 + u < ksteps) b[u] = *reinterpret_cast<const bf16x8*>(wr + 32 * (k0 + u));
+        if (k0 + u < ksteps) b[u] = load_w8<PREC>(wbase, wofs + 256 * (k0 + u));
+    }
 #pragma unroll
-      for (int u = 0; u < kKchunk; ++u) {
-        if (k0 + u < ksteps) {
-          const int k = 32 * (k0 + u) + 8 * kg;
-          const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(smem + (size_t)(col * pitch + k) * 2);
-          const bf16x8 a1 = R == 32 ? *reinterpret_cast<const bf16x8*>(
-                                          smem + (size_t)((16 + col) * pitch + k) * 2)
-                                    : a0;
-          c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b[u], c0, 0, 0, 0);
-          if (R == 32) c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b[u], c1, 0, 0, 0);
-        }
-      }
-    } else {
-      const uint8_t* wr = static_cast<const uint8_t*>(wbase) + (size_t)wn * K + 8 * kg;
-      long b[kKchunk];
-#pragma unroll
-      for (int u = 0; u < kKchunk; ++u)
-        if (k0 + u < ksteps) b[u] = *reinterpret_cast<const long*>(wr + 32 * (k0 + u));
-#pragma unroll
-      for (int u = 0; u < kKchunk; ++u) {
-        if (k0 + u < ksteps) {
-          const int k = 32 * (k0 + u) + 8 * kg;
-          const long a0 = *reinterpret_cast<const long*>(smem + (size_t)(col * pitch + k));
-          const long a1 =
-              R == 32 ? *reinterpret_cast<const long*>(smem + (size_t)((16 + col) * pitch + k)) : a0;
-          c0 = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a0, b[u], c0, 0, 0, 0);
-          if (R == 32) c1 = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a1, b[u], c1, 0, 0, 0);
-        }
+    for (int u = 0; u < kKchunk; ++u) {
+      if (k0 + u < ksteps) {
+        const int k = 32 * (k0 + u) + 8 * kg;
+        const WT a0 = load_s8<PREC>(smem, (size_t)col * pitch + k);
+        c0 = mfma_q(a0, b[u], c0);
+        if (R == 32) c1 = mfma_q(load_s8<PREC>(smem, (size_t)(16 + col) * pitch + k), b[u], c1);
       }
     }
   }
@@ -315,72 +346,56 @@ __device__ __forceinline__ void gemm_tile_qb(const GemmArgs& a, int bx, int by, 
   const int pitch = qgemm_pitch(K, PREC);
   const int m0 = by * R;
   const int rows = min(R, a.M - m0);
-  stage_a<AK, RMS, PREC, R>(a, m0, rows, smem, rstd, rmul);
-
+  typedef typename QOp<PREC>::T WT;
   const int col = lane & 15, kg = lane >> 4;
   const int per_wave = (PAIRED ? 8 : 16) * CB;
   const int nbase = bx * kWaves * per_wave + wave * per_wave;
-  int wn[CB];
+  const int ksteps = K / 32;
+  size_t wofs[CB];
   const void* wb[CB];
 #pragma unroll
   for (int c = 0; c < CB; ++c) {
+    int wn;
     if (PAIRED) {
-      wn[c] = min(nbase + 8 * c + (col & 7), a.N - 1);
+      wn = min(nbase + 8 * c + (col & 7), a.N - 1);
       wb[c] = col < 8 ? a.Wq : a.W2q;
     } else {
-      wn[c] = min(nbase + 16 * c + col, a.N - 1);
+      wn = min(nbase + 16 * c + col, a.N - 1);
       wb[c] = a.Wq;
     }
+    wofs[c] = wfrag_offset(wn, kg, ksteps);
   }
+  // the first chunk of weight loads is issued before the A rows are staged
+  WT b[KC][CB];
+#pragma unroll
+  for (int u = 0; u < KC; ++u)
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+      if (u < ksteps) b[u][c] = load_w8<PREC>(wb[c], wofs[c] + 256 * u);
+  stage_a<AK, RMS, PREC, R>(a, m0, rows, smem, rstd, rmul);
+
   f32x4 acc[RB][CB];
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
     for (int c = 0; c < CB; ++c) acc[rb][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int ksteps = K / 32;
   for (int k0 = 0; k0 < ksteps; k0 += KC) {
-    if (PREC == PSWA_PREC_BF16) {
-      bf16x8 b[KC][CB];
+    if (k0 > 0) {
 #pragma unroll
       for (int u = 0; u < KC; ++u)
 #pragma unroll
         for (int c = 0; c < CB; ++c)
-          if (k0 + u < ksteps)
-            b[u][c] = *reinterpret_cast<const bf16x8*>(static_cast<const uint16_t*>(wb[c]) +
-                                                       (size_t)wn[c] * K + 8 * kg + 32 * (k0 + u));
+          if (k0 + u < ksteps) b[u][c] = load_w8<PREC>(wb[c], wofs[c] + 256 * (k0 + u));
+    }
 #pragma unroll
-      for (int u = 0; u < KC; ++u) {
-        if (k0 + u >= ksteps) continue;
-        const int k = 32 * (k0 + u) + 8 * kg;
+    for (int u = 0; u < KC; ++u) {
+      if (k0 + u >= ksteps) continue;
+      const int k = 32 * (k0 + u) + 8 * kg;
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-          const bf16x8 af =
-              *reinterpret_cast<const bf16x8*>(smem + (size_t)((16 * rb + col) * pitch + k) * 2);
+      for (int rb = 0; rb < RB; ++rb) {
+        const WT af = load_s8<PREC>(smem, (size_t)(16 * rb + col) * pitch + k);
 #pragma unroll
-          for (int c = 0; c < CB; ++c)
-            acc[rb][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, b[u][c], acc[rb][c], 0, 0, 0);
-        }
-      }
-    } else {
-      long b[KC][CB];
-#pragma unroll
-      for (int u = 0; u < KC; ++u)
-#pragma unroll
-        for (int c = 0; c < CB; ++c)
-          if (k0 + u < ksteps)
-            b[u][c] = *reinterpret_cast<const long*>(static_cast<const uint8_t*>(wb[c]) +
-                                                     (size_t)wn[c] * K + 8 * kg + 32 * (k0 + u));
-#pragma unroll
-      for (int u = 0; u < KC; ++u) {
-        if (k0 + u >= ksteps) continue;
-        const int k = 32 * (k0 + u) + 8 * kg;
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-          const long af = *reinterpret_cast<const long*>(smem + (size_t)((16 * rb + col) * pitch + k));
-#pragma unroll
-          for (int c = 0; c < CB; ++c)
-            acc[rb][c] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(af, b[u][c], acc[rb][c], 0, 0, 0);
-        }
+        for (int c = 0; c < CB; ++c) acc[rb][c] = mfma_q(af, b[u][c], acc[rb][c]);
       }
     }
   }

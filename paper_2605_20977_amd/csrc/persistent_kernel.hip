@@ -135,8 +135,8 @@ __global__ void __launch_bounds__(kThreads) k_persistent(PersistArgs P) {
   extern __shared__ float4 smem4[];
   __shared__ float rstd[kMBq];
   float* smem = reinterpret_cast<float*>(smem4);
-  const int bm = P.block_map[blockIdx.x];
-  const GroupInfo& G = P.groups[bm >> 16];
+  const int bm = __builtin_amdgcn_readfirstlane(ldg(P.block_map + blockIdx.x));
+  const GroupInfo G = load_uniform(P.groups + (bm >> 16));
   const int rank = bm & 0xffff, nb = G.nblocks;
   const bool tracer = P.trace && bm == 0 && threadIdx.x == 0;
   const int L = P.L, ng = 6 + 4 * L, na = 1 + L;
@@ -168,38 +168,38 @@ __global__ void __launch_bounds__(kThreads) k_persistent(PersistArgs P) {
   ++nsync;
 
   for (int t = P.t_begin; t < t_end; ++t) {
-    const SymArgs& sy = G.stab[t];
+    const SymArgs sy = load_uniform(G.stab + t);
     if (sy.M == 0) continue;  // same for every block of the group
     const GemmArgs* g = G.gtab + (size_t)t * ng;
     const AttnArgs* at = G.atab + (size_t)t * na;
 
-    gemm_phase<A_FLOAT, true, EPI_STORE, PREC, R>(g[0], smem4, rstd, rank, nb);
+    gemm_phase<A_FLOAT, true, EPI_STORE, PREC, R>(load_uniform(g + 0), smem4, rstd, rank, nb);
     PSWA_SYNC
-    attn_phase<DH>(at[0], smem, rank, nb);
+    attn_phase<DH>(load_uniform(at + 0), smem, rank, nb);
     PSWA_SYNC
-    gemm_phase<A_FLOAT, false, EPI_RESID, PREC, R>(g[1], smem4, rstd, rank, nb);
+    gemm_phase<A_FLOAT, false, EPI_RESID, PREC, R>(load_uniform(g + 1), smem4, rstd, rank, nb);
     PSWA_SYNC
     for (int l = 0; l < L; ++l) {
-      gemm_phase<A_FLOAT, true, EPI_QKV, PREC, R>(g[2 + 4 * l], smem4, rstd, rank, nb);
+      gemm_phase<A_FLOAT, true, EPI_QKV, PREC, R>(load_uniform(g + 2 + 4 * l), smem4, rstd, rank, nb);
       PSWA_SYNC
-      attn_phase<DH>(at[1 + l], smem, rank, nb);
+      attn_phase<DH>(load_uniform(at + 1 + l), smem, rank, nb);
       PSWA_SYNC
-      gemm_phase<A_FLOAT, false, EPI_RESID, PREC, R>(g[3 + 4 * l], smem4, rstd, rank, nb);
+      gemm_phase<A_FLOAT, false, EPI_RESID, PREC, R>(load_uniform(g + 3 + 4 * l), smem4, rstd, rank, nb);
       PSWA_SYNC
-      gemm_phase<A_FLOAT, true, EPI_SWIGLU, PREC, R>(g[4 + 4 * l], smem4, rstd, rank, nb);
+      gemm_phase<A_FLOAT, true, EPI_SWIGLU, PREC, R>(load_uniform(g + 4 + 4 * l), smem4, rstd, rank, nb);
       PSWA_SYNC
-      gemm_phase<A_FLOAT, false, EPI_RESID, PREC, R>(g[5 + 4 * l], smem4, rstd, rank, nb);
+      gemm_phase<A_FLOAT, false, EPI_RESID, PREC, R>(load_uniform(g + 5 + 4 * l), smem4, rstd, rank, nb);
       PSWA_SYNC
     }
-    gemm_phase<A_FLOAT, true, EPI_SILU, PREC, R>(g[2 + 4 * L], smem4, rstd, rank, nb);
+    gemm_phase<A_FLOAT, true, EPI_SILU, PREC, R>(load_uniform(g + 2 + 4 * L), smem4, rstd, rank, nb);
     PSWA_SYNC
-    gemm_phase<A_FLOAT, false, EPI_HEAD, PREC, R>(g[3 + 4 * L], smem4, rstd, rank, nb);
+    gemm_phase<A_FLOAT, false, EPI_HEAD, PREC, R>(load_uniform(g + 3 + 4 * L), smem4, rstd, rank, nb);
     PSWA_SYNC
     symbol_phase(sy, rank, nb);
     PSWA_SYNC
-    gemm_phase<A_INT, false, EPI_STORE, PREC, R>(g[4 + 4 * L], smem4, rstd, rank, nb);
+    gemm_phase<A_INT, false, EPI_STORE, PREC, R>(load_uniform(g + 4 + 4 * L), smem4, rstd, rank, nb);
     PSWA_SYNC
-    gemm_phase<A_FLOAT, true, EPI_STORE, PREC, R>(g[5 + 4 * L], smem4, rstd, rank, nb);
+    gemm_phase<A_FLOAT, true, EPI_STORE, PREC, R>(load_uniform(g + 5 + 4 * L), smem4, rstd, rank, nb);
     PSWA_SYNC
   }
 #undef PSWA_SYNC

@@ -202,21 +202,45 @@ size_t blob_layout(const NetDims& x, const float* base, DevWeights* w, size_t al
   return off;
 }
 
-// Projection weights that run in the model's GEMM precision, as (tensor index
-// in the blob order, field of DevWeights that receives the copy).
-std::vector<std::pair<int, QW*>> quant_targets(DevWeights& w, int L) {
-  std::vector<std::pair<int, QW*>> t = {{3, &w.in}, {5, &w.acc_q}, {7, &w.acc_kv}, {11, &w.acc_o}};
-  for (int l = 0; l < L; ++l) {
+// Projection weights that run in the model's GEMM precision: tensor index in
+// the blob order, field of DevWeights that receives the copy, and the
+// weight's K (its row length).
+struct QuantTarget {
+  int tensor;
+  QW* dst;
+  int K;
+};
+std::vector<QuantTarget> quant_targets(DevWeights& w, const NetDims& x) {
+  std::vector<QuantTarget> t = {
+      {3, &w.in, x.C}, {5, &w.acc_q, x.d}, {7, &w.acc_kv, x.d}, {11, &w.acc_o, x.d}};
+  for (int l = 0; l < x.L; ++l) {
     LayerWeights& Ly = w.layers[l];
-    t.push_back({13 + 8 * l, &Ly.qkv});
-    t.push_back({15 + 8 * l, &Ly.o});
-    t.push_back({17 + 8 * l, &Ly.gate});
-    t.push_back({18 + 8 * l, &Ly.up});
-    t.push_back({19 + 8 * l, &Ly.down});
+    t.push_back({13 + 8 * l, &Ly.qkv, x.d});
+    t.push_back({15 + 8 * l, &Ly.o, x.d});
+    t.push_back({17 + 8 * l, &Ly.gate, x.d});
+    t.push_back({18 + 8 * l, &Ly.up, x.d});
+    t.push_back({19 + 8 * l, &Ly.down, x.F});
   }
-  t.push_back({13 + 8 * L, &w.head1});
-  t.push_back({14 + 8 * L, &w.head2});
+  t.push_back({13 + 8 * x.L, &w.head1, x.d});
+  t.push_back({14 + 8 * x.L, &w.head2, x.d});
   return t;
+}
+
+// Row-major [N][K] low-precision weight (eb bytes per element) to the MFMA
+// fragment layout: units of 8 rows, k-step blocks of 32 columns, chunk
+// (8 * kg + row % 8) of 8 consecutive values per block. Needs N % 8 == 0
+// and K % 32 == 0.
+std::vector<uint8_t> to_fragment_layout(const std::vector<uint8_t>& rm, size_t N, size_t K,
+                                        size_t eb) {
+  std::vector<uint8_t> out(rm.size());
+  const size_t ks = K / 32;
+  for (size_t n = 0; n < N; ++n)
+    for (size_t k = 0; k < K; k += 8) {
+      const size_t chunk = 8 * ((k % 32) / 8) + n % 8;
+      const size_t e = (((n / 8) * ks + k / 32) * 32 + chunk) * 8;
+      std::memcpy(&out[e * eb], &rm[(n * K + k) * eb], 8 * eb);
+    }
+  return out;
 }
 
 uint16_t bf16_rne_host(float f) {
@@ -380,9 +404,9 @@ size_t device_layout(const pswa_model_desc& desc, std::vector<std::pair<int, siz
   if (desc.prec == PSWA_FP32) return bytes;
   const size_t eb = desc.prec == PSWA_BF16 ? 2 : 1;
   DevWeights tmp{};
-  for (auto& t : quant_targets(tmp, x.L)) {
-    if (qoff) qoff->push_back({t.first, bytes});
-    bytes += align_up(spans[t.first].second * eb);
+  for (auto& t : quant_targets(tmp, x)) {
+    if (qoff) qoff->push_back({t.tensor, bytes});
+    bytes += align_up(spans[t.tensor].second * eb);
   }
   return bytes;
 }
@@ -432,10 +456,16 @@ pswa_status pswa_model_create(const pswa_model_desc* desc, const float* h_blob,
   if (desc->prec != PSWA_FP32) {
     std::vector<std::pair<int, size_t>> qoff;
     device_layout(*desc, &qoff);
-    auto targets = quant_targets(m->w, x.L);
+    auto targets = quant_targets(m->w, x);
     for (size_t i = 0; i < targets.size(); ++i) {
-      const float* w = h_blob + src[targets[i].first].first;
-      const size_t n = src[targets[i].first].second;
+      const float* w = h_blob + src[targets[i].tensor].first;
+      const size_t n = src[targets[i].tensor].second;
+      const size_t K = targets[i].K, N = n / K;
+      if (N * K != n || N % 8 != 0 || K % 32 != 0) {
+        (void)hipStreamSynchronize(st);  // copies from host buffers still in flight
+        return fail(PSWA_E_UNSUPPORTED, "projection %d of %zu values is not [8a][32b]",
+                    targets[i].tensor, n);
+      }
       std::vector<uint8_t> q;
       float inv = 1.f;
       if (desc->prec == PSWA_BF16) {
@@ -452,9 +482,10 @@ pswa_status pswa_model_create(const pswa_model_desc* desc, const float* h_blob,
         for (size_t k = 0; k < n; ++k) q[k] = fp8_e4m3_rne_host(float(double(w[k]) * sc));
         inv = float(1.0 / sc);
       }
+      q = to_fragment_layout(q, N, K, desc->prec == PSWA_BF16 ? 2 : 1);
       char* dst = static_cast<char*>(d_mem) + qoff[i].second;
       PSWA_HIP_TRY(hipMemcpyAsync(dst, q.data(), q.size(), hipMemcpyHostToDevice, st));
-      *targets[i].second = QW{dst, inv};
+      *targets[i].dst = QW{dst, inv};
       staging.push_back(std::move(q));
     }
   }
