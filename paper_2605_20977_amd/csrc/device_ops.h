@@ -72,6 +72,39 @@ __device__ __forceinline__ S load_uniform(const S* p) {
   return out;
 }
 
+// A struct that every lane reads at the same LDS address, moved into scalar
+// registers.
+template <typename S>
+__device__ __forceinline__ S lds_uniform(const S* p) {
+  static_assert(sizeof(S) % 4 == 0, "table entries are whole words");
+  constexpr int kWords = sizeof(S) / 4;
+  const int* src = reinterpret_cast<const int*>(p);
+  int w[kWords];
+#pragma unroll
+  for (int i = 0; i < kWords; ++i) w[i] = __builtin_amdgcn_readfirstlane(src[i]);
+  S out;
+  __builtin_memcpy(&out, w, sizeof(S));
+  return out;
+}
+
+// Block-wide copy of n words from device memory to LDS, 16 loads per thread
+// in flight per round (ends without a block barrier).
+__device__ __forceinline__ void copy_words_to_lds(int* dst, const int* src, int n) {
+  for (int base = 0; base < n; base += 16 * kThreads) {
+    int v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int i = min(base + u * kThreads + (int)threadIdx.x, n - 1);
+      v[u] = ldg(src + i);
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int i = base + u * kThreads + (int)threadIdx.x;
+      if (i < n) dst[i] = v[u];
+    }
+  }
+}
+
 __device__ __forceinline__ int map_row(const int* idx, int m) { return idx ? ldg(idx + m) : m; }
 
 __device__ __forceinline__ float silu(float v) { return v / (1.0f + expf(-v)); }

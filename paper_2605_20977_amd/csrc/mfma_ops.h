@@ -9,15 +9,15 @@
 //   1. row statistics, one wave per row, lane l over the row's float4 chunks
 //      l, l+64, ... in order: sum of squares (RMSNorm) through a fixed xor
 //      tree, and the row's absolute maximum after the gain (FP8 scale);
-//   2. the block stages the rows, times the gain (RMSNorm input) or the
-//      input scale (integer latents), as BF16 (round to nearest even) or as
-//      FP8 of (value * 448 / row max) (round to nearest even), in LDS with a
-//      16-byte skew per row;
+//   2. from the same registers the wave stages the row, times the gain
+//      (RMSNorm input) or the input scale (integer latents), as BF16 (round
+//      to nearest even) or as FP8 of (value * 448 / row max) (round to
+//      nearest even), in LDS with a 16-byte skew per row;
 //   3. each wave runs v_mfma_f32_16x16x32_{bf16,fp8_fp8} over k = 0, 32, ...
 //      in order for its 16 weight rows (16 k-steps of weight loads in flight
-//      at a time; the first of them issued before step 1, so the weight
-//      fetch overlaps the staging) against both row blocks: an output is one
-//      MFMA chain over K, whatever the tiling;
+//      at a time; the first of them issued right after the first row loads,
+//      so the weight fetch overlaps steps 1 and 2) against both row blocks:
+//      an output is one MFMA chain over K, whatever the tiling;
 //   4. the epilogue rescales (1/rms, row max / 448, 1 / weight scale) and
 //      applies the same epilogues as the FP32 tile.
 // A row's result depends only on that row, K and the weights: the same in
@@ -55,7 +55,6 @@ __host__ __device__ inline int qgemm_col_tiles(int N, int epi) {
   return (N + per - 1) / per;
 }
 constexpr int kKchunk = 16;  // k-steps whose weight loads are issued together
-constexpr int kStageLoads = 16;  // A loads per thread in flight while staging
 __host__ __device__ inline int qgemm_row_tiles(int M, int R = kMBq) { return (M + R - 1) / R; }
 // element pitch of a staged row: K plus a 16-byte skew
 __host__ __device__ inline int qgemm_pitch(int K, int prec) { return K + (prec == PSWA_PREC_BF16 ? 8 : 16); }
@@ -105,16 +104,38 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
   return uint16_t(u >> 16);
 }
 
-// Row statistics of rows m0 .. m0+rows-1 of A: 1/rms (RMS) and the FP8
-// input scale 448 / max|x g| (FP8). Lane l accumulates chunks l, l+64, ...
-// of a row in order, then a fixed xor tree sums the lanes. CPR = chunks per
-// lane and row; 16 / CPR rows per wave are loaded together.
-template <int AK, bool RMS, int PREC, int CPR>
-__device__ __forceinline__ void row_stats(const GemmArgs& a, int m0, int rows, float* rstd,
-                                          float* rmul) {
+// Steps 1 and 2 of a low-precision tile for rows m0 .. m0+rows-1 of A, one
+// wave per row (rows wave, wave + 4, ...): lane l loads the row's float4
+// chunks l, l+64, ... (CPR of them; RPB = 16 / CPR rows per wave in flight
+// at once, indices clamped into the row so every load is unconditional),
+//   * row statistics: the sum of squares (RMS) over the lane's chunks in
+//     order, then a fixed xor tree, gives 1/rms; the absolute maximum of
+//     x * g (FP8) through a max tree gives the input scale 448 / max;
+//   * the same registers, times the gain (RMSNorm input) or the input scale
+//     (integer latents), are written to LDS as BF16 (round to nearest even)
+//     or as FP8 of (value * 448 / row max) (round to nearest even), rows
+//     [R][pitch] with a 16-byte skew per row.
+// issue_w() runs once, right after the first batch of row loads is issued,
+// so loads the caller issues there complete after (and are not waited for
+// with) the row data.
+template <int AK, bool RMS, int PREC, int R, int CPR, typename IssueW>
+__device__ __forceinline__ void stage_rows(const GemmArgs& a, int m0, int rows, uint8_t* smem,
+                                           float* rstd, float* rmul, IssueW& issue_w) {
   constexpr int RPB = 16 / CPR;
+  constexpr int EB = PREC == PSWA_PREC_BF16 ? 2 : 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int K = a.K, K4 = a.K / 4;
+  const int pitch = qgemm_pitch(K, PREC);
+  // per-column factor (gain or input scale) of the lane's chunks
+  float4 gg[CPR];
+#pragma unroll
+  for (int it = 0; it < CPR; ++it) {
+    const int cc = min(lane + 64 * it, K4 - 1);
+    gg[it] = make_float4(1.f, 1.f, 1.f, 1.f);
+    if (RMS) gg[it] = ldg4(a.gain + 4 * cc);
+    if (AK == A_INT) gg[it] = ldg4(a.xscale + 4 * cc);
+  }
+  bool issued = false;
   for (int mb = 0; mb < rows; mb += RPB * kWaves) {
     float4 xs[RPB][CPR];
 #pragma unroll
@@ -123,132 +144,99 @@ __device__ __forceinline__ void row_stats(const GemmArgs& a, int m0, int rows, f
       const size_t off = (size_t)map_row(a.xrow, m0 + mm) * a.ldx;
 #pragma unroll
       for (int it = 0; it < CPR; ++it) {
-        const int c = lane + 64 * it;
-        xs[j][it] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (c < K4) {
-          if (AK == A_INT) {
-            const int4 xi = ldg4(a.Xi + off + 4 * c);
-            xs[j][it] = make_float4(float(xi.x), float(xi.y), float(xi.z), float(xi.w));
-          } else {
-            xs[j][it] = ldg4(a.X + off + 4 * c);
-          }
+        const int cc = min(lane + 64 * it, K4 - 1);
+        if (AK == A_INT) {
+          const int4 xi = ldg4(a.Xi + off + 4 * cc);
+          xs[j][it] = make_float4(float(xi.x), float(xi.y), float(xi.z), float(xi.w));
+        } else {
+          xs[j][it] = ldg4(a.X + off + 4 * cc);
         }
       }
     }
+    if (!issued) {
+      issue_w();
+      issued = true;
+    }
 #pragma unroll
     for (int j = 0; j < RPB; ++j) {
+      const int mm = mb + wave + kWaves * j;
       float ss = 0.f, mx = 0.f;
 #pragma unroll
       for (int it = 0; it < CPR; ++it) {
-        const int c = lane + 64 * it;
-        if (c < K4) {
-          const float4 x = xs[j][it];
-          if (RMS) ss = dot4(x, x, ss);
-          if (PREC == PSWA_PREC_FP8) {
-            float4 g = make_float4(1.f, 1.f, 1.f, 1.f);
-            if (RMS) g = ldg4(a.gain + 4 * c);
-            if (AK == A_INT) g = ldg4(a.xscale + 4 * c);
-            mx = fmaxf(mx, fmaxf(fmaxf(fabsf(x.x * g.x), fabsf(x.y * g.y)),
-                                 fmaxf(fabsf(x.z * g.z), fabsf(x.w * g.w))));
-          }
+        // a chunk past K adds +0 to the sum and cannot raise the maximum
+        const bool in = lane + 64 * it < K4;
+        const float4 x = in ? xs[j][it] : make_float4(0.f, 0.f, 0.f, 0.f);
+        if (RMS) ss = dot4(x, x, ss);
+        if (PREC == PSWA_PREC_FP8) {
+          const float4 g = gg[it];
+          mx = fmaxf(mx, fmaxf(fmaxf(fabsf(x.x * g.x), fabsf(x.y * g.y)),
+                               fmaxf(fabsf(x.z * g.z), fabsf(x.w * g.w))));
         }
       }
       if (RMS) ss = wave_sum(ss);
       if (PREC == PSWA_PREC_FP8) mx = wave_max(mx);
-      const int mm = mb + wave + kWaves * j;
-      if (lane == 0 && mm < rows) {
+      // FP8 rows are stored as value * (448 / max); a zero row stays zero
+      const float sc = PREC == PSWA_PREC_FP8 ? (mx > 0.f ? kFp8Max / mx : 1.0f) : 1.0f;
+      if (mm >= rows) continue;  // the same for the whole wave
+      if (lane == 0) {
         rstd[mm] = RMS ? 1.0f / sqrtf(ss / float(K) + kEps) : 1.0f;
-        // FP8 rows are stored as value * (448 / max); a zero row stays zero
-        rmul[mm] = PREC == PSWA_PREC_FP8 ? (mx > 0.f ? kFp8Max / mx : 1.0f) : 1.0f;
-      }
-    }
-  }
-}
-
-// Steps 1 and 2 of a low-precision tile: row statistics of rows m0 ..
-// m0+rows-1 and the staged BF16 / FP8 rows [R][pitch] in LDS (rows past the
-// end are zeros). Ends with a block barrier.
-template <int AK, bool RMS, int PREC, int R>
-__device__ __forceinline__ void stage_a(const GemmArgs& a, int m0, int rows, uint8_t* smem,
-                                        float* rstd, float* rmul) {
-  constexpr int EB = PREC == PSWA_PREC_BF16 ? 2 : 1;
-  const int tid = threadIdx.x;
-  const int K4 = a.K / 4;
-  const int pitch = qgemm_pitch(a.K, PREC);
-  // 1. row statistics: every row's chunks in flight at once, as many rows
-  // per wave as 16 loads per lane allow (a row's arithmetic is the same
-  // whatever the batching)
-  if (RMS || PREC == PSWA_PREC_FP8) {
-    const int cpr = (K4 + 63) / 64;  // float4 chunks per row and lane
-    if (cpr <= 1) row_stats<AK, RMS, PREC, 1>(a, m0, rows, rstd, rmul);
-    else if (cpr <= 2) row_stats<AK, RMS, PREC, 2>(a, m0, rows, rstd, rmul);
-    else if (cpr <= 4) row_stats<AK, RMS, PREC, 4>(a, m0, rows, rstd, rmul);
-    else row_stats<AK, RMS, PREC, 8>(a, m0, rows, rstd, rmul);
-  } else {
-    if (tid < R) {
-      rstd[tid] = 1.0f;
-      rmul[tid] = 1.0f;
-    }
-  }
-  __syncthreads();
-
-  // 2. stage the scaled rows as BF16 / FP8, 16 loads per thread in flight;
-  // rows past the end of A are zeros (their results are dropped)
-  {
-    const int total = R * K4;
-    for (int base = 0; base < total; base += kStageLoads * kThreads) {
-      float4 xv[kStageLoads];
-#pragma unroll
-      for (int u = 0; u < kStageLoads; ++u) {
-        const int e = base + u * kThreads + tid;
-        xv[u] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (e < total && e / K4 < rows) {
-          const int m = e / K4, c = e % K4;
-          const size_t off = (size_t)map_row(a.xrow, m0 + m) * a.ldx + 4 * c;
-          if (AK == A_INT) {
-            const int4 xi = ldg4(a.Xi + off);
-            xv[u] = make_float4(float(xi.x), float(xi.y), float(xi.z), float(xi.w));
-          } else {
-            xv[u] = ldg4(a.X + off);
-          }
-        }
+        rmul[mm] = sc;
       }
 #pragma unroll
-      for (int u = 0; u < kStageLoads; ++u) {
-        const int e = base + u * kThreads + tid;
-        if (e >= total) continue;
-        const int m = e / K4, c = e % K4;
-        float4 g = make_float4(1.f, 1.f, 1.f, 1.f);
-        if (RMS) g = ldg4(a.gain + 4 * c);
-        if (AK == A_INT) g = ldg4(a.xscale + 4 * c);
-        const float4 x = make_float4(xv[u].x * g.x, xv[u].y * g.y, xv[u].z * g.z, xv[u].w * g.w);
+      for (int it = 0; it < CPR; ++it) {
+        const int c = lane + 64 * it;
+        if (c >= K4) continue;
+        const float4 g = gg[it];
+        const float4 x = make_float4(xs[j][it].x * g.x, xs[j][it].y * g.y, xs[j][it].z * g.z,
+                                     xs[j][it].w * g.w);
         if (PREC == PSWA_PREC_BF16) {
           uint2 v;
           v.x = uint32_t(bf16_rne(x.x)) | (uint32_t(bf16_rne(x.y)) << 16);
           v.y = uint32_t(bf16_rne(x.z)) | (uint32_t(bf16_rne(x.w)) << 16);
-          *reinterpret_cast<uint2*>(smem + (size_t)(m * pitch + 4 * c) * EB) = v;
+          *reinterpret_cast<uint2*>(smem + (size_t)(mm * pitch + 4 * c) * EB) = v;
         } else {
-          const float sc = m < rows ? rmul[m] : 1.0f;
           const float q0 = fminf(kFp8Max, fmaxf(-kFp8Max, x.x * sc));
           const float q1 = fminf(kFp8Max, fmaxf(-kFp8Max, x.y * sc));
           const float q2 = fminf(kFp8Max, fmaxf(-kFp8Max, x.z * sc));
           const float q3 = fminf(kFp8Max, fmaxf(-kFp8Max, x.w * sc));
           const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(q0, q1, 0, false);
           const int hi = __builtin_amdgcn_cvt_pk_fp8_f32(q2, q3, lo, true);
-          *reinterpret_cast<uint32_t*>(smem + (size_t)(m * pitch + 4 * c)) = uint32_t(hi);
+          *reinterpret_cast<uint32_t*>(smem + (size_t)(mm * pitch + 4 * c)) = uint32_t(hi);
         }
       }
     }
-    __syncthreads();
   }
+  if (!issued) issue_w();
+}
 
+// Steps 1 and 2 of a low-precision tile (see stage_rows); rows past the end
+// of A up to R are zeros (their results are dropped). Ends with a block
+// barrier.
+template <int AK, bool RMS, int PREC, int R, typename IssueW>
+__device__ __forceinline__ void stage_a(const GemmArgs& a, int m0, int rows, uint8_t* smem,
+                                        float* rstd, float* rmul, IssueW& issue_w) {
+  const int K4 = a.K / 4;
+  const int cpr = (K4 + 63) / 64;  // float4 chunks per row and lane
+  if (cpr <= 1) stage_rows<AK, RMS, PREC, R, 1>(a, m0, rows, smem, rstd, rmul, issue_w);
+  else if (cpr <= 2) stage_rows<AK, RMS, PREC, R, 2>(a, m0, rows, smem, rstd, rmul, issue_w);
+  else if (cpr <= 4) stage_rows<AK, RMS, PREC, R, 4>(a, m0, rows, smem, rstd, rmul, issue_w);
+  else stage_rows<AK, RMS, PREC, R, 8>(a, m0, rows, smem, rstd, rmul, issue_w);
+  // zero rows past the end of A (whole 8-byte words of each padding row)
+  const int pitch_b = qgemm_pitch(a.K, PREC) * (PREC == PSWA_PREC_BF16 ? 2 : 1);
+  const int words = (R - rows) * pitch_b / 8;
+  for (int i = threadIdx.x; i < words; i += kThreads)
+    reinterpret_cast<uint2*>(smem + (size_t)rows * pitch_b)[i] = make_uint2(0u, 0u);
+  __syncthreads();
 }
 
 // R = A rows per tile (16 or 32, one or two 16-row MFMA blocks); a row
 // always sits at position (row % 16) of its MFMA block, so R changes which
 // tile computes a row, never how. stage = false reuses the A tile (and its
 // row statistics) this block staged for the same row tile just before.
-template <int AK, bool RMS, int EPI, int PREC, int R = kMBq>
+// KS = K / 32 when known at compile time (0: read from the arguments); a
+// compile-time count lets the k loop run without branches, so its LDS reads
+// are issued ahead of the MFMAs. The arithmetic is the same either way.
+template <int AK, bool RMS, int EPI, int PREC, int R = kMBq, int KS = 0>
 __device__ __forceinline__ void gemm_tile_q(const GemmArgs& a, int bx, int by, uint8_t* lds, float* rstd,
                             float* rmul, bool stage = true) {
   uint8_t* smem = lds + kQRedBytes;
@@ -276,25 +264,44 @@ __device__ __forceinline__ void gemm_tile_q(const GemmArgs& a, int bx, int by, u
     wn = min(bx * kWaves * 16 + wave * 16 + col, a.N - 1);
     wbase = a.Wq;
   }
-  const int ksteps = K / 32;
+  const int ksteps = KS ? KS : K / 32;
+  constexpr bool kFull = KS > 0 && KS % kKchunk == 0;  // every chunk complete
   const size_t wofs = wfrag_offset(wn, kg, ksteps);
+  // weight loads of the first chunk and the residual inputs of this lane's
+  // outputs: issued right after the A rows' first loads (or at once when
+  // the staged rows are reused)
   WT b[kKchunk];
+  float rres[R / 16][4];
+  auto issue_w = [&]() {
 #pragma unroll
-  for (int u = 0; u < kKchunk; ++u)
-    if (u < ksteps) b[u] = load_w8<PREC>(wbase, wofs + 256 * u);
-
-  if (stage) stage_a<AK, RMS, PREC, R>(a, m0, rows, smem, rstd, rmul);
+    for (int u = 0; u < kKchunk; ++u)
+      if (u < ksteps) b[u] = load_w8<PREC>(wbase, wofs + 256 * u);
+    if constexpr (EPI == EPI_RESID) {
+      const int nc = min(bx * kWaves * 16 + wave * 16 + col, a.N - 1);
+#pragma unroll
+      for (int rb = 0; rb < R / 16; ++rb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = m0 + min(16 * rb + 4 * kg + i, rows - 1);
+          rres[rb][i] = ldg(a.R + (size_t)map_row(a.rrow, row) * a.ldr + nc);
+        }
+    }
+  };
+  if (stage)
+    stage_a<AK, RMS, PREC, R>(a, m0, rows, smem, rstd, rmul, issue_w);
+  else
+    issue_w();
 
   f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
   for (int k0 = 0; k0 < ksteps; k0 += kKchunk) {
     if (k0 > 0) {
 #pragma unroll
       for (int u = 0; u < kKchunk; ++u)
-        if (k0 + u < ksteps) b[u] = load_w8<PREC>(wbase, wofs + 256 * (k0 + u));
+        if (kFull || k0 + u < ksteps) b[u] = load_w8<PREC>(wbase, wofs + 256 * (k0 + u));
     }
 #pragma unroll
     for (int u = 0; u < kKchunk; ++u) {
-      if (k0 + u < ksteps) {
+      if (kFull || k0 + u < ksteps) {
         const int k = 32 * (k0 + u) + 8 * kg;
         const WT a0 = load_s8<PREC>(smem, (size_t)col * pitch + k);
         c0 = mfma_q(a0, b[u], c0);
@@ -322,7 +329,10 @@ __device__ __forceinline__ void gemm_tile_q(const GemmArgs& a, int bx, int by, u
       const int n =
           PAIRED ? bx * kWaves * 8 + wave * 8 + col : bx * kWaves * 16 + wave * 16 + col;
       if (n >= a.N) continue;
-      epilogue<EPI>(a, row, n, v, v2);
+      if constexpr (EPI == EPI_RESID)
+        stg(a.Y + (size_t)map_row(a.yrow, row) * a.ldy + n, rres[rb][i] + v);
+      else
+        epilogue<EPI>(a, row, n, v, v2);
     }
   }
 }
@@ -334,7 +344,7 @@ __device__ __forceinline__ void gemm_tile_q(const GemmArgs& a, int bx, int by, u
 // tile's: the same MFMA chain over the k-steps in order from zero, the same
 // row statistics, scales and epilogue, so results never depend on which
 // tile computed them.
-template <int AK, bool RMS, int EPI, int PREC, int R, int CB>
+template <int AK, bool RMS, int EPI, int PREC, int R, int CB, int KS = 0>
 __device__ __forceinline__ void gemm_tile_qb(const GemmArgs& a, int bx, int by, uint8_t* lds,
                                              float* rstd, float* rmul) {
   uint8_t* smem = lds + kQRedBytes;
@@ -350,7 +360,8 @@ __device__ __forceinline__ void gemm_tile_qb(const GemmArgs& a, int bx, int by, 
   const int col = lane & 15, kg = lane >> 4;
   const int per_wave = (PAIRED ? 8 : 16) * CB;
   const int nbase = bx * kWaves * per_wave + wave * per_wave;
-  const int ksteps = K / 32;
+  const int ksteps = KS ? KS : K / 32;
+  constexpr bool kFull = KS > 0 && KS % KC == 0;  // every chunk complete
   size_t wofs[CB];
   const void* wb[CB];
 #pragma unroll
@@ -365,14 +376,16 @@ __device__ __forceinline__ void gemm_tile_qb(const GemmArgs& a, int bx, int by, 
     }
     wofs[c] = wfrag_offset(wn, kg, ksteps);
   }
-  // the first chunk of weight loads is issued before the A rows are staged
+  // the first chunk of weight loads, issued right after the A rows' first loads
   WT b[KC][CB];
+  auto issue_w = [&]() {
 #pragma unroll
-  for (int u = 0; u < KC; ++u)
+    for (int u = 0; u < KC; ++u)
 #pragma unroll
-    for (int c = 0; c < CB; ++c)
-      if (u < ksteps) b[u][c] = load_w8<PREC>(wb[c], wofs[c] + 256 * u);
-  stage_a<AK, RMS, PREC, R>(a, m0, rows, smem, rstd, rmul);
+      for (int c = 0; c < CB; ++c)
+        if (u < ksteps) b[u][c] = load_w8<PREC>(wb[c], wofs[c] + 256 * u);
+  };
+  stage_a<AK, RMS, PREC, R>(a, m0, rows, smem, rstd, rmul, issue_w);
 
   f32x4 acc[RB][CB];
 #pragma unroll
@@ -385,11 +398,11 @@ __device__ __forceinline__ void gemm_tile_qb(const GemmArgs& a, int bx, int by, 
       for (int u = 0; u < KC; ++u)
 #pragma unroll
         for (int c = 0; c < CB; ++c)
-          if (k0 + u < ksteps) b[u][c] = load_w8<PREC>(wb[c], wofs[c] + 256 * (k0 + u));
+          if (kFull || k0 + u < ksteps) b[u][c] = load_w8<PREC>(wb[c], wofs[c] + 256 * (k0 + u));
     }
 #pragma unroll
     for (int u = 0; u < KC; ++u) {
-      if (k0 + u >= ksteps) continue;
+      if (!kFull && k0 + u >= ksteps) continue;
       const int k = 32 * (k0 + u) + 8 * kg;
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb) {
@@ -428,13 +441,32 @@ __host__ __device__ inline int qgemm_big_col_tiles(int N, int epi, int cb) {
   return (N + per - 1) / per;
 }
 
+// Runtime K to the compile-time k-step counts of the model shapes in use
+// (K = 128, 192, 384, 512, 1536); other K run the generic loop.
+#define PSWA_KS_DISPATCH(K, CALL) \
+  switch ((K) / 32) {             \
+    case 4: CALL(4); break;       \
+    case 6: CALL(6); break;       \
+    case 12: CALL(12); break;     \
+    case 16: CALL(16); break;     \
+    case 48: CALL(48); break;     \
+    default: CALL(0); break;      \
+  }
+
 template <int AK, bool RMS, int EPI, int R = kMBq>
 __device__ __forceinline__ void gemm_tile_q_any(const GemmArgs& a, int bx, int by, uint8_t* lds,
                                                 float* rstd, float* rmul, bool stage = true) {
-  if (a.prec == PSWA_PREC_BF16)
-    gemm_tile_q<AK, RMS, EPI, PSWA_PREC_BF16, R>(a, bx, by, lds, rstd, rmul, stage);
-  else
-    gemm_tile_q<AK, RMS, EPI, PSWA_PREC_FP8, R>(a, bx, by, lds, rstd, rmul, stage);
+#define PSWA_TILE_BF16(KSV) \
+  gemm_tile_q<AK, RMS, EPI, PSWA_PREC_BF16, R, KSV>(a, bx, by, lds, rstd, rmul, stage)
+#define PSWA_TILE_FP8(KSV) \
+  gemm_tile_q<AK, RMS, EPI, PSWA_PREC_FP8, R, KSV>(a, bx, by, lds, rstd, rmul, stage)
+  if (a.prec == PSWA_PREC_BF16) {
+    PSWA_KS_DISPATCH(a.K, PSWA_TILE_BF16)
+  } else {
+    PSWA_KS_DISPATCH(a.K, PSWA_TILE_FP8)
+  }
+#undef PSWA_TILE_BF16
+#undef PSWA_TILE_FP8
 }
 
 }  // namespace dev

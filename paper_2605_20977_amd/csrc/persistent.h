@@ -29,9 +29,10 @@ struct SymArgs {
 //   per layer l: g(2+4l) QKV, a(1+l) attention, g(3+4l) O, g(4+4l) gate/up,
 //                g(5+4l) down,
 //   g(2+4L) head W1, g(3+4L) head W2, symbols, g(4+4L) embed, g(5+4L) acc K/V.
-// The argument tables are built on the host for every group, step and phase
-// and read by the kernel from device memory (uniform loads), so no argument
-// structure is ever built in per-lane memory.
+// The argument tables are built on the host for every group, step and phase.
+// At the start of a step every block copies the step's entries into LDS with
+// one round of loads; each phase then reads its entry from LDS into scalar
+// registers, so no phase waits on device memory for its arguments.
 struct GroupInfo {
   const GemmArgs* gtab;    // [T][6 + 4L]
   const AttnArgs* atab;    // [T][1 + L]
@@ -52,6 +53,7 @@ struct PersistArgs {
   int trace_len;
   int* xcd_tab;            // [grid]: XCD of each block, by (group, rank)
   int xcd_local;           // allow the one-XCD barrier for groups that qualify
+  int args_lds_off;        // byte offset of the step's argument copy in dynamic LDS
 };
 
 // Kernel instances: (projection arithmetic, head size, row tile). Each is
@@ -67,10 +69,20 @@ struct PersistArgs {
 #define PSWA_PERSISTENT_NAME_X(P_, D_, R_) PSWA_PERSISTENT_NAME(P_, D_, R_)
 #define PSWA_PERSISTENT_GETTER(P_, D_, R_) const void* PSWA_PERSISTENT_NAME_X(P_, D_, R_)()
 
-inline int gemm_phases(int L) { return 6 + 4 * L; }
-inline int attn_phases(int L) { return 1 + L; }
+__host__ __device__ inline int gemm_phases(int L) { return 6 + 4 * L; }
+__host__ __device__ inline int attn_phases(int L) { return 1 + L; }
 
+// Dynamic LDS of the kernel: the phases' work area, then the step's
+// argument copy at persistent_args_lds_offset().
 size_t persistent_lds_bytes(const NetDims& x, int prec, int rtile);
+size_t persistent_args_lds_offset(const NetDims& x, int prec, int rtile);
+// Bytes of one step's argument copy, and its parts' offsets within it.
+__host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
+__host__ __device__ inline size_t step_args_gemm_bytes(int L) { return align16(gemm_phases(L) * sizeof(GemmArgs)); }
+__host__ __device__ inline size_t step_args_attn_bytes(int L) { return align16(attn_phases(L) * sizeof(AttnArgs)); }
+__host__ __device__ inline size_t step_args_bytes(int L) {
+  return step_args_gemm_bytes(L) + step_args_attn_bytes(L) + align16(sizeof(SymArgs));
+}
 // Largest grid whose blocks can all be resident at once (0 on error).
 int persistent_max_grid(const NetDims& x, int prec, int rtile);
 void launch_persistent(const PersistArgs& P, const NetDims& x, int prec, int rtile, int grid,

@@ -25,13 +25,17 @@ __global__ void k_zero_ints(int* p, int n) {
 
 }  // namespace
 
-size_t persistent_lds_bytes(const NetDims& x, int prec, int rtile) {
+size_t persistent_args_lds_offset(const NetDims& x, int prec, int rtile) {
   size_t b = attn_lds_bytes(x.dh);
   for (int K : {x.F, x.d, x.C}) {
     const size_t g = prec ? qgemm_lds_bytes(K, prec, rtile) : gemm_lds_bytes(K);
     b = b > g ? b : g;
   }
-  return b;
+  return (b + 255) & ~size_t(255);
+}
+
+size_t persistent_lds_bytes(const NetDims& x, int prec, int rtile) {
+  return persistent_args_lds_offset(x, prec, rtile) + step_args_bytes(x.L);
 }
 
 // The instance for a model: projection arithmetic, head size and (for
@@ -76,9 +80,12 @@ void launch_persistent(const PersistArgs& P, const NetDims& x, int prec, int rti
     return ok;
   }();
   (void)attr;
-  void* args[] = {const_cast<PersistArgs*>(&P)};
-  (void)hipLaunchKernel(fn, dim3(grid), dim3(kThreads), args,
-                        persistent_lds_bytes(x, prec, prec ? rtile : kMBq), s);
+  const int rt = prec ? rtile : kMBq;
+  PersistArgs Q = P;
+  Q.args_lds_off = int(persistent_args_lds_offset(x, prec, rt));
+  void* args[] = {&Q};
+  (void)hipLaunchKernel(fn, dim3(grid), dim3(kThreads), args, persistent_lds_bytes(x, prec, rt),
+                        s);
 }
 
 }  // namespace pswa

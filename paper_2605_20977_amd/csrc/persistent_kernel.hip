@@ -94,22 +94,27 @@ template <int AK, bool RMS, int EPI, int PREC, int R>
 __device__ __forceinline__ void gemm_phase(const GemmArgs& a, float4* smem4, float* rstd,
                                            int rank, int nb) {
   __shared__ float rmul[kMBq];
-  if (PREC != PSWA_PREC_F32) {
+  if constexpr (PREC != PSWA_PREC_F32) {
     // tiles in row-tile-major order: a block re-stages A only when its next
     // tile starts a new row tile
     const int ct = qgemm_col_tiles(a.N, EPI), rt = qgemm_row_tiles(a.M, R);
-    int staged = -1;
-    for (int t = rank; t < ct * rt; t += nb) {
-      const int r = t / ct;
-      gemm_tile_q<AK, RMS, EPI, PREC, R>(a, t % ct, r, reinterpret_cast<uint8_t*>(smem4), rstd,
-                                         rmul, r != staged);
-      staged = r;
-    }
-    return;
+#define PSWA_TILES(KSV)                                                                    \
+  {                                                                                        \
+    int staged = -1;                                                                       \
+    for (int t = rank; t < ct * rt; t += nb) {                                             \
+      const int r = t / ct;                                                                \
+      gemm_tile_q<AK, RMS, EPI, PREC, R, KSV>(a, t % ct, r, reinterpret_cast<uint8_t*>(smem4), \
+                                              rstd, rmul, r != staged);                    \
+      staged = r;                                                                          \
+    }                                                                                      \
   }
-  const int ct = gemm_col_tiles(a.N, EPI), rt = gemm_row_tiles(a.M);
-  for (int t = rank; t < ct * rt; t += nb)
-    gemm_tile_any<AK, RMS, EPI>(a, t % ct, t / ct, smem4, rstd);
+    PSWA_KS_DISPATCH(a.K, PSWA_TILES)
+#undef PSWA_TILES
+  } else {
+    const int ct = gemm_col_tiles(a.N, EPI), rt = gemm_row_tiles(a.M);
+    for (int t = rank; t < ct * rt; t += nb)
+      gemm_tile_any<AK, RMS, EPI>(a, t % ct, t / ct, smem4, rstd);
+  }
 }
 
 template <int DH>
@@ -167,39 +172,56 @@ __global__ void __launch_bounds__(kThreads) k_persistent(PersistArgs P) {
   if (tracer && 2 * nsync + 1 < P.trace_len) P.trace[2 * nsync + 1] = wall_clock64(); \
   ++nsync;
 
-  for (int t = P.t_begin; t < t_end; ++t) {
-    const SymArgs sy = load_uniform(G.stab + t);
-    if (sy.M == 0) continue;  // same for every block of the group
-    const GemmArgs* g = G.gtab + (size_t)t * ng;
-    const AttnArgs* at = G.atab + (size_t)t * na;
+  // the step's argument copy in LDS, after the phases' work area
+  uint8_t* abase = reinterpret_cast<uint8_t*>(smem4) + P.args_lds_off;
+  GemmArgs* g = reinterpret_cast<GemmArgs*>(abase);
+  AttnArgs* at = reinterpret_cast<AttnArgs*>(abase + step_args_gemm_bytes(L));
+  SymArgs* ss = reinterpret_cast<SymArgs*>(abase + step_args_gemm_bytes(L) +
+                                           step_args_attn_bytes(L));
 
-    gemm_phase<A_FLOAT, true, EPI_STORE, PREC, R>(load_uniform(g + 0), smem4, rstd, rank, nb);
+  for (int t = P.t_begin; t < t_end; ++t) {
+    // copy the step's argument entries into LDS (every wave is done with the
+    // previous step's copy once it passes the barrier below)
+    __syncthreads();
+    copy_words_to_lds(reinterpret_cast<int*>(g),
+                      reinterpret_cast<const int*>(G.gtab + (size_t)t * ng),
+                      ng * (int)(sizeof(GemmArgs) / 4));
+    copy_words_to_lds(reinterpret_cast<int*>(at),
+                      reinterpret_cast<const int*>(G.atab + (size_t)t * na),
+                      na * (int)(sizeof(AttnArgs) / 4));
+    copy_words_to_lds(reinterpret_cast<int*>(ss), reinterpret_cast<const int*>(G.stab + t),
+                      (int)(sizeof(SymArgs) / 4));
+    __syncthreads();
+    const SymArgs sy = lds_uniform(ss);
+    if (sy.M == 0) continue;  // same for every block of the group
+
+    gemm_phase<A_FLOAT, true, EPI_STORE, PREC, R>(lds_uniform(g + 0), smem4, rstd, rank, nb);
     PSWA_SYNC
-    attn_phase<DH>(load_uniform(at + 0), smem, rank, nb);
+    attn_phase<DH>(lds_uniform(at + 0), smem, rank, nb);
     PSWA_SYNC
-    gemm_phase<A_FLOAT, false, EPI_RESID, PREC, R>(load_uniform(g + 1), smem4, rstd, rank, nb);
+    gemm_phase<A_FLOAT, false, EPI_RESID, PREC, R>(lds_uniform(g + 1), smem4, rstd, rank, nb);
     PSWA_SYNC
     for (int l = 0; l < L; ++l) {
-      gemm_phase<A_FLOAT, true, EPI_QKV, PREC, R>(load_uniform(g + 2 + 4 * l), smem4, rstd, rank, nb);
+      gemm_phase<A_FLOAT, true, EPI_QKV, PREC, R>(lds_uniform(g + 2 + 4 * l), smem4, rstd, rank, nb);
       PSWA_SYNC
-      attn_phase<DH>(load_uniform(at + 1 + l), smem, rank, nb);
+      attn_phase<DH>(lds_uniform(at + 1 + l), smem, rank, nb);
       PSWA_SYNC
-      gemm_phase<A_FLOAT, false, EPI_RESID, PREC, R>(load_uniform(g + 3 + 4 * l), smem4, rstd, rank, nb);
+      gemm_phase<A_FLOAT, false, EPI_RESID, PREC, R>(lds_uniform(g + 3 + 4 * l), smem4, rstd, rank, nb);
       PSWA_SYNC
-      gemm_phase<A_FLOAT, true, EPI_SWIGLU, PREC, R>(load_uniform(g + 4 + 4 * l), smem4, rstd, rank, nb);
+      gemm_phase<A_FLOAT, true, EPI_SWIGLU, PREC, R>(lds_uniform(g + 4 + 4 * l), smem4, rstd, rank, nb);
       PSWA_SYNC
-      gemm_phase<A_FLOAT, false, EPI_RESID, PREC, R>(load_uniform(g + 5 + 4 * l), smem4, rstd, rank, nb);
+      gemm_phase<A_FLOAT, false, EPI_RESID, PREC, R>(lds_uniform(g + 5 + 4 * l), smem4, rstd, rank, nb);
       PSWA_SYNC
     }
-    gemm_phase<A_FLOAT, true, EPI_SILU, PREC, R>(load_uniform(g + 2 + 4 * L), smem4, rstd, rank, nb);
+    gemm_phase<A_FLOAT, true, EPI_SILU, PREC, R>(lds_uniform(g + 2 + 4 * L), smem4, rstd, rank, nb);
     PSWA_SYNC
-    gemm_phase<A_FLOAT, false, EPI_HEAD, PREC, R>(load_uniform(g + 3 + 4 * L), smem4, rstd, rank, nb);
+    gemm_phase<A_FLOAT, false, EPI_HEAD, PREC, R>(lds_uniform(g + 3 + 4 * L), smem4, rstd, rank, nb);
     PSWA_SYNC
     symbol_phase(sy, rank, nb);
     PSWA_SYNC
-    gemm_phase<A_INT, false, EPI_STORE, PREC, R>(load_uniform(g + 4 + 4 * L), smem4, rstd, rank, nb);
+    gemm_phase<A_INT, false, EPI_STORE, PREC, R>(lds_uniform(g + 4 + 4 * L), smem4, rstd, rank, nb);
     PSWA_SYNC
-    gemm_phase<A_FLOAT, true, EPI_STORE, PREC, R>(load_uniform(g + 5 + 4 * L), smem4, rstd, rank, nb);
+    gemm_phase<A_FLOAT, true, EPI_STORE, PREC, R>(lds_uniform(g + 5 + 4 * L), smem4, rstd, rank, nb);
     PSWA_SYNC
   }
 #undef PSWA_SYNC
