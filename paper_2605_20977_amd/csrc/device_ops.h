@@ -367,21 +367,21 @@ __device__ __forceinline__ void gemm_tile_any(const GemmArgs& a, int bx, int by,
 // Key positions: a row's frame (fid, else the single frame0) gives its grid
 // and its offset in the global position space; temporal K/V of frame
 // position g in previous frame tau is at (tau * HWt + g) * 2d.
+// The frame of query row m.
+__device__ __forceinline__ FrameInfo attn_frame(const AttnArgs& a, int m) {
+  if (!a.fid) return a.frame0;
+  const int f = ldg(a.fid + m);
+  return FrameInfo{ldg(&a.frames[f].H), ldg(&a.frames[f].W), ldg(&a.frames[f].off),
+                   ldg(&a.frames[f].n_prev)};
+}
+
+// attn_item with the row's global position gp and frame fi already known.
 template <int DH>
-__device__ __forceinline__ void attn_item(const AttnArgs& a, int item, bool live, float* tr_all) {
+__device__ __forceinline__ void attn_item_at(const AttnArgs& a, int m, int hd, int gp,
+                                             const FrameInfo& fi, float* tr_all) {
   // each wave works alone in its own LDS region: no block-wide sync
   float* tr = tr_all + (threadIdx.x >> 6) * (DH * 65);
   const int lane = threadIdx.x & 63;
-  live = live && item < a.M * a.heads;
-  if (!live) return;
-  const int m = item / a.heads, hd = item % a.heads;
-  const int gp = map_row(a.pos, m);
-  FrameInfo fi = a.frame0;
-  if (a.fid) {
-    const int f = ldg(a.fid + m);
-    fi = FrameInfo{ldg(&a.frames[f].H), ldg(&a.frames[f].W), ldg(&a.frames[f].off),
-                   ldg(&a.frames[f].n_prev)};
-  }
   const int lp = gp - fi.off;
   const int pi = lp / fi.W, pj = lp % fi.W;
   const int r = a.r, k1 = 2 * r + 1;
@@ -491,6 +491,14 @@ __device__ __forceinline__ void attn_item(const AttnArgs& a, int item, bool live
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int DH>
+__device__ __forceinline__ void attn_item(const AttnArgs& a, int item, bool live, float* tr_all) {
+  live = live && item < a.M * a.heads;
+  if (!live) return;
+  const int m = item / a.heads, hd = item % a.heads;
+  attn_item_at<DH>(a, m, hd, map_row(a.pos, m), attn_frame(a, m), tr_all);
 }
 
 __host__ __device__ inline size_t attn_lds_bytes(int dh) {

@@ -299,30 +299,54 @@ __device__ __forceinline__ void gemm_tile_q(const GemmArgs& a, int bx, int by, u
       for (int u = 0; u < kKchunk; ++u)
         if (kFull || k0 + u < ksteps) b[u] = load_w8<PREC>(wbase, wofs + 256 * (k0 + u));
     }
+    // A fragments of 4 k-steps read from LDS together, then their MFMAs
 #pragma unroll
-    for (int u = 0; u < kKchunk; ++u) {
-      if (kFull || k0 + u < ksteps) {
-        const int k = 32 * (k0 + u) + 8 * kg;
-        const WT a0 = load_s8<PREC>(smem, (size_t)col * pitch + k);
-        c0 = mfma_q(a0, b[u], c0);
-        if (R == 32) c1 = mfma_q(load_s8<PREC>(smem, (size_t)(16 + col) * pitch + k), b[u], c1);
+    for (int u0 = 0; u0 < kKchunk; u0 += 4) {
+      WT a0[4], a1[4];
+#pragma unroll
+      for (int u = u0; u < u0 + 4; ++u) {
+        if (kFull || k0 + u < ksteps) {
+          const int k = 32 * (k0 + u) + 8 * kg;
+          a0[u - u0] = load_s8<PREC>(smem, (size_t)col * pitch + k);
+          if (R == 32) a1[u - u0] = load_s8<PREC>(smem, (size_t)(16 + col) * pitch + k);
+        }
+      }
+#pragma unroll
+      for (int u = u0; u < u0 + 4; ++u) {
+        if (kFull || k0 + u < ksteps) {
+          c0 = mfma_q(a0[u - u0], b[u], c0);
+          if (R == 32) c1 = mfma_q(a1[u - u0], b[u], c1);
+        }
       }
     }
   }
 
-  // 4. epilogue: lane holds rows 16*rb + 4*kg + i of its column
+  // 4. epilogue: lane holds rows 16*rb + 4*kg + i of its column; the row
+  // scales are read from LDS and the W2 partners exchanged for all of the
+  // lane's outputs first
   const float wsc = (PAIRED && col >= 8) ? a.w2scale : a.wscale;
+  float vv[R / 16][4], v2v[R / 16][4];
+#pragma unroll
+  for (int rb = 0; rb < R / 16; ++rb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int mrc = min(16 * rb + 4 * kg + i, rows - 1);
+      float v = (rb == 0 ? c0[i] : c1[i]) * wsc;
+      if (PREC == PSWA_PREC_FP8) v = v / rmul[mrc];
+      if (RMS) v *= rstd[mrc];
+      vv[rb][i] = v;
+    }
+#pragma unroll
+  for (int rb = 0; rb < R / 16; ++rb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      v2v[rb][i] = PAIRED ? __shfl(vv[rb][i], (lane & ~15) | ((col + 8) & 15), 64) : 0.f;
 #pragma unroll
   for (int rb = 0; rb < R / 16; ++rb) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int mr = 16 * rb + 4 * kg + i;
-      const float acc = rb == 0 ? c0[i] : c1[i];
-      const int mrc = min(mr, rows - 1);
-      float v = acc * wsc;
-      if (PREC == PSWA_PREC_FP8) v = v / rmul[mrc];
-      if (RMS) v *= rstd[mrc];
-      const float v2 = PAIRED ? __shfl(v, (lane & ~15) | ((col + 8) & 15), 64) : 0.f;
+      const float v = vv[rb][i], v2 = v2v[rb][i];
       if (mr >= rows) continue;
       if (PAIRED && col >= 8) continue;
       const int row = m0 + mr;

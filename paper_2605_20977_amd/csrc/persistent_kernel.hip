@@ -117,11 +117,31 @@ __device__ __forceinline__ void gemm_phase(const GemmArgs& a, float4* smem4, flo
   }
 }
 
+// A wave's items are g * kWaves + wave for g = rank, rank + nb, ...; the
+// positions and frames of up to 8 of them are loaded together before their
+// items run, so an item waits only on its own keys.
 template <int DH>
 __device__ __forceinline__ void attn_phase(const AttnArgs& a, float* smem, int rank, int nb) {
-  const int groups = (a.M * a.heads + kWaves - 1) / kWaves;
-  for (int g = rank; g < groups; g += nb)
-    attn_item<DH>(a, g * kWaves + (threadIdx.x >> 6), true, smem);
+  constexpr int PF = 8;
+  const int items = a.M * a.heads;
+  const int groups = (items + kWaves - 1) / kWaves;
+  const int wave = threadIdx.x >> 6;
+  for (int g0 = rank; g0 < groups; g0 += PF * nb) {
+    int gp[PF];
+    FrameInfo fi[PF];
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+      const int m = min((g0 + i * nb) * kWaves + wave, items - 1) / a.heads;
+      gp[i] = map_row(a.pos, m);
+      fi[i] = attn_frame(a, m);
+    }
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+      const int item = (g0 + i * nb) * kWaves + wave;
+      if (g0 + i * nb >= groups || item >= items) break;  // uniform across the wave
+      attn_item_at<DH>(a, item / a.heads, item % a.heads, gp[i], fi[i], smem);
+    }
+  }
 }
 
 __device__ __forceinline__ void symbol_phase(const SymArgs& c, int rank, int nb) {
