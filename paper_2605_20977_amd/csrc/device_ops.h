@@ -355,15 +355,53 @@ __device__ __forceinline__ void gemm_tile_any(const GemmArgs& a, int bx, int by,
 }
 
 // ------------------------------------------------------------ attention item
+// Sum of a LEN-element vector over the lanes of a wave, scattered: while the
+// length is even and lane-distance masks remain, partners (lane ^ MASK)
+// exchange halves and each keeps the sum of one half (the lane with the mask
+// bit set keeps the upper half, and off grows by LEN / 2 for it); the odd
+// remainder is then summed over the remaining masks in every lane of a group
+// of `group` lanes. Each sum adds the same two operands in both partners, so
+// every lane that holds an element holds the same bits, and the tree is the
+// same in every launch. On return v[0 .. merge_len) holds elements off ..
+// off + merge_len - 1 of the total.
+template <int LEN, int MASK>
+__host__ __device__ constexpr int merge_len() {
+  if constexpr (MASK > 0 && LEN % 2 == 0) return merge_len<LEN / 2, MASK / 2>();
+  else return LEN;
+}
+template <int LEN, int MASK>
+__device__ __forceinline__ void merge_lanes(float* v, int lane, int& off, int& group) {
+  if constexpr (MASK > 0 && LEN % 2 == 0) {
+    constexpr int H = LEN / 2;
+    const bool upper = (lane & MASK) != 0;
+    // in place: step j reads only v[j] and v[H + j]
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      const float send = upper ? v[j] : v[H + j];
+      const float keep = upper ? v[H + j] : v[j];
+      v[j] = keep + __shfl_xor(send, MASK, 64);
+    }
+    if (upper) off += H;
+    merge_lanes<H, MASK / 2>(v, lane, off, group);
+  } else {
+#pragma unroll
+    for (int mk = MASK; mk > 0; mk >>= 1) {
+#pragma unroll
+      for (int j = 0; j < LEN; ++j) v[j] = v[j] + __shfl_xor(v[j], mk, 64);
+    }
+    group = 2 * MASK > 0 ? 2 * MASK : 1;
+  }
+}
+
 // One 64-lane wave per (query row, head). Lane l owns keys l, l+64, ... in
 // slot order (spatial window, then the null slot or the temporal windows)
 // and runs an online softmax over them, loading each key's K and V rows
 // together. The lanes are then merged: common max and rescaled exp-sum by
-// wave reductions, the rescaled value vectors summed lane 0..63 in order
-// through the wave's own LDS region. Waves work independently (no block
-// synchronisation); a wave with `live` false or an item past the end
-// returns at once. Every lane loads the query row itself, together with its
-// first key, so one memory round trip serves both.
+// wave reductions, the rescaled value vectors by the butterfly of
+// merge_lanes (a fixed tree, in registers). Waves work independently (no
+// block synchronisation and no LDS); a wave with `live` false or an item
+// past the end returns at once. Every lane loads the query row itself,
+// together with its first key, so one memory round trip serves both.
 // Key positions: a row's frame (fid, else the single frame0) gives its grid
 // and its offset in the global position space; temporal K/V of frame
 // position g in previous frame tau is at (tau * HWt + g) * 2d.
@@ -379,8 +417,7 @@ __device__ __forceinline__ FrameInfo attn_frame(const AttnArgs& a, int m) {
 template <int DH>
 __device__ __forceinline__ void attn_item_at(const AttnArgs& a, int m, int hd, int gp,
                                              const FrameInfo& fi, float* tr_all) {
-  // each wave works alone in its own LDS region: no block-wide sync
-  float* tr = tr_all + (threadIdx.x >> 6) * (DH * 65);
+  (void)tr_all;  // no LDS: the merge runs in registers
   const int lane = threadIdx.x & 63;
   const int lp = gp - fi.off;
   const int pi = lp / fi.W, pj = lp % fi.W;
@@ -475,22 +512,18 @@ __device__ __forceinline__ void attn_item_at(const AttnArgs& a, int m, int hd, i
   const float gmx = wave_max(mx);
   const float f = mx == -INFINITY ? 0.f : expf(mx - gmx);
   const float tot = wave_sum(sum * f);
-  // lanes' rescaled value vectors summed lane 0..63 in order, through LDS
+  // lanes' rescaled value vectors summed over the 64 lanes by a fixed
+  // butterfly (see merge_lanes)
+  float v[DH];
 #pragma unroll
-  for (int e = 0; e < DH; ++e) tr[e * 65 + lane] = o[e] * f;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  if (lane < DH) {
-    float v = 0.f;
+  for (int e = 0; e < DH; ++e) v[e] = o[e] * f;
+  int off = 0, group = 1;
+  merge_lanes<DH, 32>(v, lane, off, group);
+  const int k = lane & (group - 1);
+  float val = v[0];  // v[k], by constant indices (a variable index would put v in scratch)
 #pragma unroll
-    for (int l = 0; l < 64; ++l) v += tr[lane * 65 + l];
-    stg(a.out + (size_t)m * a.ldo + hd * DH + lane, v / tot);
-  }
-  // the region is reused by this wave's next item
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int j = 1; j < merge_len<DH, 32>(); ++j) val = k == j ? v[j] : val;
+  if (k < merge_len<DH, 32>()) stg(a.out + (size_t)m * a.ldo + hd * DH + off + k, val / tot);
 }
 
 template <int DH>
@@ -501,9 +534,8 @@ __device__ __forceinline__ void attn_item(const AttnArgs& a, int item, bool live
   attn_item_at<DH>(a, m, hd, map_row(a.pos, m), attn_frame(a, m), tr_all);
 }
 
-__host__ __device__ inline size_t attn_lds_bytes(int dh) {
-  return (size_t)kWaves * dh * 65 * sizeof(float);  // one transpose buffer per wave
-}
+// Attention needs no LDS (the lanes are merged in registers).
+__host__ __device__ inline size_t attn_lds_bytes(int) { return 0; }
 
 template <int DH_dummy = 0>
 __device__ __forceinline__ void attn_item_any(const AttnArgs& a, int item, bool live,

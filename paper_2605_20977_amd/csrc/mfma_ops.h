@@ -235,12 +235,15 @@ __device__ __forceinline__ void stage_a(const GemmArgs& a, int m0, int rows, uin
 // row statistics) this block staged for the same row tile just before.
 // KS = K / 32 when known at compile time (0: read from the arguments); a
 // compile-time count lets the k loop run without branches, so its LDS reads
-// are issued ahead of the MFMAs. The arithmetic is the same either way.
-template <int AK, bool RMS, int EPI, int PREC, int R = kMBq, int KS = 0>
+// are issued ahead of the MFMAs. CB = groups of 16 weight rows per wave (a
+// wider tile: fewer tiles per block, each A fragment read once for all
+// groups). The arithmetic of an output is the same for every KS and CB.
+template <int AK, bool RMS, int EPI, int PREC, int R = kMBq, int KS = 0, int CB = 1>
 __device__ __forceinline__ void gemm_tile_q(const GemmArgs& a, int bx, int by, uint8_t* lds, float* rstd,
                             float* rmul, bool stage = true) {
   uint8_t* smem = lds + kQRedBytes;
   constexpr bool PAIRED = paired_epi(EPI);
+  constexpr int RB = R / 16;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int K = a.K;
   const int pitch = qgemm_pitch(K, PREC);
@@ -251,40 +254,51 @@ __device__ __forceinline__ void gemm_tile_q(const GemmArgs& a, int bx, int by, u
   // waves run on without a block barrier
   if (stage) __syncthreads();
 
-  // 3. MFMA over K for this wave's 16 weight rows; the first chunk of
-  // weight loads is issued before the A rows are staged
+  // 3. MFMA over K for this wave's CB groups of 16 weight rows (8 W and 8
+  // W2 rows per group for the paired epilogues)
   typedef typename QOp<PREC>::T WT;
   const int col = lane & 15, kg = lane >> 4;
-  int wn;                 // weight row this lane streams
-  const void* wbase;
-  if (PAIRED) {
-    wn = min(bx * kWaves * 8 + wave * 8 + (col & 7), a.N - 1);
-    wbase = col < 8 ? a.Wq : a.W2q;
-  } else {
-    wn = min(bx * kWaves * 16 + wave * 16 + col, a.N - 1);
-    wbase = a.Wq;
-  }
+  const int per_wave = (PAIRED ? 8 : 16) * CB;
+  const int nbase = bx * kWaves * per_wave + wave * per_wave;
   const int ksteps = KS ? KS : K / 32;
   constexpr bool kFull = KS > 0 && KS % kKchunk == 0;  // every chunk complete
-  const size_t wofs = wfrag_offset(wn, kg, ksteps);
+  size_t wofs[CB];
+  const void* wbase[CB];
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    int wn;  // weight row this lane streams for group c
+    if (PAIRED) {
+      wn = min(nbase + 8 * c + (col & 7), a.N - 1);
+      wbase[c] = col < 8 ? a.Wq : a.W2q;
+    } else {
+      wn = min(nbase + 16 * c + col, a.N - 1);
+      wbase[c] = a.Wq;
+    }
+    wofs[c] = wfrag_offset(wn, kg, ksteps);
+  }
   // weight loads of the first chunk and the residual inputs of this lane's
   // outputs: issued right after the A rows' first loads (or at once when
   // the staged rows are reused)
-  WT b[kKchunk];
-  float rres[R / 16][4];
+  WT b[CB][kKchunk];
+  float rres[CB][RB][4];
   auto issue_w = [&]() {
 #pragma unroll
-    for (int u = 0; u < kKchunk; ++u)
-      if (u < ksteps) b[u] = load_w8<PREC>(wbase, wofs + 256 * u);
+    for (int c = 0; c < CB; ++c)
+#pragma unroll
+      for (int u = 0; u < kKchunk; ++u)
+        if (u < ksteps) b[c][u] = load_w8<PREC>(wbase[c], wofs[c] + 256 * u);
     if constexpr (EPI == EPI_RESID) {
-      const int nc = min(bx * kWaves * 16 + wave * 16 + col, a.N - 1);
 #pragma unroll
-      for (int rb = 0; rb < R / 16; ++rb)
+      for (int c = 0; c < CB; ++c) {
+        const int nc = min(nbase + 16 * c + col, a.N - 1);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int row = m0 + min(16 * rb + 4 * kg + i, rows - 1);
-          rres[rb][i] = ldg(a.R + (size_t)map_row(a.rrow, row) * a.ldr + nc);
-        }
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int row = m0 + min(16 * rb + 4 * kg + i, rows - 1);
+            rres[c][rb][i] = ldg(a.R + (size_t)map_row(a.rrow, row) * a.ldr + nc);
+          }
+      }
     }
   };
   if (stage)
@@ -292,30 +306,40 @@ __device__ __forceinline__ void gemm_tile_q(const GemmArgs& a, int bx, int by, u
   else
     issue_w();
 
-  f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+  f32x4 acc[CB][RB];
+#pragma unroll
+  for (int c = 0; c < CB; ++c)
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) acc[c][rb] = f32x4{0.f, 0.f, 0.f, 0.f};
   for (int k0 = 0; k0 < ksteps; k0 += kKchunk) {
     if (k0 > 0) {
 #pragma unroll
-      for (int u = 0; u < kKchunk; ++u)
-        if (kFull || k0 + u < ksteps) b[u] = load_w8<PREC>(wbase, wofs + 256 * (k0 + u));
+      for (int c = 0; c < CB; ++c)
+#pragma unroll
+        for (int u = 0; u < kKchunk; ++u)
+          if (kFull || k0 + u < ksteps) b[c][u] = load_w8<PREC>(wbase[c], wofs[c] + 256 * (k0 + u));
     }
     // A fragments of 4 k-steps read from LDS together, then their MFMAs
 #pragma unroll
     for (int u0 = 0; u0 < kKchunk; u0 += 4) {
-      WT a0[4], a1[4];
+      WT af[RB][4];
 #pragma unroll
       for (int u = u0; u < u0 + 4; ++u) {
         if (kFull || k0 + u < ksteps) {
           const int k = 32 * (k0 + u) + 8 * kg;
-          a0[u - u0] = load_s8<PREC>(smem, (size_t)col * pitch + k);
-          if (R == 32) a1[u - u0] = load_s8<PREC>(smem, (size_t)(16 + col) * pitch + k);
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+            af[rb][u - u0] = load_s8<PREC>(smem, (size_t)(16 * rb + col) * pitch + k);
         }
       }
 #pragma unroll
       for (int u = u0; u < u0 + 4; ++u) {
         if (kFull || k0 + u < ksteps) {
-          c0 = mfma_q(a0[u - u0], b[u], c0);
-          if (R == 32) c1 = mfma_q(a1[u - u0], b[u], c1);
+#pragma unroll
+          for (int c = 0; c < CB; ++c)
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+              acc[c][rb] = mfma_q(af[rb][u - u0], b[c][u], acc[c][rb]);
         }
       }
     }
@@ -325,40 +349,55 @@ __device__ __forceinline__ void gemm_tile_q(const GemmArgs& a, int bx, int by, u
   // scales are read from LDS and the W2 partners exchanged for all of the
   // lane's outputs first
   const float wsc = (PAIRED && col >= 8) ? a.w2scale : a.wscale;
-  float vv[R / 16][4], v2v[R / 16][4];
+  float rsc[RB][4], rst[RB][4];  // the rows' FP8 input scales and 1/rms
 #pragma unroll
-  for (int rb = 0; rb < R / 16; ++rb)
+  for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int mrc = min(16 * rb + 4 * kg + i, rows - 1);
-      float v = (rb == 0 ? c0[i] : c1[i]) * wsc;
-      if (PREC == PSWA_PREC_FP8) v = v / rmul[mrc];
-      if (RMS) v *= rstd[mrc];
-      vv[rb][i] = v;
+      rsc[rb][i] = PREC == PSWA_PREC_FP8 ? rmul[mrc] : 1.0f;
+      rst[rb][i] = RMS ? rstd[mrc] : 1.0f;
     }
 #pragma unroll
-  for (int rb = 0; rb < R / 16; ++rb)
+  for (int c = 0; c < CB; ++c) {
+    float vv[RB][4], v2v[RB][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      v2v[rb][i] = PAIRED ? __shfl(vv[rb][i], (lane & ~15) | ((col + 8) & 15), 64) : 0.f;
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-  for (int rb = 0; rb < R / 16; ++rb) {
+      for (int i = 0; i < 4; ++i) {
+        float v = acc[c][rb][i] * wsc;
+        if (PREC == PSWA_PREC_FP8) v = v / rsc[rb][i];
+        if (RMS) v *= rst[rb][i];
+        vv[rb][i] = v;
+      }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int mr = 16 * rb + 4 * kg + i;
-      const float v = vv[rb][i], v2 = v2v[rb][i];
-      if (mr >= rows) continue;
-      if (PAIRED && col >= 8) continue;
-      const int row = m0 + mr;
-      const int n =
-          PAIRED ? bx * kWaves * 8 + wave * 8 + col : bx * kWaves * 16 + wave * 16 + col;
-      if (n >= a.N) continue;
-      if constexpr (EPI == EPI_RESID)
-        stg(a.Y + (size_t)map_row(a.yrow, row) * a.ldy + n, rres[rb][i] + v);
-      else
-        epilogue<EPI>(a, row, n, v, v2);
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        v2v[rb][i] = PAIRED ? __shfl(vv[rb][i], (lane & ~15) | ((col + 8) & 15), 64) : 0.f;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int mr = 16 * rb + 4 * kg + i;
+        if (mr >= rows) continue;
+        if (PAIRED && col >= 8) continue;
+        const int row = m0 + mr;
+        const int n = PAIRED ? nbase + 8 * c + col : nbase + 16 * c + col;
+        if (n >= a.N) continue;
+        if constexpr (EPI == EPI_RESID)
+          stg(a.Y + (size_t)map_row(a.yrow, row) * a.ldy + n, rres[c][rb][i] + vv[rb][i]);
+        else
+          epilogue<EPI>(a, row, n, vv[rb][i], v2v[rb][i]);
+      }
     }
   }
+}
+
+// Column tiles of a small tile with CB groups per wave.
+__host__ __device__ inline int qgemm_col_tiles_cb(int N, int epi, int cb) {
+  const int per = kWaves * (paired_epi(epi) ? 8 : 16) * cb;
+  return (N + per - 1) / per;
 }
 
 // Large-M tile: R A rows x (kWaves * CB * 16) weight rows per block. Each

@@ -97,16 +97,17 @@ __device__ __forceinline__ void gemm_phase(const GemmArgs& a, float4* smem4, flo
   if constexpr (PREC != PSWA_PREC_F32) {
     // tiles in row-tile-major order: a block re-stages A only when its next
     // tile starts a new row tile
-    const int ct = qgemm_col_tiles(a.N, EPI), rt = qgemm_row_tiles(a.M, R);
-#define PSWA_TILES(KSV)                                                                    \
-  {                                                                                        \
-    int staged = -1;                                                                       \
-    for (int t = rank; t < ct * rt; t += nb) {                                             \
-      const int r = t / ct;                                                                \
+    const int rt = qgemm_row_tiles(a.M, R);
+#define PSWA_TILES(KSV)                                                                        \
+  {                                                                                            \
+    const int ct = qgemm_col_tiles(a.N, EPI);                                                  \
+    int staged = -1;                                                                           \
+    for (int t = rank; t < ct * rt; t += nb) {                                                 \
+      const int r = t / ct;                                                                    \
       gemm_tile_q<AK, RMS, EPI, PREC, R, KSV>(a, t % ct, r, reinterpret_cast<uint8_t*>(smem4), \
-                                              rstd, rmul, r != staged);                    \
-      staged = r;                                                                          \
-    }                                                                                      \
+                                              rstd, rmul, r != staged);                        \
+      staged = r;                                                                              \
+    }                                                                                          \
   }
     PSWA_KS_DISPATCH(a.K, PSWA_TILES)
 #undef PSWA_TILES
