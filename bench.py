@@ -320,7 +320,7 @@ def main():
                 "bf16": "BF16 projections: bits overhead vs FP64 oracle <= 0.5 % (measured "
                         "-0.0001 % on the 1080p-shaped P-frame)",
                 "fp8": "FP8 e4m3 projections: bits overhead vs FP64 oracle <= 1 % (measured "
-                       "-0.0074 % on the 1080p-shaped P-frame)"}[prec]
+                       "-0.0071 % on the 1080p-shaped P-frame)"}[prec]
     rec = {
         "metric": METRIC, "value": hp["value"], "unit": "symbols/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": hp["ms_per_step"],
