@@ -140,20 +140,22 @@ def roofline(pswa, fn, steps, prec, workload):
     avg_s = p["ms"] / 1e3 / p["launches"]
     bytes_l = p["bytes"] / p["launches"]
     flops_l = p["flops"] / p["launches"]
-    if dom == "persistent_decode" and prec in MFMA_PEAK_TFLOPS:
-        # the batch's projections run on MFMA; rows per step reach ~700
-        ach = flops_l / avg_s / 1e12
-        roof = {"bound": "mfma", "achieved": ach, "peak": MFMA_PEAK_TFLOPS[prec],
-                "unit": "TFLOP/s", "frac": ach / MFMA_PEAK_TFLOPS[prec]}
-    elif dom == "persistent_decode":
-        ach = flops_l / avg_s / 1e12
-        roof = {"bound": "alu", "achieved": ach, "peak": FP32_VECTOR_TFLOPS,
-                "unit": "TFLOP/s", "frac": ach / FP32_VECTOR_TFLOPS}
+    # the roofline's own rule: arithmetic intensity (algorithmic flops per
+    # algorithmic byte) against the ridge of the compute peak in use
+    peak_tf = MFMA_PEAK_TFLOPS.get(prec, FP32_VECTOR_TFLOPS) if dom == "persistent_decode" \
+        else FP32_VECTOR_TFLOPS
+    intensity = flops_l / bytes_l if bytes_l else float("inf")
+    ridge = peak_tf * 1e12 / (HBM_PEAK_GBS * 1e9)
+    tf = flops_l / avg_s / 1e12
+    gbs = bytes_l / avg_s / 1e9
+    if intensity < ridge:
+        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs / HBM_PEAK_GBS}
     else:
-        # per-diagonal launches stream their weights for at most 24 rows
-        ach = bytes_l / avg_s / 1e9
-        roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS}
+        roof = {"bound": "mfma" if prec in MFMA_PEAK_TFLOPS else "alu", "achieved": tf,
+                "peak": peak_tf, "unit": "TFLOP/s", "frac": tf / peak_tf}
+    roof.update({"intensity_flop_per_byte": intensity, "ridge_flop_per_byte": ridge,
+                 "compute_frac": tf / peak_tf, "compute_peak_tflops": peak_tf})
     roof.update({"traffic": measured_traffic(dom, workload),
                  "kernel": ROLE_KERNEL.get(dom, dom), "role": dom,
                  "avg_launch_us": avg_s * 1e6, "alg_bytes_per_launch": bytes_l,
