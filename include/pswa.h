@@ -275,7 +275,7 @@ pswa_status pswa_batch_set_spin_limit(pswa_batch* batch, int64_t spins);
  * persistent kernel (rank 0 of group 0) writes the device wall clock
  * (100 MHz) when it reaches and when it leaves each of its group's barriers:
  * d_trace[2k] and d_trace[2k + 1] for barrier k, for 2k + 1 < n (device
- * int64). Barriers per step: 3 + 5 L + 5. n = 0 turns the trace off. */
+ * int64). Barriers per step: 3 + 5 L + 4. n = 0 turns the trace off. */
 pswa_status pswa_batch_trace(pswa_batch* batch, int64_t* d_trace, int n);
 void pswa_batch_destroy(pswa_batch* batch);
 

@@ -223,7 +223,14 @@ void build_tables(const pswa_batch* b, const GroupPlan& g, std::vector<GemmArgs>
       at->push_back(args_attn(x, w, c, l));
     }
     gt->push_back(args_head1(x, w, c));
-    gt->push_back(args_head2(x, w, c));
+    // the persistent kernel gathers the step's symbols and computes their bits
+    // in the head epilogue (no separate symbols phase)
+    GemmArgs h2 = args_head2(x, w, c);
+    h2.head.ysrc = c.ysrc;
+    h2.head.src_compact = c.src_compact;
+    h2.head.ydec = c.ydec;
+    h2.head.bits = c.bits;
+    gt->push_back(h2);
     gt->push_back(args_embed(x, w, c));
     gt->push_back(args_acc_kv(x, w, c));
     stb->push_back(SymArgs{c.M, x.C, c.gpos, c.ysrc, c.src_compact, c.ydec, c.mean, c.scale,

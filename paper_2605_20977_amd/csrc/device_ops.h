@@ -165,6 +165,16 @@ __host__ __device__ inline size_t gemm_lds_bytes(int K) {
   return tile > red ? tile : red;
 }
 
+// -log2(max(P, 1e-9)) of integer symbol y under the discretised Gaussian
+// N(mean, scale): P = Phi((|y - mean| + 1/2) / scale) - Phi((|y - mean| - 1/2) / scale),
+// written with erfc.
+__device__ __forceinline__ float symbol_bits_of(int32_t y, float mean, float scale) {
+  const float v = fabsf(float(y) - mean);
+  const float s2 = scale * 1.41421356237309515f;
+  const float p = 0.5f * (erfcf((v - 0.5f) / s2) - erfcf((v + 0.5f) / s2));
+  return -log2f(fmaxf(p, 1e-9f));
+}
+
 // Epilogue of one GEMM output (row, n): v is the finished dot product with
 // W, v2 the one with W2 (paired epilogues only).
 template <int EPI>
@@ -200,6 +210,11 @@ __device__ __forceinline__ void epilogue(const GemmArgs& a, int row, int n, floa
     if (h.center_c) {
       stg(h.center_c + (size_t)row * a.N + n, c);
       stg(h.index_c + (size_t)row * a.N + n, x);
+    }
+    if (h.ydec) {  // the row's symbol and its bits, from the values just computed
+      const int32_t y = ldg(h.ysrc + (h.src_compact ? (size_t)row * a.N + n : o));
+      stg(h.ydec + o, y);
+      stg(h.bits + o, symbol_bits_of(y, mu, sg));
     }
     if (!(fabsf(mu) <= FLT_MAX) || !(fabsf(raw) <= FLT_MAX)) atomicOr(h.flag, 1);
   }
@@ -563,10 +578,7 @@ __device__ __forceinline__ void bits_item(const int* pos, int C, const int32_t* 
                                           long idx) {
   const int m = idx / C, c = idx % C;
   const size_t o = (size_t)map_row(pos, m) * C + c;
-  const float v = fabsf(float(ldg(ydec + o)) - ldg(mean + o));
-  const float s2 = ldg(scale + o) * 1.41421356237309515f;
-  const float p = 0.5f * (erfcf((v - 0.5f) / s2) - erfcf((v + 0.5f) / s2));
-  stg(bits + o, -log2f(fmaxf(p, 1e-9f)));
+  stg(bits + o, symbol_bits_of(ldg(ydec + o), ldg(mean + o), ldg(scale + o)));
 }
 
 }  // namespace dev

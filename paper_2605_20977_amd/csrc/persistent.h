@@ -5,8 +5,9 @@
 
 namespace pswa {
 
-// Symbols phase of one global step: gather the step's symbols from the
-// source and compute their bits.
+// Symbols of one global step: its rows, the symbol source and the outputs.
+// The kernel reads M to skip an empty step; the symbols themselves are
+// gathered, and their bits computed, in the head projection's epilogue.
 struct SymArgs {
   int M, C;
   const int* gpos;
@@ -28,7 +29,8 @@ struct SymArgs {
 //   g0 acc q, a0 acc attention, g1 acc O,
 //   per layer l: g(2+4l) QKV, a(1+l) attention, g(3+4l) O, g(4+4l) gate/up,
 //                g(5+4l) down,
-//   g(2+4L) head W1, g(3+4L) head W2, symbols, g(4+4L) embed, g(5+4L) acc K/V.
+//   g(2+4L) head W1, g(3+4L) head W2 (whose epilogue also gathers the step's
+//   symbols and their bits), g(4+4L) embed, g(5+4L) acc K/V.
 // The argument tables are built on the host for every group, step and phase.
 // At the start of a step every block copies the step's entries into LDS with
 // one round of loads; each phase then reads its entry from LDS into scalar

@@ -145,13 +145,6 @@ __device__ __forceinline__ void attn_phase(const AttnArgs& a, float* smem, int r
   }
 }
 
-__device__ __forceinline__ void symbol_phase(const SymArgs& c, int rank, int nb) {
-  const long n = (long)c.M * c.C;
-  for (long i = (long)rank * blockDim.x + threadIdx.x; i < n; i += (long)nb * blockDim.x) {
-    gather_item(c.ysrc, c.src_compact, c.gpos, c.C, c.ydec, i);
-    bits_item(c.gpos, c.C, c.ydec, c.mean, c.scale, c.bits, i);
-  }
-}
 
 // PREC: the projections' arithmetic (FP32 SIMT, or BF16 / FP8 on MFMA); one
 // instance per (arithmetic, head size, row tile) keeps each one's registers
@@ -236,9 +229,8 @@ __global__ void __launch_bounds__(kThreads) k_persistent(PersistArgs P) {
     }
     gemm_phase<A_FLOAT, true, EPI_SILU, PREC, R>(lds_uniform(g + 2 + 4 * L), smem4, rstd, rank, nb);
     PSWA_SYNC
+    // head W2: mean, scale, CDF selection, and the step's symbols and bits
     gemm_phase<A_FLOAT, false, EPI_HEAD, PREC, R>(lds_uniform(g + 3 + 4 * L), smem4, rstd, rank, nb);
-    PSWA_SYNC
-    symbol_phase(sy, rank, nb);
     PSWA_SYNC
     gemm_phase<A_INT, false, EPI_STORE, PREC, R>(lds_uniform(g + 4 + 4 * L), smem4, rstd, rank, nb);
     PSWA_SYNC

@@ -47,6 +47,12 @@ struct HeadOut {
   int32_t* center_c;                     // compact [M][C] copies (or null)
   uint16_t* index_c;
   int* flag;                             // set to 1 on a non-finite mean/scale
+  // optional (persistent decode): gather the row's symbols and their bits in
+  // the same epilogue; ydec[yrow(m)][n] = ysrc[(src_compact ? m : yrow(m))][n]
+  const int32_t* ysrc;
+  int src_compact;
+  int32_t* ydec;                         // null: no symbols in the epilogue
+  float* bits;                           // [HW][C] rows yrow(m)
 };
 
 struct GemmArgs {
