@@ -118,33 +118,36 @@ __device__ __forceinline__ void gemm_phase(const GemmArgs& a, float4* smem4, flo
   }
 }
 
-// A wave's items are g * kWaves + wave for g = rank, rank + nb, ...; the
-// positions and frames of up to 8 of them are loaded together before their
-// items run, so an item waits only on its own keys.
+// Items in head-major order (item = head * M + row): a wave takes a
+// contiguous run of them, so its consecutive items are adjacent rows of one
+// head, whose key windows overlap (their K/V rows are then still in cache).
+// The positions and frames of up to 8 items are loaded together before they
+// run, so an item waits only on its own keys.
 template <int DH>
 __device__ __forceinline__ void attn_phase(const AttnArgs& a, float* smem, int rank, int nb) {
   constexpr int PF = 8;
   const int items = a.M * a.heads;
-  const int groups = (items + kWaves - 1) / kWaves;
-  const int wave = threadIdx.x >> 6;
-  for (int g0 = rank; g0 < groups; g0 += PF * nb) {
+  const int nw = nb * kWaves;
+  const int per = (items + nw - 1) / nw;
+  const int i0 = min(items, (rank * kWaves + (int)(threadIdx.x >> 6)) * per);
+  const int i1 = min(items, i0 + per);
+  for (int b0 = i0; b0 < i1; b0 += PF) {
     int gp[PF];
     FrameInfo fi[PF];
 #pragma unroll
     for (int i = 0; i < PF; ++i) {
-      const int m = min((g0 + i * nb) * kWaves + wave, items - 1) / a.heads;
+      const int m = min(b0 + i, i1 - 1) % a.M;
       gp[i] = map_row(a.pos, m);
       fi[i] = attn_frame(a, m);
     }
 #pragma unroll
     for (int i = 0; i < PF; ++i) {
-      const int item = (g0 + i * nb) * kWaves + wave;
-      if (g0 + i * nb >= groups || item >= items) break;  // uniform across the wave
-      attn_item_at<DH>(a, item / a.heads, item % a.heads, gp[i], fi[i], smem);
+      const int item = b0 + i;
+      if (item >= i1) break;  // uniform across the wave
+      attn_item_at<DH>(a, item % a.M, item / a.M, gp[i], fi[i], smem);
     }
   }
 }
-
 
 // PREC: the projections' arithmetic (FP32 SIMT, or BF16 / FP8 on MFMA); one
 // instance per (arithmetic, head size, row tile) keeps each one's registers
