@@ -1,7 +1,10 @@
 """Build the HIP library libpswa.so in-tree with hipcc for gfx950.
 
-Usage: python paper_2605_20977_amd/build.py   (or __graft_entry__.build()).
-It does not import the package, so it works with no library built.
+Usage: python paper_2605_20977_amd/build.py [--incremental]
+(or __graft_entry__.build(), which always compiles every object).
+--incremental recompiles only objects older than their source or any header
+under csrc/ and include/. It does not import the package, so it works with
+no library built.
 """
 from __future__ import annotations
 
@@ -40,8 +43,25 @@ def _run(cmd):
     return r.returncode, err
 
 
-def build(verbose: bool = True, jobs: int | None = None) -> str:
-    """Compile every object (in parallel) and link libpswa.so."""
+def _headers_mtime() -> float:
+    t = 0.0
+    for d in (CSRC, os.path.join(ROOT, "include")):
+        for f in os.listdir(d):
+            if f.endswith(".h"):
+                t = max(t, os.path.getmtime(os.path.join(d, f)))
+    return t
+
+
+def _stale(cmd, hdr_mtime: float) -> bool:
+    obj, src = cmd[-1], cmd[-3]
+    if not os.path.exists(obj):
+        return True
+    return os.path.getmtime(obj) < max(hdr_mtime, os.path.getmtime(src))
+
+
+def build(verbose: bool = True, jobs: int | None = None, incremental: bool = False) -> str:
+    """Compile every object (in parallel; only the stale ones when
+    incremental) and link libpswa.so."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     os.makedirs(OBJ, exist_ok=True)
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
@@ -54,10 +74,14 @@ def build(verbose: bool = True, jobs: int | None = None) -> str:
     for src in SOURCES:
         obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
         units.append([hipcc, *HIPCC_FLAGS, *inc, "-c", os.path.join(CSRC, src), "-o", obj])
+    objs = [u[-1] for u in units]
+    if incremental:
+        hdr = _headers_mtime()
+        units = [u for u in units if _stale(u, hdr)]
     jobs = jobs or min(16, os.cpu_count() or 1)
     if verbose:
         print(f"compiling {len(units)} objects with {jobs} jobs", flush=True)
-    with ThreadPoolExecutor(jobs) as ex:
+    with ThreadPoolExecutor(max(1, jobs)) as ex:
         results = list(ex.map(_run, units))
     failed = False
     for cmd, (rc, err) in zip(units, results):
@@ -69,7 +93,6 @@ def build(verbose: bool = True, jobs: int | None = None) -> str:
     if failed:
         raise RuntimeError("hipcc failed building libpswa.so")
     tmp = LIB + ".tmp"
-    objs = [u[-1] for u in units]
     link = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     rc, err = _run(link)
     if rc != 0:
@@ -82,4 +105,4 @@ def build(verbose: bool = True, jobs: int | None = None) -> str:
 
 
 if __name__ == "__main__":
-    build()
+    build(incremental="--incremental" in sys.argv[1:])

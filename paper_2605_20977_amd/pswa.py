@@ -675,3 +675,8 @@ def pswa_student_accept(bits_student, bits_full, max_overhead=0.01):
     by at most max_overhead (a fraction)."""
     return bool(_lib.pswa_student_accept(float(bits_student), float(bits_full),
                                          float(max_overhead)))
+
+
+def make_model(cfg, weights, prec="fp32", device="cuda"):
+    """A model in the given arithmetic, ready to run."""
+    return Model(cfg, weights, prec, device)

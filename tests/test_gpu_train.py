@@ -138,3 +138,31 @@ def test_distillation_gains(P):
     print(f"student bits overhead vs full model: untrained {100 * ov0:+.2f} %, "
           f"trained {100 * ov1:+.2f} %", flush=True)
     assert ov1 < ov0
+
+
+@pytest.mark.parametrize("n_prev", [0, 2])
+def test_gradients_match_oracle_student_shape(P, n_prev):
+    """The student's own kernel instances: 2 layers, d = 128, 4 heads of 32,
+    causal 9 x 9 window (41 spatial and 162 temporal key slots), C = 192,
+    on two 10 x 13 crops (every window clipped by a border somewhere)."""
+    from oracle import train as ot
+    cfg = synth.STUDENT
+    teacher = synth.model_weights(cfg, 15)
+    student = synth.model_weights(cfg, 16)
+    crops = _crops(cfg, teacher, 2, 10, 13, n_prev, 400 + 10 * n_prev)
+    print(f"case train grads student shape 2x10x13 P={n_prev}", flush=True)
+    tr = P.Trainer(cfg, student, max_crops=2, H=10, W=13)
+    loss = _step(tr, crops, update=False)
+    G = tr.read("grads")
+    ref_loss, ref = ot.loss_and_grads(cfg, {k: v.astype(np.float64) for k, v in student.items()},
+                                      crops)
+    print(f"loss gpu {loss:.9g} oracle {ref_loss:.9g}", flush=True)
+    assert abs(loss - ref_loss) <= 1e-5 * ref_loss
+    worst = 0.0
+    for k, g in ref.items():
+        nrm = np.linalg.norm(g)
+        err = np.linalg.norm(G[k].astype(np.float64) - g)
+        rel = err / max(nrm, 1e-30)
+        worst = max(worst, rel if nrm > 1e-8 else 0.0)
+        assert err <= 2e-4 * nrm + 1e-9, (k, rel, nrm)
+    print(f"worst relative gradient error {worst:.3e}", flush=True)
