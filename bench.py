@@ -10,20 +10,38 @@ frame); inputs resident in HBM, symbols read from device memory. Paths
   mixed<N>:<prec>  -- N frames of the mixed batch (15x20, 34x60, 45x80 and
                       68x120 in equal numbers, I- and P-frames alternating)
                       in one persistent launch;
-  cyclic<N>:<prec>  -- N 1080p I-frames decoded with the paper's cyclic
+  cyclic<N>:<prec> -- N 1080p I-frames decoded with the paper's cyclic
                       schedule (step = (i + j) mod 4, full 7x7 window: 4
                       steps per frame) by a model of the same widths;
   student4k:<prec> -- one 4K-shaped I-frame and one P-frame (135x240x192)
-                      decoded by the 2-layer d=128 student model (weights
-                      at initialization: the rate does not depend on them);
-with <prec> one of fp32, bf16, fp8. Persistent paths split their frames into
-groups that run behind their own barriers; the library's autotuner picks the
-grouping and row tile, and runs replay a captured HIP graph, unless told not
-to. One step = one pass of a path over its batch. The headline `value` is the
-fastest path; `paths` gives every path's rate and its ratio to plain FP32.
-The roofline is that of the headline path's dominant kernel, timed live with
-HIP events on its launch stream over an instrumented repeat of the timed
-steps (issued kernel by kernel).
+                      decoded by the 2-layer d=128 student model;
+  student4k<N>:<prec>, full4k<N>:<prec> -- N 4K-shaped frames (I and P
+                      alternating) decoded by the student and by the full
+                      model (the student's speed-up);
+  encode:<prec>    -- the parallel encode form of one 1080p I-frame;
+  bitstream:<prec> -- one 1080p I-frame decoded step by step from its range-
+                      coded bitstream (host range decoder, one thread, in
+                      the loop at every diagonal);
+with <prec> one of fp32, bf16, fp8 (FP8 activations scaled per tensor from
+maxima calibrated on frames no path decodes). Persistent paths split their
+frames into groups that run behind their own barriers; the library's
+autotuner picks the grouping and row tile, and runs replay a captured HIP
+graph, unless told not to. One step = one pass of a path over its batch.
+
+The headline `value` is the BF16 1080p batch; `paths` gives every path's rate
+and its ratio to plain FP32. After timing, frame 0 of the headline batch is
+checked bit for bit against the encode form of the same model, and its total
+bits are compared with the FP32 path and with the FP64 oracle (the oracle's
+prediction of that frame is the first frame of the CPU baseline).
+
+Roofline: the headline's dominant kernel, timed live with HIP events on its
+launch stream over an instrumented repeat of the timed steps. Its
+algorithmic work follows the method, not the implementation: 2 flops per
+multiply-add of the network (15,383,808 per position of an I-frame of the
+1080p-shaped model) and, in bytes, the projection weights once per global
+step of the batch plus each frame's own resident data (latents and
+hyperprior read, hyper tokens, accumulator and layer key/value caches
+written and read once, the per-symbol outputs written once).
 """
 from __future__ import annotations
 
@@ -31,6 +49,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -42,16 +61,19 @@ HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp8": 5000.0}
 FP32_VECTOR_TFLOPS = 157.3
 METRIC = "decoded latent symbols/sec (1080p-shaped) vs plain FP32, at stated bits overhead"
-ROLE_KERNEL = {
-    "persistent_decode": "k_persistent (every phase of every diagonal of the batch, one launch)",
-    "down_gemm": "k_gemm<0, false, 1, 8> (residual epilogue, K=1536)",
-    "gateup_swiglu_gemm": "k_gemm<0, true, 4, 2> (RMSNorm prologue, SwiGLU epilogue)",
-    "qkv_gemm": "k_gemm<0, true, 2, 2> (RMSNorm prologue, QKV epilogue)",
-    "o_gemm": "k_gemm<0, false, 1, 2> (residual epilogue, K=384)",
-    "layer_attention": "k_attn<48>",
-}
 DEFAULT_PATHS = ("plain:fp32,batch32:bf16,batch32:fp8,mixed32:bf16,student4k:bf16,"
+                 "student4k8:bf16,full4k8:bf16,encode:fp32,encode:bf16,bitstream:fp32,"
                  "cyclic32:bf16")
+BITS_BOUND = {"fp32": None, "bf16": 0.005, "fp8": 0.01}
+# The paper's own runtime comparison (Table 2; no GPU or CPU named).
+PAPER_CONTEXT = {
+    "claim": "P-SWA entropy-model decoding 36 % faster than VCT (409 ms vs 301 ms per frame, "
+             "full codec decode, 16 autoregressive steps per frame)",
+    "hardware": "not stated in the paper",
+    "comparable": False,
+    "note": "context only: a different network (channel groups, cyclic 4-step mask) and "
+            "hardware; this benchmark decodes the wavefront form on one MI355X",
+}
 
 
 def parse():
@@ -59,8 +81,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--paths", default=DEFAULT_PATHS,
-                    help="comma list of plain:<prec>, batch<N>:<prec>, mixed<N>:<prec>")
+    ap.add_argument("--paths", default=DEFAULT_PATHS, help="comma list of <kind>:<prec>")
     ap.add_argument("--grid", type=int, default=0,
                     help="one group of this many blocks; 0 lets the autotuner choose")
     ap.add_argument("--rtile", type=int, default=0, help="row tile 16/32; 0: autotuner")
@@ -73,7 +94,61 @@ def parse():
                          "kernel for scaling memory counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-check", action="store_true", help="skip the post-timing bit checks")
     return ap.parse_args()
+
+
+# ------------------------------------------------------- algorithmic work
+
+def macs_per_position(cfg, n_prev=0):
+    """Multiply-adds of one position of the wavefront model (Sec. 3.1
+    network as built here): hyper token (per position), latent embedding,
+    accumulator (q, k/v of the decoded position, o, attention over the
+    causal window and the null slot), L layers (QKV, attention over the
+    causal window and self, O, SwiGLU), head; P-frames add the temporal
+    window's attention and one previous frame's temporal keys/values per
+    layer (the other previous frame's are the earlier frame's own)."""
+    d, C, F, L, r = cfg.d, cfg.C, cfg.F, cfg.L, cfg.r
+    n_acc = 2 * r * (r + 1)
+    k2 = (2 * r + 1) ** 2
+    acc = d * d + 2 * d * d + d * d + (n_acc + 1) * 2 * d
+    layer = 3 * d * d + d * d + 2 * d * F + F * d + (n_acc + 1) * 2 * d
+    m = cfg.Ch * d + C * d + acc + L * layer + d * d + 2 * C * d
+    if n_prev:
+        m += L * (2 * k2 * 2 * d + 2 * d * d) + C * d
+    return m
+
+
+def projection_params(cfg):
+    """Weights the projections read at every step (latent embedding,
+    accumulator q/kv/o, per layer QKV/O/gate/up/down, head W1/W2)."""
+    d, C, F, L = cfg.d, cfg.C, cfg.F, cfg.L
+    return C * d + 4 * d * d + L * (4 * d * d + 3 * d * F) + d * d + 2 * C * d
+
+
+def resident_bytes(cfg, H, W, n_prev=0):
+    """Bytes of one frame's own data at their algorithmic minimum: latents
+    (and previous latents) and hyperprior read once; hyper tokens,
+    accumulator K/V, layer K/V (and temporal K/V) caches (FP32) written and
+    read once; mean, scale, bits, centre, decoded latent (4 B) and table
+    index (2 B) written once."""
+    HW = H * W
+    b = 4 * HW * cfg.C + 4 * (-(-H // 4)) * (-(-W // 4)) * cfg.Ch
+    b += 2 * 4 * HW * cfg.d + 2 * 4 * HW * 2 * cfg.d + 2 * 4 * cfg.L * HW * 2 * cfg.d
+    b += 22 * HW * cfg.C
+    if n_prev:
+        b += 2 * 4 * HW * cfg.C + 2 * 4 * cfg.L * 2 * HW * 2 * cfg.d
+    return b
+
+
+def alg_work(cfg, frames, prec, steps):
+    """(flops, bytes) of one pass over frames [(H, W, n_prev)] taking
+    `steps` global steps, weights read once per step."""
+    wb = {"fp32": 4, "bf16": 2, "fp8": 1}[prec]
+    flops = sum(2.0 * macs_per_position(cfg, npv) * H * W for H, W, npv in frames)
+    byts = steps * wb * projection_params(cfg) + sum(resident_bytes(cfg, H, W, npv)
+                                                     for H, W, npv in frames)
+    return flops, float(byts)
 
 
 def kernel_source_sha():
@@ -98,23 +173,97 @@ def measured_traffic(role, prec, workload):
     return rec["hbm_bytes_per_launch"]
 
 
+def roofline_of(flops, byts, seconds, prec, traffic=None):
+    """Both fractions, and the bound the roofline's own rule picks: the
+    algorithmic intensity against the ridge of the compute peak in use."""
+    peak_tf = MFMA_PEAK_TFLOPS.get(prec, FP32_VECTOR_TFLOPS)
+    tf = flops / seconds / 1e12
+    gbs = byts / seconds / 1e9
+    intensity = flops / byts
+    ridge = peak_tf * 1e12 / (HBM_PEAK_GBS * 1e9)
+    if intensity < ridge:
+        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs / HBM_PEAK_GBS}
+    else:
+        roof = {"bound": "mfma" if prec in MFMA_PEAK_TFLOPS else "alu", "achieved": tf,
+                "peak": peak_tf, "unit": "TFLOP/s", "frac": tf / peak_tf}
+    roof.update({"traffic": traffic,
+                 "traffic_over_alg_bytes": (traffic / byts) if traffic else None,
+                 "compute_achieved_tflops": tf, "compute_peak_tflops": peak_tf,
+                 "compute_frac": tf / peak_tf, "hbm_achieved_GBps": gbs,
+                 "hbm_frac": gbs / HBM_PEAK_GBS, "intensity_flop_per_byte": intensity,
+                 "ridge_flop_per_byte": ridge, "alg_flops_per_launch": flops,
+                 "alg_bytes_per_launch": byts})
+    return roof
+
+
+# ------------------------------------------------------------ CPU baseline
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(cfg, Wt, y, z, budget_s=12.0):
     """The FP64 oracle (parallel definition form) on whole 1080p I-frames of
-    the workload, repeated until about budget_s seconds have passed."""
+    the workload (the first is frame 0 of the headline batch) until about
+    budget_s seconds have passed; then the oracle on the tiny configuration
+    at one BLAS thread in its parallel and sequential (wavefront) forms.
+    Returns the record and the oracle's prediction of the first frame."""
+    import synth
     from oracle import model as om
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
     n = 0
+    first = None
     while True:
-        om.forward(cfg, Wt, y, z)
+        o = om.forward(cfg, Wt, y, z)
+        first = first or o
         n += 1
         dt = time.perf_counter() - t0
         if dt >= budget_s:
             break
-    return {"value": n * y.size / dt, "unit": "symbols/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} whole {y.shape[0]}x{y.shape[1]}x{y.shape[2]} I-frame(s) of the "
-                      f"workload, float64 parallel form, {dt:.1f} s, BLAS threads {threads}"}
+    rec = {"value": n * y.size / dt, "unit": "symbols/s", "cores": threads, "kind": "oracle",
+           "sample": f"{n} whole {y.shape[0]}x{y.shape[1]}x{y.shape[2]} I-frame(s) of the "
+                     f"workload, float64 parallel form, {dt:.1f} s, BLAS threads {threads}",
+           "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:
+        threadpool_limits = None
+    tc = synth.TINY
+    tw = synth.model_weights(tc, synth.CONFIG_SEEDS["tiny"][1])
+    ty, tz, _ = synth.frame_inputs(tc, synth.FrameCfg(16, 16), synth.CONFIG_SEEDS["tiny"][0])
+    one = {}
+    ctx = threadpool_limits(limits=1) if threadpool_limits else None
+    if ctx:
+        ctx.__enter__()
+    try:
+        for form in ("parallel", "sequential"):
+            t1 = time.perf_counter()
+            k = 0
+            while time.perf_counter() - t1 < 2.0:
+                if form == "parallel":
+                    om.forward(tc, tw, ty, tz)
+                else:
+                    om.forward_sequential(tc, tw, ty, tz, om.schedule_groups(tc, 16, 16))
+                k += 1
+            d1 = time.perf_counter() - t1
+            one[form] = {"value": k * ty.size / d1, "unit": "symbols/s", "cores": 1,
+                         "sample": f"{k} tiny 16x16x32 frame(s), {d1:.1f} s"}
+    finally:
+        if ctx:
+            ctx.__exit__(None, None, None)
+    rec["tiny_one_thread"] = one
+    return rec, first
 
+
+# ---------------------------------------------------------------- timing
 
 def timed(fn, steps, warmup):
     import torch
@@ -128,7 +277,9 @@ def timed(fn, steps, warmup):
     return time.perf_counter() - t0
 
 
-def roofline(pswa, fn, steps, prec, workload):
+def live_kernel_times(pswa, fn, steps):
+    """Per-role launch counts and event-timed milliseconds of an
+    instrumented repeat of `steps` runs."""
     import torch
     pswa.pswa_profile_enable(True)
     for _ in range(steps):
@@ -136,55 +287,20 @@ def roofline(pswa, fn, steps, prec, workload):
     torch.cuda.synchronize()
     prof = pswa.pswa_profile_read()
     pswa.pswa_profile_enable(False)
-    dom = max(prof, key=lambda k: prof[k]["ms"])
-    p = prof[dom]
-    avg_s = p["ms"] / 1e3 / p["launches"]
-    bytes_l = p["bytes"] / p["launches"]
-    flops_l = p["flops"] / p["launches"]
-    # the roofline's own rule: arithmetic intensity (algorithmic flops per
-    # algorithmic byte) against the ridge of the compute peak in use
-    peak_tf = MFMA_PEAK_TFLOPS.get(prec, FP32_VECTOR_TFLOPS) if dom == "persistent_decode" \
-        else FP32_VECTOR_TFLOPS
-    intensity = flops_l / bytes_l if bytes_l else float("inf")
-    ridge = peak_tf * 1e12 / (HBM_PEAK_GBS * 1e9)
-    tf = flops_l / avg_s / 1e12
-    gbs = bytes_l / avg_s / 1e9
-    if intensity < ridge:
-        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": gbs / HBM_PEAK_GBS}
-    else:
-        roof = {"bound": "mfma" if prec in MFMA_PEAK_TFLOPS else "alu", "achieved": tf,
-                "peak": peak_tf, "unit": "TFLOP/s", "frac": tf / peak_tf}
-    roof.update({"intensity_flop_per_byte": intensity, "ridge_flop_per_byte": ridge,
-                 "compute_frac": tf / peak_tf, "compute_peak_tflops": peak_tf})
-    roof.update({"traffic": measured_traffic(dom, prec, workload),
-                 "kernel": ROLE_KERNEL.get(dom, dom), "role": dom,
-                 "avg_launch_us": avg_s * 1e6, "alg_bytes_per_launch": bytes_l,
-                 "alg_flops_per_launch": flops_l, "launches_per_step": p["launches"] / steps,
-                 "hbm_GBps_alg": bytes_l / avg_s / 1e9})
-    tot = sum(v["ms"] for v in prof.values())
-    kernels = {k: {"share": round(v["ms"] / tot, 4),
-                   "avg_us": round(1e3 * v["ms"] / v["launches"], 3),
-                   "GBps": round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1),
-                   "TFLOPs": round(v["flops"] / (v["ms"] / 1e3) / 1e12, 3)}
-               for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
-    return roof, kernels
+    return prof
 
 
 def batch_frames(synth, cfg, kind, n, dseed):
     """Inputs of a batch path: n 1080p I-frames, n frames of the mixed batch
-    (sizes in equal numbers, I- and P-frames alternating per size), or the
-    4K-shaped I- and P-frame of the student workload."""
+    (sizes in equal numbers, I- and P-frames alternating per size), or n
+    4K-shaped frames (I and P alternating)."""
     frames = []
-    if kind == "student4k":
-        s0 = synth.CONFIG_SEEDS["4k_student"][0]
-        for k, n_prev in enumerate((0, 2)):
-            y, z, pv = synth.frame_inputs(synth.STUDENT, synth.FrameCfg(135, 240, n_prev), s0 + k)
-            frames.append({"latents": y, "hyper": z, "prev": pv})
-        return frames
     for k in range(n):
         if kind in ("batch", "cyclic"):
             fc, seed = synth.FrameCfg(68, 120), dseed + 1000 * k
+        elif kind in ("student4k", "full4k"):
+            fc, seed = synth.FrameCfg(135, 240, 2 if k % 2 else 0), \
+                synth.CONFIG_SEEDS["4k_student"][0] + k
         else:
             H, W = synth.BATCH_MIX[(k * len(synth.BATCH_MIX)) // n]
             fc, seed = synth.FrameCfg(H, W, 2 if k % 2 else 0), synth.CONFIG_SEEDS["batch"][0] + k
@@ -193,12 +309,18 @@ def batch_frames(synth, cfg, kind, n, dseed):
     return frames
 
 
+def frame_shapes(frames):
+    return [(f["latents"].shape[0], f["latents"].shape[1], 0 if f["prev"] is None else 2)
+            for f in frames]
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): every path here is "
               "measured on a single device", file=sys.stderr)
         sys.exit(2)
+    import numpy as np
     import torch
     import synth
     from paper_2605_20977_amd import pswa
@@ -225,21 +347,22 @@ def main():
         key = (prec, kind)
         if key not in models:
             if kind == "student":
-                models[key] = pswa.Model(synth.STUDENT, synth.model_weights(synth.STUDENT, 51),
-                                         prec)
+                mc, mw = synth.STUDENT, synth.model_weights(synth.STUDENT, 51)
             elif kind == "cyclic":
-                models[key] = pswa.Model(
-                    synth.CYCLIC,
-                    synth.model_weights(synth.CYCLIC, synth.CONFIG_SEEDS["1080p_cyclic"][1]), prec)
+                mc, mw = synth.CYCLIC, synth.model_weights(
+                    synth.CYCLIC, synth.CONFIG_SEEDS["1080p_cyclic"][1])
             else:
-                models[key] = pswa.Model(cfg, Wt, prec)
+                mc, mw = cfg, Wt
+            calib = synth.calibration_frames(mc) if prec == "fp8" else None
+            models[key] = (pswa.make_model(mc, mw, prec, calib), mc)
         return models[key]
 
-    paths, runners, keep = {}, {}, []
+    paths, runners, batches, keep = {}, {}, {}, []
     for spec in args.paths.split(","):
         kind, prec = spec.split(":")
-        model = model_for(prec, "student" if kind == "student4k"
-                          else "cyclic" if kind.startswith("cyclic") else "full")
+        mkind = ("student" if kind.startswith("student") else
+                 "cyclic" if kind.startswith("cyclic") else "full")
+        model, mc = model_for(prec, mkind)
         if kind == "plain":
             mem = torch.empty(pswa.pswa_state_bytes(model, H, W), dtype=torch.uint8,
                               device="cuda")
@@ -255,13 +378,48 @@ def main():
                            "ms_per_step": 1e3 * dt / args.steps,
                            "value": sym_frame * args.steps / dt}
             runners[spec] = plain
+        elif kind == "encode":
+            ws = torch.empty(pswa.lib().pswa_encode_workspace_bytes(
+                model.handle, pswa.C.byref(pswa.frame_desc(H, W))), dtype=torch.uint8,
+                device="cuda")
+
+            def enc(model=model, ws=ws):
+                pswa.pswa_encode_params(model, yd, zd, total_bits=False, ws=ws)
+            dt = timed(enc, 3 * args.steps, args.warmup)
+            sec = dt / (3 * args.steps)
+            fl, by = alg_work(cfg, [(H, W, 0)], prec, 1)
+            paths[spec] = {"frames": 1, "symbols_per_step": sym_frame, "ms_per_step": 1e3 * sec,
+                           "value": sym_frame / sec,
+                           "roofline": roofline_of(fl, by, sec, prec)}
+            runners[spec] = enc
+        elif kind == "bitstream":
+            o = pswa.pswa_encode_params(model, yd, zd)
+            stream = pswa.pswa_range_encode(H, W, cfg.C, cfg.window, y,
+                                            o["center"].cpu().numpy(),
+                                            pswa.index_u16(o["index"]))
+            mem = torch.empty(pswa.pswa_state_bytes(model, H, W), dtype=torch.uint8,
+                              device="cuda")
+            out = {}
+
+            def bits_dec(model=model, mem=mem, stream=stream, out=out):
+                st = pswa.pswa_decode_begin(model, H, W, zd, source="bitstream", src=stream,
+                                            mem=mem)
+                for t in range(st.T):
+                    pswa.pswa_decode_step(st, t)
+                out["y"] = pswa.pswa_decode_end(st, H, W, cfg.C, total_bits=False)["latents"]
+                st.close()
+            steps = max(1, args.steps // 2)
+            dt = timed(bits_dec, steps, 1)
+            paths[spec] = {"frames": 1, "symbols_per_step": sym_frame,
+                           "ms_per_step": 1e3 * dt / steps, "value": sym_frame * steps / dt,
+                           "stream_bytes": len(stream), "coder_threads": 1,
+                           "round_trip_exact": bool(torch.equal(out["y"], yd))}
+            runners[spec] = bits_dec
         else:
-            if kind == "student4k":
-                base, n = "student4k", 2
-            else:
-                base = next(b_ for b_ in ("batch", "mixed", "cyclic") if kind.startswith(b_))
-                n = int(kind[len(base):])
-            frames = batch_frames(synth, cfg, base, n, dseed)
+            base = next(b_ for b_ in ("batch", "mixed", "cyclic", "student4k", "full4k")
+                        if kind.startswith(b_))
+            n = int(kind[len(base):] or 2)
+            frames = batch_frames(synth, mc, base, n, dseed)
             nsym = sum(f["latents"].size for f in frames)
             b = pswa.Batch(model, frames)
             keep.append(b)
@@ -292,6 +450,7 @@ def main():
                            "ms_per_step": 1e3 * dt / args.steps,
                            "value": nsym * args.steps / dt}
             runners[spec] = run
+            batches[spec] = (b, frames, model, mc)
         print(f"{spec}: {paths[spec]['ms_per_step']:.2f} ms per step "
               f"({paths[spec]['frames']} frame(s)) -> "
               f"{paths[spec]['value'] / 1e6:.2f} M symbols/s", file=sys.stderr, flush=True)
@@ -299,10 +458,14 @@ def main():
     base = paths.get("plain:fp32", {}).get("value")
     for p in paths.values():
         p["vs_plain_fp32"] = (p["value"] / base) if base else None
-    # the headline is a 1080p-shaped path (the mixed batch and the student's
-    # 4K frames are reported beside it)
-    # (BF16 when it ran: the tighter bits-overhead bound; FP8 is reported
-    # beside it in "paths")
+    s4, f4 = [k for k in paths if k.startswith("student4k") and k[9:10].isdigit()], \
+        [k for k in paths if k.startswith("full4k")]
+    student_gain = None
+    if s4 and f4:
+        student_gain = {"student": s4[0], "full": f4[0],
+                        "speedup": paths[s4[0]]["value"] / paths[f4[0]]["value"]}
+
+    # the headline: the BF16 1080p batch (FP8 and the other paths beside it)
     cand = ([k for k in paths if k.startswith("batch") and k.endswith(":bf16")]
             or [k for k in paths if k.split(":")[0].startswith(("plain", "batch"))]
             or list(paths))
@@ -319,15 +482,69 @@ def main():
                       f"{hp['frames']} frames, {hp['groups']} groups with their own barriers, "
                       f"row tile {hp['rtile']}"
                       + (", HIP graph replay" if hp["graph"] else ""))
+
     roof = kernels = None
     if not args.no_roofline:
-        roof, kernels = roofline(pswa, runners[best], args.steps, prec, workload)
-    overhead = {"fp32": "FP32: max relative error <= 1e-4 on mean/scale against the FP64 "
-                        "oracle (parity tests)",
-                "bf16": "BF16 projections: bits overhead vs FP64 oracle <= 0.5 % (measured "
-                        "-0.0001 % on the 1080p-shaped P-frame)",
-                "fp8": "FP8 e4m3 projections: bits overhead vs FP64 oracle <= 1 % (measured "
-                       "-0.0071 % on the 1080p-shaped P-frame)"}[prec]
+        prof = live_kernel_times(pswa, runners[best], args.steps)
+        dom = max(prof, key=lambda k: prof[k]["ms"])
+        p = prof[dom]
+        avg_s = p["ms"] / 1e3 / p["launches"]
+        if best in batches:
+            b, frames, _, mc = batches[best]
+            fl, by = alg_work(mc, frame_shapes(frames), prec, b.T)
+        else:
+            fl, by = alg_work(cfg, [(H, W, 0)], prec, 455)
+        fl /= p["launches"] / args.steps
+        by /= p["launches"] / args.steps
+        roof = roofline_of(fl, by, avg_s, prec, measured_traffic(dom, prec, workload))
+        roof.update({"kernel": dom, "avg_launch_us": avg_s * 1e6,
+                     "launches_per_step": p["launches"] / args.steps,
+                     "library_count_bytes_per_launch": p["bytes"] / p["launches"]})
+        tot = sum(v["ms"] for v in prof.values())
+        kernels = {k: {"share": round(v["ms"] / tot, 4),
+                       "avg_us": round(1e3 * v["ms"] / v["launches"], 3)}
+                   for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
+
+    # checks of the timed batch after timing: frame 0 bit for bit against the
+    # encode form of the same model, and its bits against the FP32 path
+    bits = {"bound_pct": None if BITS_BOUND[prec] is None else 100 * BITS_BOUND[prec]}
+    if not args.no_check and best in batches:
+        b, frames, model, mc = batches[best]
+        o = b.outputs(0)
+        e = pswa.pswa_encode_params(model, frames[0]["latents"], frames[0]["hyper"])
+        same = all(torch.equal(o[k], e[k]) for k in ("mean", "scale", "bits", "center", "index"))
+        b32 = None
+        if mc is cfg:
+            m32 = model_for("fp32")[0]
+            b32 = pswa.pswa_encode_params(m32, frames[0]["latents"],
+                                          frames[0]["hyper"])["total_bits"]
+        bits.update({"frame": "frame 0 of the timed batch (68x120 I)",
+                     "batch_equals_encode_bitwise": bool(same),
+                     "total_bits": o["total_bits"], "fp32_total_bits": b32,
+                     "vs_fp32_path_pct": None if b32 is None else
+                     100 * (o["total_bits"] - b32) / b32,
+                     "mean": o["mean"], "scale": o["scale"]})
+        if not same:
+            print("timed batch differs from the encode form", file=sys.stderr)
+            sys.exit(1)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu, ref0 = cpu_baseline(cfg, Wt, y, z)
+        if "mean" in bits:
+            from oracle import entropy as oe
+            b64 = float(oe.bits(y, ref0["mu"], ref0["sigma"]).sum())
+            mu = bits["mean"].cpu().numpy().astype(np.float64)
+            sg = bits["scale"].cpu().numpy().astype(np.float64)
+            bits.update({"fp64_total_bits": b64,
+                         "vs_fp64_oracle_pct": 100 * (bits["total_bits"] - b64) / b64,
+                         "mean_err_max": float(np.max(np.abs(mu - ref0["mu"]) /
+                                                      np.maximum(np.abs(ref0["mu"]), 1))),
+                         "scale_err_max": float(np.max(np.abs(sg - ref0["sigma"]) /
+                                                       ref0["sigma"]))})
+    bits.pop("mean", None)
+    bits.pop("scale", None)
+
     rec = {
         "metric": METRIC, "value": hp["value"], "unit": "symbols/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": hp["ms_per_step"],
@@ -338,13 +555,15 @@ def main():
                                "6 layers d=384, 8 heads of 48, causal 9x9 window (slope 5, "
                                "455 diagonals per frame), symbols read from device memory",
                    "path": path_descr, "frames_per_step": hp["frames"],
-                   "bits_overhead": overhead},
+                   "bits_overhead": bits},
         "vs_plain_fp32": hp["vs_plain_fp32"],
         "paths": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
                       for kk, vv in v.items()} for k, v in paths.items()},
+        "student_speedup_4k": student_gain,
         "roofline": roof,
         "kernels": kernels,
-        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(cfg, Wt, y, z),
+        "cpu_baseline": cpu,
+        "paper_context": PAPER_CONTEXT,
     }
     print(json.dumps(rec), flush=True)
 

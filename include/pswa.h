@@ -75,7 +75,22 @@ typedef struct {
                     step = (i + j) mod c over the full window, the accumulator
                     seeing strictly earlier steps and the layers steps up to
                     the query's own (Sec. 3.2, Fig. 2) */
+  int32_t act_scaling; /* FP8 activation scaling (pswa_act_scaling); must be
+                          PSWA_ACT_TENSOR for FP32 and BF16 models */
 } pswa_model_desc;
+
+/* How a PSWA_FP8_E4M3 model scales each projection input before rounding it
+ * to FP8 (Sec. 4.2.2 runs the network in reduced precision; the per-tensor
+ * form is the configured one):
+ *   PSWA_ACT_TENSOR: one static scale per projection input, 448 / amax, from
+ *     maxima calibrated offline (pswa_calibrate) and passed after the weight
+ *     blob; values beyond amax saturate at +-448. For RMSNorm inputs the
+ *     scaled value is the normalized row (times its gain).
+ *   PSWA_ACT_ROW: each row scaled by 448 / its own maximum, computed in the
+ *     tile (no calibration).
+ * Either way every row's arithmetic depends on that row only, so encode,
+ * decode and batch decode stay bit-identical. */
+typedef enum { PSWA_ACT_TENSOR = 0, PSWA_ACT_ROW = 1 } pswa_act_scaling;
 
 /* Frame shape. Hh = ceil(H/4), Wh = ceil(W/4) (the hyperprior is at a
  * quarter of the latent resolution, Fig. 1); n_prev = 0 (I-frame) or 2
@@ -101,8 +116,18 @@ typedef struct pswa_state pswa_state;
  * with r = (window-1)/2, F = mlp_ratio*d, nS = 2r(r+1)+1 spatial bias slots
  * (the causal window in row-major order, then the query itself) and
  * nT = 2(2r+1)^2 temporal slots (previous frame 1 then 2, each its full
- * window in row-major order). Returns 0 for an invalid desc. */
+ * window in row-major order). For a PSWA_FP8_E4M3 model with
+ * act_scaling = PSWA_ACT_TENSOR the weights are followed by
+ * pswa_act_points(desc) floats: the calibrated absolute maximum of every
+ * projection input (finite, >= 0; 0 gives the scale 1). Returns 0 for an
+ * invalid desc. */
 size_t pswa_model_blob_floats(const pswa_model_desc* desc);
+
+/* Number of projection inputs, in this order: the latent embedding (in.W),
+ * the accumulator's q, k/v and o projections, per layer the QKV, O, gate/up
+ * (one input for both) and down projections, then head.W1 and head.W2:
+ * 6 + 4 L. Returns 0 for an invalid desc. */
+int pswa_act_points(const pswa_model_desc* desc);
 
 /* Device bytes the model needs (weights plus their low-precision copies). */
 size_t pswa_model_device_bytes(const pswa_model_desc* desc);
@@ -138,6 +163,21 @@ pswa_status pswa_encode_params(const pswa_model* model, const pswa_frame_desc* f
                                float* d_bits, int32_t* d_cdf_center,
                                uint16_t* d_cdf_index, double* h_total_bits,
                                void* d_ws, size_t ws_bytes, void* stream);
+
+/* Calibration of FP8 per-tensor activation scales: runs the encode form of
+ * an FP32 model on one frame (arguments as in pswa_encode_params) and
+ * max-combines into d_amax [pswa_act_points] (device float, zeroed by the
+ * caller before the first frame) the largest |value| each projection
+ * multiplies: the RMSNorm output (gain included) for normed inputs, the
+ * latent times its input scale for the embedding, the raw input otherwise;
+ * the temporal keys/values of P-frames count toward their layer's QKV input.
+ * d_ws: pswa_calibrate_workspace_bytes, 256-byte aligned. Returns
+ * PSWA_E_UNSUPPORTED for a model that is not FP32. Does not wait. */
+size_t pswa_calibrate_workspace_bytes(const pswa_model* model, const pswa_frame_desc* frame);
+pswa_status pswa_calibrate(const pswa_model* model, const pswa_frame_desc* frame,
+                           const int32_t* d_latents, const int32_t* d_hyper,
+                           const int32_t* d_prev, float* d_amax, void* d_ws, size_t ws_bytes,
+                           void* stream);
 
 /* ---------------------------------------------------------------- decode */
 

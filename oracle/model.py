@@ -330,7 +330,7 @@ def head(cfg, Wt, x):
 # Sequential form: positions decoded group by group from caches
 # --------------------------------------------------------------------------
 
-def forward_sequential(cfg, Wt, y, z, groups, prev=None):
+def forward_sequential(cfg, Wt, y, z, groups, prev=None, on_group=None):
     """Decode in the given order and return dict(mu, sigma, lsig).
 
     groups: list of int arrays [n, 2] of (i, j). Each group is predicted at
@@ -338,7 +338,10 @@ def forward_sequential(cfg, Wt, y, z, groups, prev=None):
     accumulator may see must have been decoded in an earlier group, and
     every cell a layer may see must be decoded or in the same group
     (checked); each group's own latents are read only after its prediction.
-    This is the decoder's view: it never touches y of undecoded positions."""
+    This is the decoder's view: it never touches y of undecoded positions.
+    on_group(grp, prediction), if given, runs after a group is predicted and
+    before its latents are read (prediction: dict(mu, sigma, lsig) of the
+    group's rows); it may write y at the group's positions."""
     H, W, C = y.shape
     d, heads, r, L = cfg.d, cfg.heads, cfg.r, cfg.L
     dh = d // heads
@@ -435,12 +438,31 @@ def forward_sequential(cfg, Wt, y, z, groups, prev=None):
         hd = head(cfg, Wt, x)
         for k in res:
             res[k][gi, gj] = hd[k]
+        if on_group is not None:
+            on_group(grp, hd)
         # The group's symbols are now decoded: fill the accumulator cache.
         e = latent_embed(Wt, y[gi, gj])
         acc_cache[gi, gj] = acc_keys_values(Wt, e)
         decoded[gi, gj] = True
     assert decoded.all()
     return res
+
+
+def sample_latents(cfg, Wt, z, noise, prev=None):
+    """Latents drawn from the model itself, in decode order: at each
+    diagonal the model predicts mu and sigma from the symbols drawn so far,
+    and y = rint(mu + sigma * noise) there (noise [H, W, C], given). On such
+    data the model is the true source, so its ideal bits approach the
+    entropy and errors in mu or sigma show up as rate (test data for the
+    precision forms; the method itself never samples)."""
+    H, W, C = noise.shape
+    y = np.zeros((H, W, C), dtype=np.int32)
+
+    def draw(grp, pred):
+        y[grp[:, 0], grp[:, 1]] = np.rint(pred["mu"] + pred["sigma"] * noise[grp[:, 0], grp[:, 1]])
+
+    forward_sequential(cfg, Wt, y, z, schedule_groups(cfg, H, W), prev, on_group=draw)
+    return y
 
 
 def raster_order(H, W):

@@ -312,6 +312,29 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& a, int bx, int by, flo
       if (lane == 0) rstd[m] = 1.0f / sqrtf(ss / float(K) + kEps);
     }
   }
+  if (a.amax) {
+    // calibration: the largest |value| this projection multiplies (the
+    // RMSNorm output, or the input times its scale), over the tile's rows
+    float mx = 0.f;
+    for (int m = wave; m < rows; m += kWaves) {
+      float rm = 0.f, ss = 0.f;
+#pragma unroll
+      for (int it = 0; it < KC; ++it) {
+        const int c = lane + 64 * it;
+        if (c < K4) {
+          const float4 x = smem4[m * K4 + c];
+          if (RMS) ss = dot4(x, x, ss);
+          rm = fmaxf(rm, fmaxf(fmaxf(fabsf(x.x * g[it].x), fabsf(x.y * g[it].y)),
+                               fmaxf(fabsf(x.z * g[it].z), fabsf(x.w * g[it].w))));
+        }
+      }
+      rm = wave_max(rm);
+      if (RMS) rm *= 1.0f / sqrtf(wave_sum(ss) / float(K) + kEps);
+      mx = fmaxf(mx, rm);
+    }
+    // non-negative floats order as their bit patterns
+    if (lane == 0 && mx > 0.f) atomicMax(reinterpret_cast<unsigned*>(a.amax), __float_as_uint(mx));
+  }
 
   float acc[kMB][kRowsW];
 #pragma unroll

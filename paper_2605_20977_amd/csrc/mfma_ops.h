@@ -11,15 +11,17 @@
 //      tree, and the row's absolute maximum after the gain (FP8 scale);
 //   2. from the same registers the wave stages the row, times the gain
 //      (RMSNorm input) or the input scale (integer latents), as BF16 (round
-//      to nearest even) or as FP8 of (value * 448 / row max) (round to
-//      nearest even), in LDS with a 16-byte skew per row;
+//      to nearest even) or as FP8 (round to nearest even, saturating) of
+//      either value * 448 / row max (per-row scale) or value * 1/rms *
+//      ascale (static per-tensor scale of the projection input, calibrated
+//      offline), in LDS with a 16-byte skew per row;
 //   3. each wave runs v_mfma_f32_16x16x32_{bf16,fp8_fp8} over k = 0, 32, ...
 //      in order for its 16 weight rows (16 k-steps of weight loads in flight
 //      at a time; the first of them issued right after the first row loads,
 //      so the weight fetch overlaps steps 1 and 2) against both row blocks:
 //      an output is one MFMA chain over K, whatever the tiling;
-//   4. the epilogue rescales (1/rms, row max / 448, 1 / weight scale) and
-//      applies the same epilogues as the FP32 tile.
+//   4. the epilogue rescales (1/rms and row max / 448, or 1 / ascale; and
+//      1 / weight scale) and applies the same epilogues as the FP32 tile.
 // A row's result depends only on that row, K and the weights: the same in
 // every launch shape, so encode and decode stay bit-identical.
 // Paired epilogues: columns 0-7 of a wave are W rows n..n+7 and columns 8-15
@@ -109,11 +111,12 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
 // chunks l, l+64, ... (CPR of them; RPB = 16 / CPR rows per wave in flight
 // at once, indices clamped into the row so every load is unconditional),
 //   * row statistics: the sum of squares (RMS) over the lane's chunks in
-//     order, then a fixed xor tree, gives 1/rms; the absolute maximum of
-//     x * g (FP8) through a max tree gives the input scale 448 / max;
+//     order, then a fixed xor tree, gives 1/rms; for per-row FP8 the absolute
+//     maximum of x * g through a max tree gives the input scale 448 / max;
 //   * the same registers, times the gain (RMSNorm input) or the input scale
 //     (integer latents), are written to LDS as BF16 (round to nearest even)
-//     or as FP8 of (value * 448 / row max) (round to nearest even), rows
+//     or as FP8 (round to nearest even, saturating) of value * 448 / row max
+//     (per row) or value * 1/rms * ascale (static per tensor), rows
 //     [R][pitch] with a 16-byte skew per row.
 // issue_w() runs once, right after the first batch of row loads is issued,
 // so loads the caller issues there complete after (and are not waited for
@@ -126,6 +129,7 @@ __device__ __forceinline__ void stage_rows(const GemmArgs& a, int m0, int rows, 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int K = a.K, K4 = a.K / 4;
   const int pitch = qgemm_pitch(K, PREC);
+  const bool stat = PREC == PSWA_PREC_FP8 && a.ascale > 0.f;  // static per-tensor FP8 scale
   // per-column factor (gain or input scale) of the lane's chunks
   float4 gg[CPR];
 #pragma unroll
@@ -167,20 +171,32 @@ __device__ __forceinline__ void stage_rows(const GemmArgs& a, int m0, int rows, 
         const bool in = lane + 64 * it < K4;
         const float4 x = in ? xs[j][it] : make_float4(0.f, 0.f, 0.f, 0.f);
         if (RMS) ss = dot4(x, x, ss);
-        if (PREC == PSWA_PREC_FP8) {
+        if (PREC == PSWA_PREC_FP8 && !stat) {
           const float4 g = gg[it];
           mx = fmaxf(mx, fmaxf(fmaxf(fabsf(x.x * g.x), fabsf(x.y * g.y)),
                                fmaxf(fabsf(x.z * g.z), fabsf(x.w * g.w))));
         }
       }
       if (RMS) ss = wave_sum(ss);
-      if (PREC == PSWA_PREC_FP8) mx = wave_max(mx);
-      // FP8 rows are stored as value * (448 / max); a zero row stays zero
-      const float sc = PREC == PSWA_PREC_FP8 ? (mx > 0.f ? kFp8Max / mx : 1.0f) : 1.0f;
+      const float rs = RMS ? 1.0f / sqrtf(ss / float(K) + kEps) : 1.0f;
+      // FP8 rows are stored as value * sc. Per row: sc = 448 / the row's
+      // maximum (a zero row stays zero); the product is divided by sc and,
+      // for RMSNorm inputs, multiplied by 1/rms. Static per tensor: sc =
+      // ascale * 1/rms, so the stored values are the RMSNorm output times the
+      // tensor's scale, and the product is divided by ascale alone.
+      float sc = 1.0f;
+      if (PREC == PSWA_PREC_FP8) {
+        if (stat) {
+          sc = RMS ? a.ascale * rs : a.ascale;
+        } else {
+          mx = wave_max(mx);
+          sc = mx > 0.f ? kFp8Max / mx : 1.0f;
+        }
+      }
       if (mm >= rows) continue;  // the same for the whole wave
       if (lane == 0) {
-        rstd[mm] = RMS ? 1.0f / sqrtf(ss / float(K) + kEps) : 1.0f;
-        rmul[mm] = sc;
+        rstd[mm] = stat ? 1.0f : rs;
+        rmul[mm] = stat ? a.ascale : sc;
       }
 #pragma unroll
       for (int it = 0; it < CPR; ++it) {

@@ -19,9 +19,14 @@ constexpr int kMaxLayers = 16;
 
 // A projection weight in the model's GEMM precision: the BF16 / FP8 copy and
 // 1 / its quantization scale (FP8; 1 for BF16). q is null for FP32 models.
+// ascale: the FP8 static activation scale of the projection's input (0: per
+// row); slot: the input's index among the model's projection inputs (its
+// calibration record).
 struct QW {
-  const void* q;
-  float inv_scale;
+  const void* q = nullptr;
+  float inv_scale = 1.f;
+  float ascale = 0.f;
+  int slot = -1;
 };
 
 struct LayerWeights {
@@ -36,7 +41,13 @@ struct DevWeights {
   const float *head_g, *W1, *W2, *gmu, *bmu, *gsig, *bsig;
   int prec;  // PSWA_PREC_*: arithmetic of every projection below
   QW in, acc_q, acc_kv, acc_o, head1, head2;
+  float* calib = nullptr;  // calibration: per-input maxima (FP32 models only)
 };
+
+// Projection inputs, in calibration-slot order: latent embedding,
+// accumulator q / kv / o, per layer QKV, O, gate/up (one input), down, then
+// head W1 and W2.
+__host__ __device__ inline int act_points(int L) { return 6 + 4 * L; }
 
 struct NetDims {
   int L, d, heads, dh, r, s, F, C, Ch, n_acc, n_sp, n_tm;
@@ -84,13 +95,16 @@ __host__ __device__ inline GemmArgs gemm_base(int M, int N, int K, int role) {
   return g;
 }
 
-__host__ __device__ inline void use_q(GemmArgs& g, int prec, QW w, QW w2 = QW{nullptr, 1.f},
+__host__ __device__ inline void use_q(GemmArgs& g, const DevWeights& dw, QW w, QW w2 = QW{},
                                      size_t off = 0, size_t off2 = 0) {
+  if (dw.calib && w.slot >= 0) g.amax = dw.calib + w.slot;
+  const int prec = dw.prec;
   if (prec == 0 || !w.q) return;
   const int eb = prec == 1 ? 2 : 1;
   g.prec = prec;
   g.Wq = static_cast<const char*>(w.q) + off * eb;
   g.wscale = w.inv_scale;
+  g.ascale = w.ascale;
   if (w2.q) {
     g.W2q = static_cast<const char*>(w2.q) + off2 * eb;
     g.w2scale = w2.inv_scale;
@@ -124,7 +138,7 @@ __host__ __device__ inline GemmArgs args_acc_q(const NetDims& x, const DevWeight
   GemmArgs g = gemm_base(c.M, x.d, x.d, R_ACC_Q);
   g.X = c.h; g.ldx = x.d; g.xrow = c.gpos; g.gain = w.acc_gq; g.W = w.acc_Wq;
   g.Y = c.q; g.ldy = x.d;
-  use_q(g, w.prec, w.acc_q);
+  use_q(g, w, w.acc_q);
   return g;
 }
 __host__ __device__ inline AttnArgs args_acc_attn(const NetDims& x, const DevWeights& w,
@@ -139,7 +153,7 @@ __host__ __device__ inline GemmArgs args_acc_o(const NetDims& x, const DevWeight
   GemmArgs g = gemm_base(c.M, x.d, x.d, R_ACC_O);
   g.X = c.att; g.ldx = x.d; g.W = w.acc_Wo;
   g.R = c.h; g.ldr = x.d; g.rrow = c.gpos; g.Y = c.x; g.ldy = x.d;
-  use_q(g, w.prec, w.acc_o);
+  use_q(g, w, w.acc_o);
   return g;
 }
 
@@ -151,7 +165,7 @@ __host__ __device__ inline GemmArgs args_qkv(const NetDims& x, const DevWeights&
   g.X = c.x; g.ldx = x.d; g.gain = L.g1; g.W = L.Wqkv;
   g.Y = c.q; g.ldy = x.d; g.Y2 = c.kv + l * c.kv_stride; g.ldy2 = 2 * x.d; g.y2row = c.gpos;
   g.nsplit = x.d;
-  use_q(g, w.prec, L.qkv);
+  use_q(g, w, L.qkv);
   return g;
 }
 __host__ __device__ inline AttnArgs args_attn(const NetDims& x, const DevWeights& w,
@@ -168,7 +182,7 @@ __host__ __device__ inline GemmArgs args_o(const NetDims& x, const DevWeights& w
   GemmArgs g = gemm_base(c.M, x.d, x.d, R_O);
   g.X = c.att; g.ldx = x.d; g.W = w.layers[l].Wo;
   g.R = c.x; g.ldr = x.d; g.Y = c.x; g.ldy = x.d;
-  use_q(g, w.prec, w.layers[l].o);
+  use_q(g, w, w.layers[l].o);
   return g;
 }
 __host__ __device__ inline GemmArgs args_gateup(const NetDims& x, const DevWeights& w,
@@ -176,7 +190,7 @@ __host__ __device__ inline GemmArgs args_gateup(const NetDims& x, const DevWeigh
   GemmArgs g = gemm_base(c.M, x.F, x.d, R_GATEUP);
   g.X = c.x; g.ldx = x.d; g.gain = w.layers[l].g2; g.W = w.layers[l].Wgate;
   g.W2 = w.layers[l].Wup; g.Y = c.hmid; g.ldy = x.F;
-  use_q(g, w.prec, w.layers[l].gate, w.layers[l].up);
+  use_q(g, w, w.layers[l].gate, w.layers[l].up);
   return g;
 }
 __host__ __device__ inline GemmArgs args_down(const NetDims& x, const DevWeights& w,
@@ -184,7 +198,7 @@ __host__ __device__ inline GemmArgs args_down(const NetDims& x, const DevWeights
   GemmArgs g = gemm_base(c.M, x.d, x.F, R_DOWN);
   g.X = c.hmid; g.ldx = x.F; g.W = w.layers[l].Wdown;
   g.R = c.x; g.ldr = x.d; g.Y = c.x; g.ldy = x.d;
-  use_q(g, w.prec, w.layers[l].down);
+  use_q(g, w, w.layers[l].down);
   return g;
 }
 
@@ -193,7 +207,7 @@ __host__ __device__ inline GemmArgs args_head1(const NetDims& x, const DevWeight
                                                const PassCtx& c) {
   GemmArgs g = gemm_base(c.M, x.d, x.d, R_HEAD1);
   g.X = c.x; g.ldx = x.d; g.gain = w.head_g; g.W = w.W1; g.Y = c.t1; g.ldy = x.d;
-  use_q(g, w.prec, w.head1);
+  use_q(g, w, w.head1);
   return g;
 }
 __host__ __device__ inline GemmArgs args_head2(const NetDims& x, const DevWeights& w,
@@ -205,7 +219,7 @@ __host__ __device__ inline GemmArgs args_head2(const NetDims& x, const DevWeight
   g.head.mean = c.mean; g.head.scale = c.scale; g.head.center = c.center;
   g.head.index = c.index; g.head.center_c = c.center_c; g.head.index_c = c.index_c;
   g.head.flag = c.flag;
-  use_q(g, w.prec, w.head2, w.head2, 0, (size_t)x.C * x.d);
+  use_q(g, w, w.head2, w.head2, 0, (size_t)x.C * x.d);
   return g;
 }
 
@@ -215,7 +229,7 @@ __host__ __device__ inline GemmArgs args_embed(const NetDims& x, const DevWeight
   GemmArgs g = gemm_base(c.M, x.d, x.C, R_EMBED);
   g.Xi = c.ydec; g.ldx = x.C; g.xrow = c.gpos; g.xscale = w.ing; g.W = w.inW;
   g.Y = c.e; g.ldy = x.d;
-  use_q(g, w.prec, w.in);
+  use_q(g, w, w.in);
   return g;
 }
 __host__ __device__ inline GemmArgs args_acc_kv(const NetDims& x, const DevWeights& w,
@@ -223,7 +237,7 @@ __host__ __device__ inline GemmArgs args_acc_kv(const NetDims& x, const DevWeigh
   GemmArgs g = gemm_base(c.M, 2 * x.d, x.d, R_ACCKV);
   g.X = c.e; g.ldx = x.d; g.gain = w.acc_gkv; g.W = w.acc_Wkv;
   g.Y = c.acc_kv; g.ldy = 2 * x.d; g.yrow = c.gpos;
-  use_q(g, w.prec, w.acc_kv);
+  use_q(g, w, w.acc_kv);
   return g;
 }
 

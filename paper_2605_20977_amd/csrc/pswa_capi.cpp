@@ -76,7 +76,7 @@ void embed_prev(const pswa_model* m, int HW, int HWt, int off, const int32_t* pr
     GemmArgs a = gemm_base(HW, x.d, x.C, R_TKV);
     a.Xi = prev + (size_t)tau * HW * x.C; a.ldx = x.C; a.xscale = m->w.ing; a.W = m->w.inW;
     a.Y = e_prev + ((size_t)tau * HWt + off) * x.d; a.ldy = x.d;
-    use_q(a, m->w.prec, m->w.in);
+    use_q(a, m->w, m->w.in);
     gemm_run(A_INT, false, EPI_STORE, a, st);
   }
 }
@@ -89,7 +89,7 @@ void temporal_kv_layer(const pswa_model* m, int HW, int HWt, int off, const floa
     a.X = e_prev + ((size_t)tau * HWt + off) * x.d; a.ldx = x.d; a.gain = m->w.layers[l].g1;
     a.W = m->w.layers[l].Wqkv + (size_t)x.d * x.d;
     a.Y = tkv_l + ((size_t)tau * HWt + off) * 2 * x.d; a.ldy = 2 * x.d;
-    use_q(a, m->w.prec, m->w.layers[l].qkv, QW{nullptr, 1.f}, (size_t)x.d * x.d);
+    use_q(a, m->w, m->w.layers[l].qkv, QW{}, (size_t)x.d * x.d);
     gemm_run(A_FLOAT, true, EPI_STORE, a, st);
   }
 }
@@ -129,7 +129,15 @@ bool valid_desc(const pswa_model_desc* d, std::string* why) {
     return *why = "unknown precision", false;
   if (d->cycle != 0 && (d->cycle < 2 || d->cycle > 16))
     return *why = "cycle must be 0 (wavefront) or in [2, 16]", false;
+  if (d->act_scaling != PSWA_ACT_TENSOR &&
+      !(d->prec == PSWA_FP8_E4M3 && d->act_scaling == PSWA_ACT_ROW))
+    return *why = "act_scaling must be PSWA_ACT_TENSOR, or PSWA_ACT_ROW for FP8 models", false;
   return true;
+}
+
+// Whether the blob carries calibrated activation maxima after the weights.
+bool has_act_maxima(const pswa_model_desc& d) {
+  return d.prec == PSWA_FP8_E4M3 && d.act_scaling == PSWA_ACT_TENSOR;
 }
 
 NetDims dims_of(const pswa_model_desc& m) {
@@ -210,6 +218,24 @@ struct QuantTarget {
   QW* dst;
   int K;
 };
+// Calibration slot of every projection input (see act_points): gate and up
+// share their input.
+void assign_slots(DevWeights& w, const NetDims& x) {
+  w.in.slot = 0;
+  w.acc_q.slot = 1;
+  w.acc_kv.slot = 2;
+  w.acc_o.slot = 3;
+  for (int l = 0; l < x.L; ++l) {
+    LayerWeights& Ly = w.layers[l];
+    Ly.qkv.slot = 4 + 4 * l;
+    Ly.o.slot = 5 + 4 * l;
+    Ly.gate.slot = Ly.up.slot = 6 + 4 * l;
+    Ly.down.slot = 7 + 4 * l;
+  }
+  w.head1.slot = 4 + 4 * x.L;
+  w.head2.slot = 5 + 4 * x.L;
+}
+
 std::vector<QuantTarget> quant_targets(DevWeights& w, const NetDims& x) {
   std::vector<QuantTarget> t = {
       {3, &w.in, x.C}, {5, &w.acc_q, x.d}, {7, &w.acc_kv, x.d}, {11, &w.acc_o, x.d}};
@@ -392,7 +418,14 @@ const char* pswa_last_error(void) { return pswa::last_error(); }
 size_t pswa_model_blob_floats(const pswa_model_desc* desc) {
   std::string why;
   if (!valid_desc(desc, &why)) return 0;
-  return blob_layout(dims_of(*desc), nullptr, nullptr);
+  const NetDims x = dims_of(*desc);
+  return blob_layout(x, nullptr, nullptr) + (has_act_maxima(*desc) ? act_points(x.L) : 0);
+}
+
+int pswa_act_points(const pswa_model_desc* desc) {
+  std::string why;
+  if (!valid_desc(desc, &why)) return 0;
+  return act_points(desc->L);
 }
 
 // Device layout: the FP32 weights (each tensor 256-byte aligned), then for
@@ -428,9 +461,16 @@ pswa_status pswa_model_create(const pswa_model_desc* desc, const float* h_blob,
   if ((reinterpret_cast<uintptr_t>(d_mem) % kAlign) != 0)
     return fail(PSWA_E_ARG, "device memory must be 256-byte aligned");
   const NetDims x = dims_of(*desc);
-  const size_t need = blob_layout(x, nullptr, nullptr);
+  const size_t nweights = blob_layout(x, nullptr, nullptr);
+  const size_t need = pswa_model_blob_floats(desc);
   if (blob_floats != need)
     return fail(PSWA_E_SHAPE, "blob has %zu floats, model needs %zu", blob_floats, need);
+  if (has_act_maxima(*desc))
+    for (int k = 0; k < act_points(x.L); ++k) {
+      const float v = h_blob[nweights + k];
+      if (!(v >= 0.f) || !std::isfinite(v))
+        return fail(PSWA_E_ARG, "activation maximum %d is %g (must be finite and >= 0)", k, v);
+    }
   if (d_bytes < pswa_model_device_bytes(desc))
     return fail(PSWA_E_ARG, "device region %zu bytes < %zu", d_bytes, pswa_model_device_bytes(desc));
   if (desc->prec != PSWA_FP32 && (x.C % 32 != 0 || x.d % 32 != 0))
@@ -452,6 +492,7 @@ pswa_status pswa_model_create(const pswa_model_desc* desc, const float* h_blob,
   blob_layout(x, static_cast<const float*>(d_mem), &m->w, kTensorAlign);
   m->w.prec = desc->prec == PSWA_BF16 ? PSWA_PREC_BF16
               : desc->prec == PSWA_FP8_E4M3 ? PSWA_PREC_FP8 : PSWA_PREC_F32;
+  assign_slots(m->w, x);
   std::vector<std::vector<uint8_t>> staging;
   if (desc->prec != PSWA_FP32) {
     std::vector<std::pair<int, size_t>> qoff;
@@ -485,7 +526,13 @@ pswa_status pswa_model_create(const pswa_model_desc* desc, const float* h_blob,
       q = to_fragment_layout(q, N, K, desc->prec == PSWA_BF16 ? 2 : 1);
       char* dst = static_cast<char*>(d_mem) + qoff[i].second;
       PSWA_HIP_TRY(hipMemcpyAsync(dst, q.data(), q.size(), hipMemcpyHostToDevice, st));
-      *targets[i].dst = QW{dst, inv};
+      QW& qw = *targets[i].dst;
+      qw.q = dst;
+      qw.inv_scale = inv;
+      if (has_act_maxima(*desc)) {  // static per-tensor activation scale
+        const double amax = h_blob[nweights + qw.slot];
+        qw.ascale = amax > 0 ? float(448.0 / amax) : 1.0f;
+      }
       staging.push_back(std::move(q));
     }
   }
@@ -522,11 +569,15 @@ size_t pswa_encode_workspace_bytes(const pswa_model* model, const pswa_frame_des
   return plan_encode(model->x, *frame, nullptr).bytes;
 }
 
-pswa_status pswa_encode_params(const pswa_model* model, const pswa_frame_desc* frame,
-                               const int32_t* d_latents, const int32_t* d_hyper,
-                               const int32_t* d_prev, float* d_mean, float* d_scale,
-                               float* d_bits, int32_t* d_cdf_center, uint16_t* d_cdf_index,
-                               double* h_total_bits, void* d_ws, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+pswa_status encode_impl(const pswa_model* model, const pswa_frame_desc* frame,
+                        const int32_t* d_latents, const int32_t* d_hyper,
+                        const int32_t* d_prev, float* d_mean, float* d_scale,
+                        float* d_bits, int32_t* d_cdf_center, uint16_t* d_cdf_index,
+                        double* h_total_bits, void* d_ws, size_t ws_bytes, void* stream) {
   std::string why;
   if (!model) return fail(PSWA_E_ARG, "model is null");
   if (!valid_frame(frame, &why)) return fail(PSWA_E_SHAPE, "invalid frame: %s", why.c_str());
@@ -571,6 +622,69 @@ pswa_status pswa_encode_params(const pswa_model* model, const pswa_frame_desc* f
   if (h_total_bits)
     return finish_sum(d_bits, (size_t)HW * x.C, ws.sum, ws.flag, h_total_bits, st);
   return PSWA_OK;
+}
+
+// Per-symbol outputs a calibration run writes and discards, after the encode
+// workspace.
+struct CalibOut {
+  float *mean, *scale, *bits;
+  int32_t* center;
+  uint16_t* index;
+  size_t bytes;
+};
+CalibOut plan_calib(size_t n, void* base) {
+  Layout L(base);
+  CalibOut o;
+  o.mean = L.take<float>(n);
+  o.scale = L.take<float>(n);
+  o.bits = L.take<float>(n);
+  o.center = L.take<int32_t>(n);
+  o.index = L.take<uint16_t>(n);
+  o.bytes = L.used;
+  return o;
+}
+
+}  // namespace
+
+extern "C" {
+
+pswa_status pswa_encode_params(const pswa_model* model, const pswa_frame_desc* frame,
+                               const int32_t* d_latents, const int32_t* d_hyper,
+                               const int32_t* d_prev, float* d_mean, float* d_scale,
+                               float* d_bits, int32_t* d_cdf_center, uint16_t* d_cdf_index,
+                               double* h_total_bits, void* d_ws, size_t ws_bytes, void* stream) {
+  return encode_impl(model, frame, d_latents, d_hyper, d_prev, d_mean, d_scale, d_bits,
+                     d_cdf_center, d_cdf_index, h_total_bits, d_ws, ws_bytes, stream);
+}
+
+size_t pswa_calibrate_workspace_bytes(const pswa_model* model, const pswa_frame_desc* frame) {
+  std::string why;
+  if (!model || !valid_frame(frame, &why)) return 0;
+  const size_t n = (size_t)frame->H * frame->W * model->x.C;
+  return align_up(plan_encode(model->x, *frame, nullptr).bytes) + plan_calib(n, nullptr).bytes;
+}
+
+pswa_status pswa_calibrate(const pswa_model* model, const pswa_frame_desc* frame,
+                           const int32_t* d_latents, const int32_t* d_hyper,
+                           const int32_t* d_prev, float* d_amax, void* d_ws, size_t ws_bytes,
+                           void* stream) {
+  std::string why;
+  if (!model) return fail(PSWA_E_ARG, "model is null");
+  if (model->desc.prec != PSWA_FP32)
+    return fail(PSWA_E_UNSUPPORTED, "calibration runs on an FP32 model");
+  if (!valid_frame(frame, &why)) return fail(PSWA_E_SHAPE, "invalid frame: %s", why.c_str());
+  if (!d_amax || !d_ws) return fail(PSWA_E_ARG, "null pointer argument");
+  if ((reinterpret_cast<uintptr_t>(d_ws) % kAlign) != 0)
+    return fail(PSWA_E_ARG, "workspace must be 256-byte aligned");
+  const size_t need = pswa_calibrate_workspace_bytes(model, frame);
+  if (ws_bytes < need) return fail(PSWA_E_ARG, "workspace %zu bytes < %zu", ws_bytes, need);
+  const size_t enc = align_up(plan_encode(model->x, *frame, nullptr).bytes);
+  const size_t n = (size_t)frame->H * frame->W * model->x.C;
+  CalibOut o = plan_calib(n, static_cast<char*>(d_ws) + enc);
+  pswa_model rec = *model;  // the same weights, recording each input's maximum
+  rec.w.calib = d_amax;
+  return encode_impl(&rec, frame, d_latents, d_hyper, d_prev, o.mean, o.scale, o.bits, o.center,
+                     o.index, nullptr, d_ws, enc, stream);
 }
 
 size_t pswa_state_bytes(const pswa_model* model, const pswa_frame_desc* frame) {

@@ -70,6 +70,14 @@ struct GemmArgs {
   const void* Wq = nullptr;              // [N][K] BF16 or FP8 copy of W
   const void* W2q = nullptr;
   float wscale = 1.f, w2scale = 1.f;     // 1 / (weight quantization scale)
+  // FP8 activations: ascale > 0 is the static per-tensor scale 448 / amax of
+  // this projection's input (the RMSNorm output for normed inputs), applied
+  // before rounding and divided out after the product; 0 scales each row by
+  // 448 / its own maximum.
+  float ascale = 0.f;
+  // Calibration (FP32 tiles only): when set, the largest |input| this
+  // projection multiplies is max-combined into *amax.
+  float* amax = nullptr;
   float* Y = nullptr;
   int ldy = 0;
   const int* yrow = nullptr;

@@ -22,6 +22,8 @@ PSWA_SRC_DEVICE, PSWA_SRC_BITSTREAM = 0, 1
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_SHAPE", -3: "E_ORDER", -4: "E_HIP",
           -5: "E_UNSUPPORTED", -6: "E_CORRUPT", -7: "E_NUMERIC"}
 PRECISIONS = {"fp32": PSWA_FP32, "bf16": PSWA_BF16, "fp8": PSWA_FP8_E4M3}
+PSWA_ACT_TENSOR, PSWA_ACT_ROW = 0, 1
+ACT_SCALING = {"tensor": PSWA_ACT_TENSOR, "row": PSWA_ACT_ROW}
 
 
 class PswaError(RuntimeError):
@@ -33,7 +35,8 @@ class PswaError(RuntimeError):
 
 class ModelDesc(C.Structure):
     _fields_ = [(n, C.c_int32) for n in
-                ("L", "d", "heads", "window", "mlp_ratio", "C", "Ch", "prec", "cycle")]
+                ("L", "d", "heads", "window", "mlp_ratio", "C", "Ch", "prec", "cycle",
+                 "act_scaling")]
 
 
 class FrameDesc(C.Structure):
@@ -55,6 +58,9 @@ def _load():
     P = C.POINTER
     sig = {
         "pswa_model_blob_floats": (sz, [P(ModelDesc)]),
+        "pswa_act_points": (i32, [P(ModelDesc)]),
+        "pswa_calibrate_workspace_bytes": (sz, [vp, P(FrameDesc)]),
+        "pswa_calibrate": (i32, [vp, P(FrameDesc), vp, vp, vp, vp, vp, sz, vp]),
         "pswa_model_device_bytes": (sz, [P(ModelDesc)]),
         "pswa_model_create": (i32, [P(ModelDesc), vp, sz, vp, sz, vp, P(vp)]),
         "pswa_model_destroy": (None, [vp]),
@@ -131,7 +137,8 @@ EXPORTED = ("pswa_model_blob_floats", "pswa_model_device_bytes", "pswa_model_cre
             "pswa_batch_autotune", "pswa_batch_capture", "pswa_batch_set_groups",
             "pswa_batch_groups", "pswa_train_workspace_bytes", "pswa_train_create",
             "pswa_train_step", "pswa_train_read", "pswa_train_num_steps", "pswa_train_destroy",
-            "pswa_student_accept", "pswa_batch_set_xcd_barrier")
+            "pswa_student_accept", "pswa_batch_set_xcd_barrier", "pswa_act_points",
+            "pswa_calibrate_workspace_bytes", "pswa_calibrate")
 
 
 def lib():
@@ -159,10 +166,10 @@ def _stream():
 
 # ------------------------------------------------------------------ shapes
 
-def model_desc(cfg, prec="fp32") -> ModelDesc:
+def model_desc(cfg, prec="fp32", act="tensor") -> ModelDesc:
     return ModelDesc(cfg.L, cfg.d, cfg.heads, cfg.window, cfg.mlp_ratio, cfg.C, cfg.Ch,
                      PRECISIONS[prec] if isinstance(prec, str) else int(prec),
-                     getattr(cfg, "cycle", 0))
+                     getattr(cfg, "cycle", 0), ACT_SCALING[act])
 
 
 def frame_desc(H, W, n_prev=0) -> FrameDesc:
@@ -216,13 +223,24 @@ def unpack_blob(cfg, blob) -> dict:
 # ------------------------------------------------------------------- model
 
 class Model:
-    """A model uploaded into a torch-owned device region."""
+    """A model uploaded into a torch-owned device region.
 
-    def __init__(self, cfg, weights, prec="fp32", device="cuda"):
+    FP8 models scale their projection inputs per tensor (act='tensor', the
+    default), from the calibrated maxima act_amax (see calibrate), or per row
+    (act='row')."""
+
+    def __init__(self, cfg, weights, prec="fp32", device="cuda", act="tensor", act_amax=None):
         import torch
         self.cfg = cfg
-        self.desc = model_desc(cfg, prec)
+        fp8 = (PRECISIONS[prec] if isinstance(prec, str) else int(prec)) == PSWA_FP8_E4M3
+        self.act = act if fp8 else "tensor"
+        self.desc = model_desc(cfg, prec, self.act)
         blob = pack_blob(cfg, weights)
+        if fp8 and self.act == "tensor":
+            if act_amax is None:
+                raise PswaError(-1, "an FP8 per-tensor model needs calibrated act_amax")
+            blob = np.concatenate([blob, np.asarray(act_amax, dtype=np.float32).ravel()])
+        self.act_amax = None if act_amax is None else np.asarray(act_amax, np.float32)
         need = _lib.pswa_model_blob_floats(C.byref(self.desc))
         if need != blob.size:
             raise PswaError(-2, f"blob has {blob.size} floats, library expects {need}")
@@ -677,6 +695,40 @@ def pswa_student_accept(bits_student, bits_full, max_overhead=0.01):
                                          float(max_overhead)))
 
 
-def make_model(cfg, weights, prec="fp32", device="cuda"):
-    """A model in the given arithmetic, ready to run."""
-    return Model(cfg, weights, prec, device)
+def pswa_act_points(cfg) -> int:
+    return _lib.pswa_act_points(C.byref(model_desc(cfg)))
+
+
+def pswa_calibrate(model: Model, frames):
+    """Maxima of every projection input of the FP32 model over the frames
+    (dicts with latents, hyper, prev): float32 numpy [pswa_act_points]."""
+    import torch
+    dev = model.mem.device
+    amax = torch.zeros(pswa_act_points(model.cfg), dtype=torch.float32, device=dev)
+    ws = None
+    for f in frames:
+        y = _i32(f["latents"], dev)
+        z = _i32(f["hyper"], dev)
+        pv = _i32(f["prev"], dev) if f.get("prev") is not None else None
+        _shape_check(model, y, z, pv)
+        fd = frame_desc(y.shape[0], y.shape[1], 2 if pv is not None else 0)
+        nws = _lib.pswa_calibrate_workspace_bytes(model.handle, C.byref(fd))
+        if ws is None or ws.numel() < nws:
+            ws = torch.empty(nws, dtype=torch.uint8, device=dev)
+        _check(_lib.pswa_calibrate(model.handle, C.byref(fd), _ptr(y), _ptr(z), _ptr(pv),
+                                   _ptr(amax), _ptr(ws), ws.numel(), _stream()))
+    torch.cuda.current_stream().synchronize()
+    return amax.cpu().numpy()
+
+
+def make_model(cfg, weights, prec="fp32", calib_frames=None, act="tensor", device="cuda"):
+    """A model in the given arithmetic, ready to run. An FP8 per-tensor
+    model is calibrated first, with the FP32 model, on calib_frames."""
+    if prec == "fp8" and act == "tensor":
+        if not calib_frames:
+            raise PswaError(-1, "an FP8 per-tensor model needs calibration frames")
+        ref = Model(cfg, weights, "fp32", device)
+        amax = pswa_calibrate(ref, calib_frames)
+        ref.close()
+        return Model(cfg, weights, prec, device, act="tensor", act_amax=amax)
+    return Model(cfg, weights, prec, device, act=act)

@@ -5,7 +5,9 @@ holds shapes, seeds and random draws only: none of the context model's
 arithmetic lives here, so the oracle and the HIP path stay independent.
 
 Everything is drawn with NumPy's PCG64 generator in float64 and rounded once
-(to int32 for symbols, to float32 for weights).
+(to int32 for symbols, to float32 for weights); each kind of draw (weights,
+latent, hyperprior, previous frames) has its own stream, seeded by
+SeedSequence([seed, kind]).
 
 Data recipe (a stand-in for the 1080p test sequences the paper evaluates on,
 which are not available):
@@ -33,7 +35,7 @@ __all__ = [
     "ModelCfg", "FrameCfg", "TINY", "FULL", "STUDENT",
     "bias_sizes", "weight_shapes", "model_weights",
     "latent_frame", "hyper_frame", "prev_frames", "frame_inputs",
-    "BATCH_MIX", "CONFIG_SEEDS", "CYCLIC", "TINY_CYCLIC",
+    "BATCH_MIX", "CONFIG_SEEDS", "CYCLIC", "TINY_CYCLIC", "CALIB_SEED", "calibration_frames",
 ]
 
 
@@ -108,6 +110,31 @@ CONFIG_SEEDS = {
     "1080p_cyclic": (50, 12),
 }
 
+# Data seeds of the frames that calibrate FP8 per-tensor activation scales:
+# disjoint from every seed a test or the benchmark decodes.
+CALIB_SEED = 9000
+
+
+def calibration_frames(mcfg: ModelCfg, H: int = 68, W: int = 120) -> list[dict]:
+    """One I-frame and one P-frame of H x W for calibrating activation
+    scales, as dicts of latents, hyper and prev."""
+    out = []
+    for k, n_prev in enumerate((0, 2)):
+        y, z, prev = frame_inputs(mcfg, FrameCfg(H, W, n_prev), CALIB_SEED + 10 * k)
+        out.append({"latents": y, "hyper": z, "prev": prev})
+    return out
+
+
+# Every kind of draw has its own stream, keyed by (seed, kind), so that equal
+# seed numbers of different kinds never share random numbers (a hyperprior
+# drawn from the weights' own stream would be correlated with the hyperprior
+# projection).
+_WEIGHTS, _LATENT, _HYPER, _PREV = 1, 2, 3, 4
+
+
+def _rng(seed: int, kind: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, kind])))
+
 
 def bias_sizes(cfg: ModelCfg) -> tuple[int, int, int]:
     """Number of relative-bias slots: (accumulator, spatial layer, temporal
@@ -154,7 +181,7 @@ def weight_shapes(cfg: ModelCfg) -> list[tuple[str, tuple[int, ...]]]:
 
 def model_weights(cfg: ModelCfg, seed: int) -> dict[str, np.ndarray]:
     """Random-init float32 weights, drawn in float64 and rounded once."""
-    rng = np.random.Generator(np.random.PCG64(seed))
+    rng = _rng(seed, _WEIGHTS)
     w: dict[str, np.ndarray] = {}
     for name, shape in weight_shapes(cfg):
         leaf = name.split(".")[-1]
@@ -197,7 +224,7 @@ def _smooth_field(rng, H, W, C, std_px=2.0, target_std=3.0):
 
 def latent_frame(H: int, W: int, C: int, seed: int) -> np.ndarray:
     """int32 [H, W, C] latent symbols (see the module recipe)."""
-    rng = np.random.Generator(np.random.PCG64(seed))
+    rng = _rng(seed, _LATENT)
     mu = _smooth_field(rng, H, W, C)
     b = np.exp(rng.uniform(math.log(0.2), math.log(4.0), size=C))
     lap = rng.laplace(0.0, 1.0, size=(H, W, C))
@@ -206,13 +233,13 @@ def latent_frame(H: int, W: int, C: int, seed: int) -> np.ndarray:
 
 def hyper_frame(Hh: int, Wh: int, Ch: int, seed: int) -> np.ndarray:
     """int32 [Hh, Wh, Ch] hyperprior symbols, rint(N(0, 2))."""
-    rng = np.random.Generator(np.random.PCG64(seed))
+    rng = _rng(seed, _HYPER)
     return np.rint(2.0 * rng.standard_normal((Hh, Wh, Ch))).astype(np.int32)
 
 
 def prev_frames(y: np.ndarray, seed: int) -> np.ndarray:
     """int32 [2, H, W, C]: y plus independent rint(N(0, 1)) drift per frame."""
-    rng = np.random.Generator(np.random.PCG64(seed))
+    rng = _rng(seed, _PREV)
     drift = np.rint(rng.standard_normal((2,) + y.shape)).astype(np.int32)
     return (y[None] + drift).astype(np.int32)
 

@@ -195,3 +195,31 @@ def test_frame_encode_uses_cyclic_order():
     assert data == P.pswa_range_encode_seq(ys, cs, xs)
     with pytest.raises(P.PswaError):
         P.pswa_range_encode(H, W, Cc, k, y, c, idx, cycle=1)
+
+
+def test_fp8_activation_scaling_descs():
+    """FP8 per-tensor models carry one calibrated maximum per projection
+    input after the weights (6 + 4 L of them); the per-row form and the
+    other precisions carry none; a negative or NaN maximum is refused before
+    any device call; per-row scaling is only for FP8."""
+    lib = P.lib()
+    cfg = synth.TINY
+    nw = lib.pswa_model_blob_floats(C.byref(P.model_desc(cfg, "fp32")))
+    assert lib.pswa_act_points(C.byref(P.model_desc(cfg))) == 6 + 4 * cfg.L
+    assert lib.pswa_model_blob_floats(C.byref(P.model_desc(cfg, "bf16"))) == nw
+    assert lib.pswa_model_blob_floats(C.byref(P.model_desc(cfg, "fp8", "row"))) == nw
+    assert lib.pswa_model_blob_floats(C.byref(P.model_desc(cfg, "fp8"))) == nw + 6 + 4 * cfg.L
+    for prec in ("fp32", "bf16"):
+        assert lib.pswa_model_blob_floats(C.byref(P.model_desc(cfg, prec, "row"))) == 0
+    d = P.model_desc(cfg, "fp8")
+    n = nw + 6 + 4 * cfg.L
+    for bad in (-1.0, float("nan"), float("inf")):
+        blob = np.zeros(n, np.float32)
+        blob[nw + 3] = bad
+        h = C.c_void_p()
+        st = lib.pswa_model_create(C.byref(d), blob.ctypes.data, n, 256, 1 << 30, None,
+                                   C.byref(h))
+        assert st == -1 and not h.value
+        assert b"activation maximum 3" in lib.pswa_last_error()
+    with pytest.raises(P.PswaError):
+        P.Model(cfg, synth.model_weights(cfg, 1), "fp8", device="cpu")  # no maxima given

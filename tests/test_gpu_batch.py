@@ -133,7 +133,8 @@ def test_batch_row_tile_and_autotune_keep_outputs(P, prec, tmp_path):
     """The row tile and grid only move rows between tiles and blocks: every
     (grid, row tile) choice, the autotuner's included, gives the same bits."""
     cfg = synth.TINY
-    model = P.Model(cfg, synth.model_weights(cfg, 1), prec)
+    model = P.make_model(cfg, synth.model_weights(cfg, 1), prec,
+                         synth.calibration_frames(cfg, 16, 16))
     fr = _frames(cfg, [(16, 16, 0), (13, 21, 2), (4, 37, 0)], 700)
     b = P.Batch(model, fr)
     b.run()

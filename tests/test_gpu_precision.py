@@ -1,11 +1,25 @@
 """GPU tests of the BF16 and FP8 (e4m3fn) projection forms.
 
-Within a precision, encode, per-diagonal decode and persistent batch decode
-run the same row-invariant MFMA tiles, so they must be bit-identical. Against
-the FP64 oracle the forms are held to their bits-overhead targets on the
-1080p-shaped P-frame (0.5 % for BF16, 1 % for FP8) and their mean/scale
-errors are reported.
+FP8 runs in both activation scalings: static per-tensor scales calibrated
+on frames whose seeds no test decodes (the configured form), and per-row
+scales.
+
+* Within a form, encode, per-diagonal decode and persistent batch decode
+  are bit-identical.
+* Against the FP64 oracle on the 1080p-shaped P-frame and I-frame, every
+  form's mean error |d mu| / max(|mu|, 1) and relative scale error are
+  bounded (the bounds are the largest errors measured, times 2), and its
+  bits overhead is held to the target (0.5 % BF16, 1 % FP8).
+* On those random-init frames sigma is about 3 everywhere and the data is
+  not what the model predicts, so bits barely move with mu (an FP8 mean
+  error of 0.2 costs < 0.01 %). A sharp model (scale offset ln 0.5) on
+  latents drawn from the FP64 model itself (oracle.model.sample_latents)
+  is where mu errors cost rate (an error of 0.1 on every mean costs about
+  2 %, tests/test_oracle_sampling.py), so the overhead bounds discriminate
+  there.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -18,6 +32,12 @@ pytestmark = pytest.mark.gpu
 
 KEYS = ("mean", "scale", "bits", "center", "index")
 BITS_TARGET = {"bf16": 0.005, "fp8": 0.01}
+FORMS = [("bf16", "tensor"), ("fp8", "tensor"), ("fp8", "row")]
+IDS = ["bf16", "fp8-tensor", "fp8-row"]
+# (mean error, scale error) bounds per form at 1080p: twice the largest
+# errors measured on the 1080p-shaped frames.
+ERR_BOUND = {("bf16", "tensor"): (0.05, 0.02), ("fp8", "tensor"): (1.0, 0.3),
+             ("fp8", "row"): (0.5, 0.2)}
 
 
 @pytest.fixture(scope="module")
@@ -37,6 +57,10 @@ def _same(a, b, label):
         assert torch.equal(a[k], b[k]), f"{label}: {k}"
 
 
+def _model(P, cfg, Wt, prec, act, calib_hw=(68, 120)):
+    return P.make_model(cfg, Wt, prec, synth.calibration_frames(cfg, *calib_hw), act=act)
+
+
 def _report(out, ref, y, label):
     mu = _np(out["mean"]).astype(np.float64)
     sg = _np(out["scale"]).astype(np.float64)
@@ -51,46 +75,97 @@ def _report(out, ref, y, label):
     return ov, emu, esg
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp8"])
-def test_tiny_precision_forms_agree(P, prec):
+@pytest.mark.parametrize("prec,act", FORMS, ids=IDS)
+def test_tiny_precision_forms_agree(P, prec, act):
     cfg = synth.TINY
     Wt = synth.model_weights(cfg, 1)
-    model = P.Model(cfg, Wt, prec)
+    model = _model(P, cfg, Wt, prec, act)
     fr = []
     for k, (H, W, npv) in enumerate([(16, 16, 0), (13, 21, 2), (5, 3, 0)]):
         y, z, prev = synth.frame_inputs(cfg, synth.FrameCfg(H, W, npv), 40 + k)
         fr.append({"latents": y, "hyper": z, "prev": prev})
-        print(f"case tiny {prec} {H}x{W} P={npv}", flush=True)
+        print(f"case tiny {prec}-{act} {H}x{W} P={npv}", flush=True)
         enc = P.pswa_encode_params(model, y, z, prev)
         dec = P.decode_frame(model, H, W, z, prev=prev, source="device", src=y)
-        _same(enc, dec, f"{prec} {H}x{W}")
+        _same(enc, dec, f"{prec}-{act} {H}x{W}")
         ref = om.forward(cfg, Wt, y, z, prev)
-        ov, emu, esg = _report(enc, ref, y, f"tiny {prec} {H}x{W}")
-        assert emu.max() < (0.05 if prec == "bf16" else 0.2)
+        ov, emu, esg = _report(enc, ref, y, f"tiny {prec}-{act} {H}x{W}")
+        assert emu.max() < (0.05 if prec == "bf16" else 1.0)
         fr[-1]["dec"] = dec
     b = P.Batch(model, fr)
     b.run()
     b.check()
     for k, f in enumerate(fr):
-        _same(b.outputs(k), f["dec"], f"batch {prec} frame {k}")
+        _same(b.outputs(k), f["dec"], f"batch {prec}-{act} frame {k}")
+
+
+def _frame_and_ref(key, n_prev):
+    cfg = synth.FULL
+    Wt = synth.model_weights(cfg, synth.CONFIG_SEEDS[key][1])
+    y, z, prev = synth.frame_inputs(cfg, synth.FrameCfg(68, 120, n_prev), synth.CONFIG_SEEDS[key][0])
+    return cfg, Wt, y, z, prev, om.forward(cfg, Wt, y, z, prev)
 
 
 @pytest.fixture(scope="module")
 def pframe():
-    cfg = synth.FULL
-    Wt = synth.model_weights(cfg, synth.CONFIG_SEEDS["1080p_P"][1])
-    y, z, prev = synth.frame_inputs(cfg, synth.FrameCfg(68, 120, 2), synth.CONFIG_SEEDS["1080p_P"][0])
-    ref = om.forward(cfg, Wt, y, z, prev)
-    return cfg, Wt, y, z, prev, ref
+    return _frame_and_ref("1080p_P", 2)
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp8"])
-def test_1080p_pframe_precision_bits_overhead(P, pframe, prec):
+@pytest.fixture(scope="module")
+def iframe():
+    return _frame_and_ref("1080p_I", 0)
+
+
+@pytest.mark.parametrize("prec,act", FORMS, ids=IDS)
+def test_1080p_pframe_precision(P, pframe, prec, act):
     cfg, Wt, y, z, prev, ref = pframe
-    print(f"case 1080p P {prec}", flush=True)
-    model = P.Model(cfg, Wt, prec)
+    print(f"case 1080p P {prec}-{act}", flush=True)
+    model = _model(P, cfg, Wt, prec, act)
     enc = P.pswa_encode_params(model, y, z, prev)
-    ov, emu, esg = _report(enc, ref, y, f"1080p-P {prec}")
+    ov, emu, esg = _report(enc, ref, y, f"1080p-P {prec}-{act}")
+    bm, bs = ERR_BOUND[(prec, act)]
+    assert emu.max() <= bm and esg.max() <= bs
     assert ov <= BITS_TARGET[prec]
     dec = P.decode_frame(model, 68, 120, z, prev=prev, source="device", src=y)
-    _same(enc, dec, f"1080p {prec}")
+    _same(enc, dec, f"1080p {prec}-{act}")
+
+
+@pytest.mark.parametrize("prec,act", FORMS, ids=IDS)
+def test_1080p_iframe_precision(P, iframe, prec, act):
+    """The headline's frame type (I-frames of the 1080p-shaped model)."""
+    cfg, Wt, y, z, prev, ref = iframe
+    print(f"case 1080p I {prec}-{act}", flush=True)
+    model = _model(P, cfg, Wt, prec, act)
+    enc = P.pswa_encode_params(model, y, z, prev)
+    ov, emu, esg = _report(enc, ref, y, f"1080p-I {prec}-{act}")
+    bm, bs = ERR_BOUND[(prec, act)]
+    assert emu.max() <= bm and esg.max() <= bs
+    assert ov <= BITS_TARGET[prec]
+
+
+@pytest.fixture(scope="module")
+def sharp():
+    """The 1080p-shaped model with scale offset ln 0.5 on a 12 x 20 I-frame
+    drawn from the FP64 model itself (about 1.3 bits per symbol)."""
+    cfg = synth.FULL
+    Wt = synth.model_weights(cfg, synth.CONFIG_SEEDS["1080p_I"][1])
+    Wt["head.bsig"][:] = np.float32(math.log(0.5))
+    H, W = 12, 20
+    z = synth.hyper_frame(-(-H // 4), -(-W // 4), cfg.Ch, 71)
+    noise = np.random.default_rng(72).standard_normal((H, W, cfg.C))
+    y = om.sample_latents(cfg, Wt, z, noise)
+    return cfg, Wt, y, z, om.forward(cfg, Wt, y, z)
+
+
+@pytest.mark.parametrize("prec,act", FORMS, ids=IDS)
+def test_sharp_model_bits_overhead(P, sharp, prec, act):
+    cfg, Wt, y, z, ref = sharp
+    print(f"case sharp model {prec}-{act}", flush=True)
+    model = _model(P, cfg, Wt, prec, act)
+    enc = P.pswa_encode_params(model, y, z)
+    ov, emu, esg = _report(enc, ref, y, f"sharp {prec}-{act}")
+    assert ov <= BITS_TARGET[prec]
+    m32 = P.Model(cfg, Wt)
+    o32 = P.pswa_encode_params(m32, y, z)
+    ov32, _, _ = _report(o32, ref, y, "sharp fp32")
+    assert abs(ov32) <= 1e-4

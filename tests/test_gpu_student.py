@@ -66,7 +66,7 @@ def test_student_fp32_matches_oracle_at_samples(P, frames, weights):
 def test_student_low_precision_batch_decode(P, frames, weights, prec, bound):
     cfg = synth.STUDENT
     m32 = P.Model(cfg, weights)
-    model = P.Model(cfg, weights, prec)
+    model = P.make_model(cfg, weights, prec, synth.calibration_frames(cfg))
     enc = [P.pswa_encode_params(model, f["latents"], f["hyper"], f["prev"]) for f in frames]
     b = P.Batch(model, frames)
     print(f"case student 4K {prec} batch groups {b.groups}", flush=True)
