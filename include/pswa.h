@@ -164,6 +164,26 @@ pswa_status pswa_encode_params(const pswa_model* model, const pswa_frame_desc* f
                                uint16_t* d_cdf_index, double* h_total_bits,
                                void* d_ws, size_t ws_bytes, void* stream);
 
+/* pswa_encode_params without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the workspace is the library's static
+ * scratch array on the current device, pswa_noalloc_scratch_bytes() bytes
+ * (64 MiB), held by every GPU the library runs on until the process ends.
+ * Other arguments and outputs as in pswa_encode_params (the caller still
+ * owns inputs and outputs). A frame whose workspace
+ * (pswa_encode_workspace_bytes) exceeds the scratch is refused with
+ * PSWA_E_UNSUPPORTED before any device work. Every call on one GPU shares
+ * that GPU's scratch: calls that overlap on one GPU (other streams, other
+ * threads) race, and must be serialized by the caller. The call clears what
+ * must start at zero itself; the scratch keeps the last call's contents. */
+size_t pswa_noalloc_scratch_bytes(void);
+pswa_status pswa_encode_params_noalloc(const pswa_model* model, const pswa_frame_desc* frame,
+                                       const int32_t* d_latents, const int32_t* d_hyper,
+                                       const int32_t* d_prev, float* d_mean, float* d_scale,
+                                       float* d_bits, int32_t* d_cdf_center,
+                                       uint16_t* d_cdf_index, double* h_total_bits,
+                                       void* stream);
+
 /* Calibration of FP8 per-tensor activation scales: runs the encode form of
  * an FP32 model on one frame (arguments as in pswa_encode_params) and
  * max-combines into d_amax [pswa_act_points] (device float, zeroed by the

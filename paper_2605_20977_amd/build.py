@@ -20,7 +20,7 @@ LIB = os.path.join(PKG, "libpswa.so")
 OBJ = os.path.join(PKG, "_build")
 
 SOURCES = ["kernels_f32.hip", "persistent.hip", "train.hip", "pswa_capi.cpp", "batch.cpp",
-           "coder.cpp", "profile.cpp"]
+           "coder.cpp", "profile.cpp", "noalloc.hip"]
 # persistent_kernel.hip is compiled once per (arithmetic, head size, row tile)
 PERSISTENT_INSTANCES = [(0, d, 32) for d in (16, 32, 48, 64)] + [
     (p, d, r) for p in (1, 2) for r in (16, 32) for d in (16, 32, 48, 64)]

@@ -646,6 +646,17 @@ CalibOut plan_calib(size_t n, void* base) {
 
 }  // namespace
 
+namespace pswa {
+pswa_status encode_into(const pswa_model* model, const pswa_frame_desc* frame,
+                        const int32_t* d_latents, const int32_t* d_hyper, const int32_t* d_prev,
+                        float* d_mean, float* d_scale, float* d_bits, int32_t* d_cdf_center,
+                        uint16_t* d_cdf_index, double* h_total_bits, void* d_ws, size_t ws_bytes,
+                        void* stream) {
+  return encode_impl(model, frame, d_latents, d_hyper, d_prev, d_mean, d_scale, d_bits,
+                     d_cdf_center, d_cdf_index, h_total_bits, d_ws, ws_bytes, stream);
+}
+}  // namespace pswa
+
 extern "C" {
 
 pswa_status pswa_encode_params(const pswa_model* model, const pswa_frame_desc* frame,

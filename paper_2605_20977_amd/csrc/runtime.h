@@ -114,6 +114,14 @@ void embed_prev(const pswa_model* m, int HW, int HWt, int off, const int32_t* pr
 void temporal_kv_layer(const pswa_model* m, int HW, int HWt, int off, const float* e_prev, int l,
                        float* tkv_l, hipStream_t st);
 
+// The parallel encode form with its workspace at d_ws (the body of
+// pswa_encode_params; the no-allocation variant passes its static scratch).
+pswa_status encode_into(const pswa_model* model, const pswa_frame_desc* frame,
+                        const int32_t* d_latents, const int32_t* d_hyper, const int32_t* d_prev,
+                        float* d_mean, float* d_scale, float* d_bits, int32_t* d_cdf_center,
+                        uint16_t* d_cdf_index, double* h_total_bits, void* d_ws, size_t ws_bytes,
+                        void* stream);
+
 pswa_status finish_sum(const float* bits, size_t n, float* d_sum, const int* d_flag,
                        double* h_total, hipStream_t st);
 

@@ -61,6 +61,9 @@ def _load():
         "pswa_act_points": (i32, [P(ModelDesc)]),
         "pswa_calibrate_workspace_bytes": (sz, [vp, P(FrameDesc)]),
         "pswa_calibrate": (i32, [vp, P(FrameDesc), vp, vp, vp, vp, vp, sz, vp]),
+        "pswa_noalloc_scratch_bytes": (sz, []),
+        "pswa_encode_params_noalloc": (i32, [vp, P(FrameDesc), vp, vp, vp, vp, vp, vp, vp, vp,
+                                             P(C.c_double), vp]),
         "pswa_model_device_bytes": (sz, [P(ModelDesc)]),
         "pswa_model_create": (i32, [P(ModelDesc), vp, sz, vp, sz, vp, P(vp)]),
         "pswa_model_destroy": (None, [vp]),
@@ -138,7 +141,8 @@ EXPORTED = ("pswa_model_blob_floats", "pswa_model_device_bytes", "pswa_model_cre
             "pswa_batch_groups", "pswa_train_workspace_bytes", "pswa_train_create",
             "pswa_train_step", "pswa_train_read", "pswa_train_num_steps", "pswa_train_destroy",
             "pswa_student_accept", "pswa_batch_set_xcd_barrier", "pswa_act_points",
-            "pswa_calibrate_workspace_bytes", "pswa_calibrate")
+            "pswa_calibrate_workspace_bytes", "pswa_calibrate", "pswa_noalloc_scratch_bytes",
+            "pswa_encode_params_noalloc")
 
 
 def lib():
@@ -316,6 +320,29 @@ def pswa_encode_params(model: Model, latents, hyper, prev=None, total_bits=True,
         model.handle, C.byref(fd), _ptr(y), _ptr(z), _ptr(pv), _ptr(out["mean"]),
         _ptr(out["scale"]), _ptr(out["bits"]), _ptr(out["center"]), _ptr(out["index"]),
         C.byref(tot) if total_bits else None, _ptr(ws), ws.numel(), _stream()))
+    if total_bits:
+        out["total_bits"] = tot.value
+    return out
+
+
+def pswa_encode_params_noalloc(model: Model, latents, hyper, prev=None, total_bits=True,
+                               out=None):
+    """The encode form on the library's static scratch (no workspace is
+    allocated by the library or here); out: optional preallocated outputs
+    (dict as returned)."""
+    dev = model.mem.device
+    y = _i32(latents, dev)
+    z = _i32(hyper, dev)
+    H, W, Cc = y.shape
+    pv = _i32(prev, dev) if prev is not None else None
+    _shape_check(model, y, z, pv)
+    fd = frame_desc(H, W, 2 if pv is not None else 0)
+    out = out or _outputs(H, W, Cc, dev)
+    tot = C.c_double(0.0)
+    _check(_lib.pswa_encode_params_noalloc(
+        model.handle, C.byref(fd), _ptr(y), _ptr(z), _ptr(pv), _ptr(out["mean"]),
+        _ptr(out["scale"]), _ptr(out["bits"]), _ptr(out["center"]), _ptr(out["index"]),
+        C.byref(tot) if total_bits else None, _stream()))
     if total_bits:
         out["total_bits"] = tot.value
     return out
