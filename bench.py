@@ -61,7 +61,7 @@ HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp8": 5000.0}
 FP32_VECTOR_TFLOPS = 157.3
 METRIC = "decoded latent symbols/sec (1080p-shaped) vs plain FP32, at stated bits overhead"
-DEFAULT_PATHS = ("plain:fp32,batch32:bf16,batch32:fp8,mixed32:bf16,student4k:bf16,"
+DEFAULT_PATHS = ("plain:fp32,batch32:bf16,batch256:bf16,batch32:fp8,mixed32:bf16,student4k:bf16,"
                  "student4k8:bf16,full4k8:bf16,encode:fp32,encode:bf16,bitstream:fp32,"
                  "cyclic32:bf16")
 BITS_BOUND = {"fp32": None, "bf16": 0.005, "fp8": 0.01}
@@ -87,6 +87,8 @@ def parse():
     ap.add_argument("--rtile", type=int, default=0, help="row tile 16/32; 0: autotuner")
     ap.add_argument("--groups", default="", metavar="FxB",
                     help="F frames per group, B blocks per group (default: autotuner)")
+    ap.add_argument("--attention", choices=("auto", "staged", "global"), default="auto",
+                    help="wavefront attention form (default: the autotuner's)")
     ap.add_argument("--tune-cache", default=None, help="autotuner JSON-lines cache file")
     ap.add_argument("--no-graph", action="store_true", help="issue runs without a HIP graph")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -294,8 +296,9 @@ def batch_frames(synth, cfg, kind, n, dseed):
     """Inputs of a batch path: n 1080p I-frames, n frames of the mixed batch
     (sizes in equal numbers, I- and P-frames alternating per size), or n
     4K-shaped frames (I and P alternating)."""
-    frames = []
-    for k in range(n):
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(k):
         if kind in ("batch", "cyclic"):
             fc, seed = synth.FrameCfg(68, 120), dseed + 1000 * k
         elif kind in ("student4k", "full4k"):
@@ -305,8 +308,9 @@ def batch_frames(synth, cfg, kind, n, dseed):
             H, W = synth.BATCH_MIX[(k * len(synth.BATCH_MIX)) // n]
             fc, seed = synth.FrameCfg(H, W, 2 if k % 2 else 0), synth.CONFIG_SEEDS["batch"][0] + k
         y, z, pv = synth.frame_inputs(cfg, fc, seed)
-        frames.append({"latents": y, "hyper": z, "prev": pv})
-    return frames
+        return {"latents": y, "hyper": z, "prev": pv}
+    with ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        return list(ex.map(one, range(n)))
 
 
 def frame_shapes(frames):
@@ -431,6 +435,8 @@ def main():
             if args.groups:
                 f, g = (int(v) for v in args.groups.split("x"))
                 b.set_groups(f, g)
+            if args.attention != "auto":
+                b.set_attention(args.attention == "staged")
             if not args.grid and not args.rtile and not args.groups:
                 print(f"{spec}: autotuning", file=sys.stderr, flush=True)
                 f, g, r, est = b.autotune(args.tune_cache, reps=2)
@@ -447,6 +453,7 @@ def main():
             paths[spec] = {"frames": n, "symbols_per_step": nsym, "grid": b.grid,
                            "groups": f"{ngr} x ({fpg} frames, {bpg} blocks)", "rtile": b.rtile,
                            "graph": not args.no_graph, "autotuned": tuned,
+                           "attention": "lds-staged" if b.attention_staged else "global",
                            "ms_per_step": 1e3 * dt / args.steps,
                            "value": nsym * args.steps / dt}
             runners[spec] = run

@@ -307,7 +307,8 @@ pswa_status pswa_batch_set_rtile(pswa_batch* batch, int rtile);
 int pswa_batch_rtile(const pswa_batch* batch);
 /* Autotuner: times every grouping candidate (frames per group and blocks
  * per group in powers of two) with 32-row tiles, then 16-row tiles on the
- * best grouping (BF16/FP8), each on a window of the widest global steps
+ * best grouping (BF16/FP8), then the other attention form on the winner
+ * (pswa_batch_set_attention), each on a window of the widest global steps
  * (reps timed runs, median), and keeps the fastest. With cache_path, a
  * result for the same device, model and frame mix is read from that file
  * (JSON lines) instead of timing, and new results are appended. Reports the
@@ -328,6 +329,16 @@ pswa_status pswa_batch_capture(pswa_batch* batch, void* stream);
  * L1; off, or for groups that span XCDs, every barrier is device-scope
  * (L2 written back and invalidated). Both give the same results. */
 pswa_status pswa_batch_set_xcd_barrier(pswa_batch* batch, int on);
+/* Attention form of the wavefront schedule (an autotuner knob; both give
+ * the same bits): staged != 0 stages, per tile of up to four consecutive
+ * diagonal rows of a frame, the union of their causal windows (K and V rows
+ * of a few heads at a time, the queries and the window biases) in LDS with
+ * direct global-to-LDS loads and computes the rows' items from LDS; 0 lets
+ * every lane load its key's rows from global memory. The cyclic schedule
+ * rejects staged != 0 (PSWA_E_UNSUPPORTED). Drops a captured graph.
+ * pswa_batch_attention returns the current form (-1 for a null batch). */
+pswa_status pswa_batch_set_attention(pswa_batch* batch, int staged);
+int pswa_batch_attention(const pswa_batch* batch);
 /* Bound on the spin count of one barrier wait before the launch aborts
  * (default about a second of waiting). Lowering it forces the abort path. */
 pswa_status pswa_batch_set_spin_limit(pswa_batch* batch, int64_t spins);
@@ -335,7 +346,7 @@ pswa_status pswa_batch_set_spin_limit(pswa_batch* batch, int64_t spins);
  * persistent kernel (rank 0 of group 0) writes the device wall clock
  * (100 MHz) when it reaches and when it leaves each of its group's barriers:
  * d_trace[2k] and d_trace[2k + 1] for barrier k, for 2k + 1 < n (device
- * int64). Barriers per step: 3 + 5 L + 4. n = 0 turns the trace off. */
+ * int64). Barriers per step: 2 + 5 L + 4. n = 0 turns the trace off. */
 pswa_status pswa_batch_trace(pswa_batch* batch, int64_t* d_trace, int n);
 void pswa_batch_destroy(pswa_batch* batch);
 

@@ -1,13 +1,16 @@
 """Build the HIP library libpswa.so in-tree with hipcc for gfx950.
 
-Usage: python paper_2605_20977_amd/build.py [--incremental]
+Usage: python paper_2605_20977_amd/build.py [--incremental] [--only P_D_R,...]
 (or __graft_entry__.build(), which always compiles every object).
 --incremental recompiles only objects older than their source or any header
-under csrc/ and include/. It does not import the package, so it works with
-no library built.
+under csrc/ and include/. --only (development builds) compiles just the
+listed persistent-kernel instances (arithmetic_headsize_rowtile) and stubs
+the others out. It does not import the package, so it works with no library
+built.
 """
 from __future__ import annotations
 
+import hashlib
 import os
 import subprocess
 import sys
@@ -43,41 +46,56 @@ def _run(cmd):
     return r.returncode, err
 
 
-def _headers_mtime() -> float:
-    t = 0.0
+def _headers_digest() -> str:
+    h = hashlib.sha256()
     for d in (CSRC, os.path.join(ROOT, "include")):
-        for f in os.listdir(d):
+        for f in sorted(os.listdir(d)):
             if f.endswith(".h"):
-                t = max(t, os.path.getmtime(os.path.join(d, f)))
-    return t
+                h.update(f.encode())
+                h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
 
 
-def _stale(cmd, hdr_mtime: float) -> bool:
-    obj, src = cmd[-1], cmd[-3]
-    if not os.path.exists(obj):
+def _unit_digest(cmd, hdr: str) -> str:
+    """Digest of what an object is built from: the command, its source and
+    every header (taken before the compile starts)."""
+    h = hashlib.sha256(hdr.encode())
+    h.update(" ".join(cmd[:-1]).encode())
+    h.update(open(cmd[-3], "rb").read())
+    return h.hexdigest()
+
+
+def _stale(cmd, digest: str) -> bool:
+    obj = cmd[-1]
+    stamp = obj + ".stamp"
+    if not (os.path.exists(obj) and os.path.exists(stamp)):
         return True
-    return os.path.getmtime(obj) < max(hdr_mtime, os.path.getmtime(src))
+    return open(stamp).read().strip() != digest
 
 
-def build(verbose: bool = True, jobs: int | None = None, incremental: bool = False) -> str:
+def build(verbose: bool = True, jobs: int | None = None, incremental: bool = False,
+          only: list | None = None) -> str:
     """Compile every object (in parallel; only the stale ones when
-    incremental) and link libpswa.so."""
+    incremental; `only` persistent instances, the rest as stubs) and link
+    libpswa.so."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     os.makedirs(OBJ, exist_ok=True)
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
     units = []  # the long persistent instances first
     for p, d, r in PERSISTENT_INSTANCES:
-        obj = os.path.join(OBJ, f"persistent_kernel_{p}_{d}_{r}.o")
+        stub = only is not None and (p, d, r) not in only
+        obj = os.path.join(OBJ, f"persistent_kernel_{p}_{d}_{r}{'_stub' if stub else ''}.o")
         units.append([hipcc, *HIPCC_FLAGS, *inc, f"-DPSWA_PREC={p}", f"-DPSWA_DH={d}",
-                      f"-DPSWA_R={r}", "-c", os.path.join(CSRC, "persistent_kernel.hip"),
-                      "-o", obj])
+                      f"-DPSWA_R={r}", *(["-DPSWA_STUB_INSTANCE"] if stub else []), "-c",
+                      os.path.join(CSRC, "persistent_kernel.hip"), "-o", obj])
     for src in SOURCES:
         obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
         units.append([hipcc, *HIPCC_FLAGS, *inc, "-c", os.path.join(CSRC, src), "-o", obj])
     objs = [u[-1] for u in units]
+    hdr = _headers_digest()
+    digests = {u[-1]: _unit_digest(u, hdr) for u in units}
     if incremental:
-        hdr = _headers_mtime()
-        units = [u for u in units if _stale(u, hdr)]
+        units = [u for u in units if _stale(u, digests[u[-1]])]
     jobs = jobs or min(16, os.cpu_count() or 1)
     if verbose:
         print(f"compiling {len(units)} objects with {jobs} jobs", flush=True)
@@ -88,8 +106,11 @@ def build(verbose: bool = True, jobs: int | None = None, incremental: bool = Fal
         if rc != 0:
             failed = True
             sys.stderr.write(" ".join(cmd) + "\n" + err + "\n")
-        elif verbose and err.strip():
-            sys.stderr.write(err + "\n")
+        else:
+            with open(cmd[-1] + ".stamp", "w") as f:
+                f.write(digests[cmd[-1]] + "\n")
+            if verbose and err.strip():
+                sys.stderr.write(err + "\n")
     if failed:
         raise RuntimeError("hipcc failed building libpswa.so")
     tmp = LIB + ".tmp"
@@ -105,4 +126,9 @@ def build(verbose: bool = True, jobs: int | None = None, incremental: bool = Fal
 
 
 if __name__ == "__main__":
-    build(incremental="--incremental" in sys.argv[1:])
+    argv = sys.argv[1:]
+    sel = None
+    if "--only" in argv:
+        sel = [tuple(int(v) for v in spec.split("_"))
+               for spec in argv[argv.index("--only") + 1].split(",")]
+    build(incremental="--incremental" in argv, only=sel)

@@ -58,6 +58,7 @@ struct pswa_batch {
   long long* trace = nullptr;
   int trace_len = 0;
   int rtile = 32;                       // A rows per MFMA tile (16 or 32)
+  int attn_staged = 0;                  // attention form (wavefront schedule)
   hipGraphExec_t graph = nullptr;       // captured run (pswa_batch_capture)
   ~pswa_batch() {
     if (graph) (void)hipGraphExecDestroy(graph);
@@ -67,6 +68,7 @@ struct pswa_batch {
   FrameInfo* d_frames = nullptr;
   int *gpos_all = nullptr, *fid_all = nullptr;
   float *h = nullptr, *acc_kv = nullptr, *kv = nullptr, *tkv = nullptr, *e_prev = nullptr;
+  float* q_acc = nullptr;  // accumulator queries of every position, before the launch
   int32_t *ysrc = nullptr, *ydec = nullptr;
   float *mean = nullptr, *scale = nullptr, *bits = nullptr;
   int32_t* center = nullptr;
@@ -129,6 +131,7 @@ void lay_out(const NetDims& x, const Plan& p, int n, void* base, pswa_batch* b) 
   b->gpos_all = L.take<int>(HWt);
   b->fid_all = L.take<int>(HWt);
   b->h = L.take<float>(HWt * x.d);
+  b->q_acc = L.take<float>(HWt * x.d);
   b->acc_kv = L.take<float>(HWt * 2 * x.d);
   b->kv = L.take<float>((size_t)x.L * HWt * 2 * x.d);
   b->tkv = p.any_p ? L.take<float>((size_t)x.L * 2 * HWt * 2 * x.d) : nullptr;
@@ -212,9 +215,13 @@ void build_tables(const pswa_batch* b, const GroupPlan& g, std::vector<GemmArgs>
     c.M = g.row_start[t + 1] - g.row_start[t];
     c.gpos = b->gpos_all + g.pos_off + g.row_start[t];
     c.fid = b->fid_all + g.pos_off + g.row_start[t];
-    gt->push_back(args_acc_q(x, w, c));
+    gt->push_back(args_acc_q(x, w, c));  // (computed before the launch, kept for the layout)
     gt->push_back(args_acc_o(x, w, c));
-    at->push_back(args_acc_attn(x, w, c));
+    AttnArgs aa = args_acc_attn(x, w, c);  // queries of the rows' positions
+    aa.q = b->q_acc;
+    aa.qrow = c.gpos;
+    aa.ldq = x.d;
+    at->push_back(aa);
     for (int l = 0; l < x.L; ++l) {
       gt->push_back(args_qkv(x, w, c, l));
       gt->push_back(args_o(x, w, c, l));
@@ -251,6 +258,8 @@ PersistArgs persist_args(const pswa_batch* b) {
   P.trace_len = b->trace_len;
   P.xcd_tab = b->xcd_tab;
   P.xcd_local = b->xcd_local;
+  P.cycle = b->model->x.cycle;
+  P.attn_staged = b->attn_staged;
   return P;
 }
 
@@ -380,6 +389,13 @@ pswa_status run(pswa_batch* b, hipStream_t st) {
         temporal_kv_layer(m, HW, b->HWt, fi.off, b->e_prev, l,
                           b->tkv + (size_t)l * 2 * b->HWt * 2 * x.d, st);
     }
+  }
+  {  // the accumulator's queries depend on the hyperprior tokens only
+    PassCtx c{};
+    c.M = b->HWt;
+    c.h = b->h;
+    c.q = b->q_acc;
+    gemm_run(A_FLOAT, true, EPI_STORE, args_acc_q(x, m->w, c), st);
   }
   const int ev = prof_begin(st);
   launch_persistent(persist_args(b), m->x, m->w.prec, b->rtile, b->grid, st);
@@ -575,14 +591,15 @@ pswa_status pswa_batch_autotune(pswa_batch* b, const char* cache_path, int reps,
     const std::string k = "{\"key\": \"" + key.str() + "\"";
     while (std::getline(in, line)) {
       if (line.compare(0, k.size(), k) != 0) continue;
-      int f = 0, g = 0, r = 0;
+      int f = 0, g = 0, r = 0, sa = 0;
       float ms = 0;
       if (std::sscanf(line.c_str() + k.size(),
                       ", \"frames_per_group\": %d, \"blocks_per_group\": %d, \"rtile\": %d, "
-                      "\"ms\": %f", &f, &g, &r, &ms) == 4 &&
-          (r == 16 || r == 32) && (r == 32 || m->w.prec)) {
+                      "\"attn_staged\": %d, \"ms\": %f", &f, &g, &r, &sa, &ms) == 5 &&
+          (r == 16 || r == 32) && (r == 32 || m->w.prec) && (sa == 0 || sa == 1)) {
         const int r_old = b->rtile;
         b->rtile = r;
+        b->attn_staged = x.cycle ? 0 : sa;
         const pswa_status s2 = apply_groups(b, f, g, st);
         if (s2 != PSWA_OK) {  // a stale entry (another device limit): retune
           b->rtile = r_old;
@@ -666,6 +683,25 @@ pswa_status pswa_batch_autotune(pswa_batch* b, const char* cache_path, int reps,
   b->rtile = br;
   pswa_status gs = apply_groups(b, bf, bb, st);
   if (gs != PSWA_OK) return gs;
+  // the attention form on the winner (wavefront schedule only)
+  int bs = b->attn_staged;
+  if (!x.cycle) {
+    for (int sa : {0, 1}) {
+      if (sa == bs) continue;
+      const int keep = b->attn_staged;
+      b->attn_staged = sa;
+      float med = 0;
+      const pswa_status ts = time_it(br, &med);
+      if (ts != PSWA_OK) return ts;
+      if (med < best) {
+        best = med;
+        bs = sa;
+      } else {
+        b->attn_staged = keep;
+      }
+    }
+    b->attn_staged = bs;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (best >= 1e30f) return fail(PSWA_E_HIP, "autotune: every candidate aborted");
@@ -677,8 +713,8 @@ pswa_status pswa_batch_autotune(pswa_batch* b, const char* cache_path, int reps,
   if (cache_path) {
     std::ofstream o(cache_path, std::ios::app);
     o << "{\"key\": \"" << key.str() << "\", \"frames_per_group\": " << bf
-      << ", \"blocks_per_group\": " << bb << ", \"rtile\": " << br << ", \"ms\": " << *out_ms
-      << "}\n";
+      << ", \"blocks_per_group\": " << bb << ", \"rtile\": " << br
+      << ", \"attn_staged\": " << b->attn_staged << ", \"ms\": " << *out_ms << "}\n";
   }
   return PSWA_OK;
 }
@@ -739,6 +775,17 @@ pswa_status pswa_batch_set_xcd_barrier(pswa_batch* b, int on) {
   drop_graph(b);
   return PSWA_OK;
 }
+
+pswa_status pswa_batch_set_attention(pswa_batch* b, int staged) {
+  if (!b) return fail(PSWA_E_ARG, "batch is null");
+  if (staged && b->model->x.cycle)
+    return fail(PSWA_E_UNSUPPORTED, "LDS-staged window tiles serve the wavefront schedule");
+  b->attn_staged = staged ? 1 : 0;
+  drop_graph(b);
+  return PSWA_OK;
+}
+
+int pswa_batch_attention(const pswa_batch* b) { return b ? b->attn_staged : -1; }
 
 pswa_status pswa_batch_trace(pswa_batch* b, int64_t* d_trace, int n) {
   if (!b) return fail(PSWA_E_ARG, "batch is null");

@@ -451,31 +451,19 @@ __device__ __forceinline__ FrameInfo attn_frame(const AttnArgs& a, int m) {
                    ldg(&a.frames[f].n_prev)};
 }
 
-// attn_item with the row's global position gp and frame fi already known.
-template <int DH>
-__device__ __forceinline__ void attn_item_at(const AttnArgs& a, int m, int hd, int gp,
-                                             const FrameInfo& fi, float* tr_all) {
-  (void)tr_all;  // no LDS: the merge runs in registers
+// The arithmetic of one (query row, head) item, shared by every path: lane
+// l owns key slots l, l+64, ... in slot order and runs an online softmax over
+// them; the lanes are then merged (common max and rescaled exp-sum by wave
+// reductions, the rescaled value vectors by the fixed butterfly of
+// merge_lanes). key_at(kk, kr, vr, b) fills key slot kk's K and V rows
+// (DH/4 float4 each) and its bias and returns false for a slot that is out
+// of the frame or masked; where a key comes from (global memory or an LDS
+// tile) never changes the arithmetic.
+template <int DH, class KeyAt>
+__device__ __forceinline__ void attn_core(const float4* q4, int n_keys, KeyAt& key_at,
+                                          float* out) {
   const int lane = threadIdx.x & 63;
-  const int lp = gp - fi.off;
-  const int pi = lp / fi.W, pj = lp % fi.W;
-  const int r = a.r, k1 = 2 * r + 1;
-  const int n_causal = 2 * r * (r + 1);
-  const int n_sp = a.cycle ? k1 * k1 : n_causal + (a.include_self ? 1 : 0);
-  const int step_p = a.cycle ? (pi + pj) % a.cycle : 0;
-  const bool temporal = a.tkv && fi.n_prev > 0;
-  const int n_tm = temporal ? 2 * k1 * k1 : 0;
-  const int n_keys = n_sp + (a.knull ? 1 : 0) + n_tm;
-  const int d = a.d;
   const float scale = 1.0f / sqrtf(float(DH));
-
-  // the query: every lane loads the whole row (the same addresses, served
-  // once), issued together with the first key's loads
-  const float* qp = a.q + (size_t)m * a.ldq + hd * DH;
-  float4 q4[DH / 4];
-#pragma unroll
-  for (int e = 0; e < DH / 4; ++e) q4[e] = ldg4(qp + 4 * e);
-
   float mx = -INFINITY, sum = 0.f;
   float o[DH];
 #pragma unroll
@@ -487,48 +475,9 @@ __device__ __forceinline__ void attn_item_at(const AttnArgs& a, int m, int hd, i
   for (int u = 0; u < kMaxKeys / 64; ++u) {
     const int kk = lane + 64 * u;
     if (kk >= n_keys) break;
-    const float* kp = nullptr;
-    const float* vp = nullptr;
-    float b = 0.f;
-    if (kk < n_sp) {
-      int da, db;
-      if (a.cycle || kk < r * k1) {  // cyclic: the full window in raster order
-        da = kk / k1 - r;
-        db = kk % k1 - r;
-      } else if (kk < n_causal) {
-        da = 0;
-        db = kk - r * k1 - r;
-      } else {
-        da = 0;
-        db = 0;
-      }
-      const int ki = pi + da, kj = pj + db;
-      if (ki < 0 || ki >= fi.H || kj < 0 || kj >= fi.W) continue;
-      if (a.cycle) {  // decoded early enough: strictly (accumulator) or not
-        const int step_k = (ki + kj) % a.cycle;
-        if (a.include_self ? step_k > step_p : step_k >= step_p) continue;
-      }
-      kp = a.kv + (size_t)(fi.off + ki * fi.W + kj) * 2 * d + hd * DH;
-      vp = kp + d;
-      b = ldg(a.bias + hd * a.nbias + kk);
-    } else if (a.knull && kk == n_sp) {
-      kp = a.knull + hd * DH;
-      vp = a.vnull + hd * DH;
-    } else {
-      const int t = kk - n_sp - (a.knull ? 1 : 0);
-      const int tau = t / (k1 * k1), rem = t % (k1 * k1);
-      const int ki = pi + rem / k1 - r, kj = pj + rem % k1 - r;
-      if (ki < 0 || ki >= fi.H || kj < 0 || kj >= fi.W) continue;
-      kp = a.tkv + ((size_t)tau * a.HWt + (size_t)(fi.off + ki * fi.W + kj)) * 2 * d + hd * DH;
-      vp = kp + d;
-      b = ldg(a.bias + hd * a.nbias + n_sp + t);
-    }
     float4 kr[DH / 4], vr[DH / 4];
-#pragma unroll
-    for (int e = 0; e < DH / 4; ++e) {
-      kr[e] = ldg4(kp + 4 * e);
-      vr[e] = ldg4(vp + 4 * e);
-    }
+    float b = 0.f;
+    if (!key_at(kk, kr, vr, b)) continue;
     float dot = 0.f;
 #pragma unroll
     for (int e = 0; e < DH / 4; ++e) dot = dot4(q4[e], kr[e], dot);
@@ -561,7 +510,101 @@ __device__ __forceinline__ void attn_item_at(const AttnArgs& a, int m, int hd, i
   float val = v[0];  // v[k], by constant indices (a variable index would put v in scratch)
 #pragma unroll
   for (int j = 1; j < merge_len<DH, 32>(); ++j) val = k == j ? v[j] : val;
-  if (k < merge_len<DH, 32>()) stg(a.out + (size_t)m * a.ldo + hd * DH + off + k, val / tot);
+  if (k < merge_len<DH, 32>()) stg(out + off + k, val / tot);
+}
+
+// Spatial window slot kk of a query at (pi, pj): its offset (da, db) (the
+// cyclic schedule's full window in raster order; else the r rows above in
+// full, the r cells to the left, then the query itself).
+__device__ __forceinline__ void window_offset(const AttnArgs& a, int kk, int& da, int& db) {
+  const int r = a.r, k1 = 2 * r + 1;
+  if (a.cycle || kk < r * k1) {
+    da = kk / k1 - r;
+    db = kk % k1 - r;
+  } else if (kk < 2 * r * (r + 1)) {
+    da = 0;
+    db = kk - r * k1 - r;
+  } else {
+    da = 0;
+    db = 0;
+  }
+}
+
+// Slot counts of a row: spatial (with self for layers), null, temporal.
+__device__ __forceinline__ int attn_n_sp(const AttnArgs& a) {
+  const int k1 = 2 * a.r + 1;
+  return a.cycle ? k1 * k1 : 2 * a.r * (a.r + 1) + (a.include_self ? 1 : 0);
+}
+
+// Temporal slot t (previous frame tau = t / k1^2 + 1, window in raster
+// order) of a query at (pi, pj): K/V row pointer and bias, false outside the
+// frame.
+__device__ __forceinline__ bool temporal_key(const AttnArgs& a, int hd, int dh, int pi, int pj,
+                                             const FrameInfo& fi, int n_sp, int t,
+                                             const float*& kp, float& b) {
+  const int r = a.r, k1 = 2 * r + 1;
+  const int tau = t / (k1 * k1), rem = t % (k1 * k1);
+  const int ki = pi + rem / k1 - r, kj = pj + rem % k1 - r;
+  if (ki < 0 || ki >= fi.H || kj < 0 || kj >= fi.W) return false;
+  kp = a.tkv + ((size_t)tau * a.HWt + (size_t)(fi.off + ki * fi.W + kj)) * 2 * a.d + hd * dh;
+  b = ldg(a.bias + hd * a.nbias + n_sp + t);
+  return true;
+}
+
+// attn_item with the row's global position gp and frame fi already known:
+// every key read from global memory. Every lane loads the query row itself
+// (the same addresses, served once), issued together with its first key.
+template <int DH>
+__device__ __forceinline__ void attn_item_at(const AttnArgs& a, int m, int hd, int gp,
+                                             const FrameInfo& fi, float* tr_all) {
+  (void)tr_all;  // no LDS: the merge runs in registers
+  const int lp = gp - fi.off;
+  const int pi = lp / fi.W, pj = lp % fi.W;
+  const int n_sp = attn_n_sp(a);
+  const int step_p = a.cycle ? (pi + pj) % a.cycle : 0;
+  const bool temporal = a.tkv && fi.n_prev > 0;
+  const int k1 = 2 * a.r + 1;
+  const int n_keys = n_sp + (a.knull ? 1 : 0) + (temporal ? 2 * k1 * k1 : 0);
+  const int d = a.d;
+
+  const float* qp = a.q + (size_t)map_row(a.qrow, m) * a.ldq + hd * DH;
+  float4 q4[DH / 4];
+#pragma unroll
+  for (int e = 0; e < DH / 4; ++e) q4[e] = ldg4(qp + 4 * e);
+
+  auto key_at = [&](int kk, float4* kr, float4* vr, float& b) -> bool {
+    const float* kp;
+    if (kk < n_sp) {
+      int da, db;
+      window_offset(a, kk, da, db);
+      const int ki = pi + da, kj = pj + db;
+      if (ki < 0 || ki >= fi.H || kj < 0 || kj >= fi.W) return false;
+      if (a.cycle) {  // decoded early enough: strictly (accumulator) or not
+        const int step_k = (ki + kj) % a.cycle;
+        if (a.include_self ? step_k > step_p : step_k >= step_p) return false;
+      }
+      kp = a.kv + (size_t)(fi.off + ki * fi.W + kj) * 2 * d + hd * DH;
+      b = ldg(a.bias + hd * a.nbias + kk);
+    } else if (a.knull && kk == n_sp) {
+      kp = a.knull + hd * DH;
+#pragma unroll
+      for (int e = 0; e < DH / 4; ++e) {
+        kr[e] = ldg4(kp + 4 * e);
+        vr[e] = ldg4(a.vnull + hd * DH + 4 * e);
+      }
+      return true;
+    } else {
+      if (!temporal_key(a, hd, DH, pi, pj, fi, n_sp, kk - n_sp - (a.knull ? 1 : 0), kp, b))
+        return false;
+    }
+#pragma unroll
+    for (int e = 0; e < DH / 4; ++e) {
+      kr[e] = ldg4(kp + 4 * e);
+      vr[e] = ldg4(kp + d + 4 * e);
+    }
+    return true;
+  };
+  attn_core<DH>(q4, n_keys, key_at, a.out + (size_t)m * a.ldo + hd * DH);
 }
 
 template <int DH>
@@ -574,6 +617,38 @@ __device__ __forceinline__ void attn_item(const AttnArgs& a, int item, bool live
 
 // Attention needs no LDS (the lanes are merged in registers).
 __host__ __device__ inline size_t attn_lds_bytes(int) { return 0; }
+
+// ------------------------------------------------ LDS-staged window tiles
+// Attention of the persistent wavefront decode: a block takes up to
+// kStageRows consecutive diagonal rows of one frame (query rows i0 .. i1 =
+// i0 + R - 1 at columns j(i) = j0 - s (i - i0)) and stages the union of
+// their causal windows in LDS, stage_heads heads at a time, with direct
+// global-to-LDS loads: per window cell an 896-byte slot holding the K and V
+// rows of those heads (one wave's load per cell), then the rows' queries and
+// the heads' window biases.
+// Each wave then computes its row's items for those heads from LDS alone
+// (for P-frames the temporal keys come from global memory). In image row ii
+// (i0 - r .. i1) the union is the column range [j(hi) - r, j(lo) + r] of the
+// query rows lo .. hi whose windows hold ii (windows of neighbouring
+// diagonal rows overlap, s <= 2r + 1), clipped to the frame; cells are
+// numbered image row by image row, and the accumulator's null key and value
+// follow as one more cell. A cell's data starts 16 (cell mod 8) bytes into
+// its slot, so that lanes reading different cells spread over the banks.
+constexpr int kStageRows = kWaves;             // query rows of a tile (one per wave)
+constexpr int kStageImgRows = kStageRows + 4;  // image rows of a tile (r <= 4)
+constexpr int kStageCells = 133;               // window cells (at most 132: r = 4, s = 5) + null
+constexpr int kStageCellBytes = 896;           // 56 16-byte slots per cell
+// heads staged together: their K and V rows fill at most 48 of a cell's 56
+// 16-byte slots (the rest is room for the skew of up to 7 slots)
+__host__ __device__ inline constexpr int stage_heads(int dh) { return 96 / dh > 0 ? 96 / dh : 1; }
+// byte offsets of the queries and the biases after the cells
+constexpr size_t kStageQOff = (size_t)kStageCells * kStageCellBytes;
+__host__ __device__ inline constexpr size_t stage_bias_off(int dh) {
+  return kStageQOff + (size_t)kStageRows * stage_heads(dh) * dh * 4;
+}
+__host__ __device__ inline size_t attn_stage_lds_bytes(int dh) {
+  return stage_bias_off(dh) + (size_t)stage_heads(dh) * 64 * 4;
+}
 
 template <int DH_dummy = 0>
 __device__ __forceinline__ void attn_item_any(const AttnArgs& a, int item, bool live,

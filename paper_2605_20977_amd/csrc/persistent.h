@@ -26,7 +26,8 @@ struct SymArgs {
 //
 // Per step t a group runs, in order (g = GEMM table entry, a = attention
 // table entry; every phase ends with the group barrier):
-//   g0 acc q, a0 acc attention, g1 acc O,
+//   a0 acc attention (its queries, g0, are computed for every position
+//   before the launch), g1 acc O,
 //   per layer l: g(2+4l) QKV, a(1+l) attention, g(3+4l) O, g(4+4l) gate/up,
 //                g(5+4l) down,
 //   g(2+4L) head W1, g(3+4L) head W2 (whose epilogue also gathers the step's
@@ -56,6 +57,9 @@ struct PersistArgs {
   int* xcd_tab;            // [grid]: XCD of each block, by (group, rank)
   int xcd_local;           // allow the one-XCD barrier for groups that qualify
   int args_lds_off;        // byte offset of the step's argument copy in dynamic LDS
+  int cycle;               // the model's schedule (0: wavefront)
+  int attn_staged;         // wavefront attention from LDS-staged window tiles (else
+                           // every key read by its lane from global memory)
 };
 
 // Kernel instances: (projection arithmetic, head size, row tile). Each is

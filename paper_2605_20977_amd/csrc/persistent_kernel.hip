@@ -149,6 +149,175 @@ __device__ __forceinline__ void attn_phase(const AttnArgs& a, float* smem, int r
   }
 }
 
+// Direct global-to-LDS loads (gfx950): every active lane moves `bytes` from
+// its own global address to lds + lane * bytes (lds: the same in the wave).
+__device__ __forceinline__ void lds_load16(const float* src, float* lds) {
+  __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                   (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
+}
+__device__ __forceinline__ void lds_load4(const float* src, float* lds) {
+  __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                   (__attribute__((address_space(3))) void*)lds, 4, 0, 0);
+}
+
+// Wavefront attention from LDS-staged window tiles (see device_ops.h): the
+// phase's rows are split into contiguous runs over the group's blocks; a
+// block cuts its run into tiles of up to kStageRows consecutive diagonal
+// rows of one frame and, per tile and group of stage_heads heads, loads the
+// union of the rows' windows (one wave load per cell), the rows' queries
+// and the heads' window biases into LDS, then each wave computes its row's
+// items from LDS (temporal keys of P-frames are read from global memory).
+// The arithmetic of every item is attn_core's, as in every other path.
+template <int DH>
+__device__ __forceinline__ void attn_phase_staged(const AttnArgs& a, float* smem, int rank,
+                                                  int nb) {
+  constexpr int HT = stage_heads(DH);
+  constexpr int QH = DH / 2;                 // 16-byte pieces of one head's K and V rows
+  constexpr int CF = kStageCellBytes / 4;    // floats per cell slot
+  __shared__ int s_base[kStageImgRows + 1], s_c0[kStageImgRows], s_gpos[kStageCells];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = a.r, s = r + 1, d = a.d;
+  const int n_sp = attn_n_sp(a);
+  const int k1 = 2 * r + 1;
+  float* qtile = smem + kStageQOff / 4;
+  float* btile = smem + stage_bias_off(DH) / 4;
+  // this lane's piece of a cell: head lh of the group, 16 bytes lq of that
+  // head's K (lq < DH/4) or V row
+  const int lh = lane / QH, lq = lane % QH;
+  const int lpart = lh * DH + (lq < DH / 4 ? 4 * lq : d - DH + 4 * lq);
+  const int rpb = (a.M + nb - 1) / nb;
+  const int m_lo = min(a.M, rank * rpb), m_hi = min(a.M, m_lo + rpb);
+  for (int m0 = m_lo; m0 < m_hi;) {
+    // the tile's rows: consecutive diagonal rows (i + 1, j - s) of one frame
+    const int gp0 = map_row(a.pos, m0);
+    const int f0 = a.fid ? ldg(a.fid + m0) : 0;
+    const FrameInfo fi = attn_frame(a, m0);
+    int R = 1;
+    while (R < kStageRows && m0 + R < m_hi) {
+      const int f = a.fid ? ldg(a.fid + m0 + R) : 0;
+      if (f != f0 || map_row(a.pos, m0 + R) != gp0 + R * (fi.W - s)) break;
+      ++R;
+    }
+    const int i0 = (gp0 - fi.off) / fi.W, j0 = (gp0 - fi.off) % fi.W;
+    // union of the windows, image row by image row
+    int base[kStageImgRows + 1], c0[kStageImgRows];
+    {
+      int acc = 0;
+#pragma unroll
+      for (int k = 0; k < kStageImgRows; ++k) {
+        const int ii = i0 - r + k;
+        int ca = 0, w = 0;
+        if (k < R + r && ii >= 0) {
+          const int lo = max(i0, ii), hi = min(i0 + R - 1, ii + r);
+          ca = max(0, j0 - s * (hi - i0) - r);
+          const int cb = min(fi.W - 1, j0 - s * (lo - i0) + r);
+          w = cb >= ca ? cb - ca + 1 : 0;
+        }
+        base[k] = acc;
+        c0[k] = ca;
+        acc += w;
+      }
+      base[kStageImgRows] = acc;
+    }
+    const int cells = base[kStageImgRows];
+    const int ncell = cells + (a.knull ? 1 : 0);  // the null key is cell `cells`
+    // the geometry in LDS: image rows (for the items' key lookup) and the
+    // global position of every cell (for the loads)
+#pragma unroll
+    for (int k = 0; k <= kStageImgRows; ++k)
+      if ((int)threadIdx.x == k) {
+        s_base[k] = base[k];
+        if (k < kStageImgRows) s_c0[k] = c0[k];
+      }
+    if ((int)threadIdx.x < cells) {
+      const int cell = threadIdx.x;
+      int k = 0;
+#pragma unroll
+      for (int kk = 1; kk < kStageImgRows; ++kk) k += cell >= base[kk] ? 1 : 0;
+      int bk = base[0], ck = c0[0];
+#pragma unroll
+      for (int kk = 1; kk < kStageImgRows; ++kk)
+        if (k == kk) {
+          bk = base[kk];
+          ck = c0[kk];
+        }
+      s_gpos[cell] = fi.off + (i0 - r + k) * fi.W + ck + cell - bk;
+    }
+    __syncthreads();
+    const bool live = wave < R;
+    const int m = m0 + min(wave, R - 1);
+    const int qr = map_row(a.qrow, m);
+    const int pi = i0 + wave, pj = j0 - s * wave;
+    const bool temporal = a.tkv && fi.n_prev > 0;
+    const int n_keys = n_sp + (a.knull ? 1 : 0) + (temporal ? 2 * k1 * k1 : 0);
+    for (int h0 = 0; h0 < a.heads; h0 += HT) {
+      const int nh = min(HT, a.heads - h0);
+      // K/V rows of the heads: cell c by wave c mod 4, 16 bytes per lane
+      if (lane < nh * QH) {
+        for (int c = wave; c < ncell; c += kWaves) {
+          const float* src = c < cells
+              ? a.kv + (size_t)s_gpos[c] * 2 * d + h0 * DH + lpart
+              : (lq < DH / 4 ? a.knull + (h0 + lh) * DH + 4 * lq
+                             : a.vnull + (h0 + lh) * DH + 4 * lq - DH);
+          lds_load16(src, smem + c * CF + 4 * (c & 7));
+        }
+      }
+      // each row's query for the heads, loaded by its own wave
+      if (live && lane < nh * DH / 4)
+        lds_load16(a.q + (size_t)qr * a.ldq + h0 * DH + 4 * lane, qtile + wave * HT * DH);
+      // the heads' window biases, 64 floats apart
+      for (int hh = wave; hh < nh; hh += kWaves)
+        if (lane < n_sp) lds_load4(a.bias + (h0 + hh) * a.nbias + lane, btile + hh * 64);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+      if (live) {
+        for (int hh = 0; hh < nh; ++hh) {
+          const int hd = h0 + hh;
+          float4 q4[DH / 4];
+#pragma unroll
+          for (int e = 0; e < DH / 4; ++e)
+            q4[e] = *reinterpret_cast<const float4*>(qtile + wave * HT * DH + hh * DH + 4 * e);
+          auto key_at = [&](int kk, float4* kr, float4* vr, float& b) -> bool {
+            int c;
+            if (kk < n_sp) {
+              int da, db;
+              window_offset(a, kk, da, db);
+              const int ki = pi + da, kj = pj + db;
+              if (ki < 0 || ki >= fi.H || kj < 0 || kj >= fi.W) return false;
+              const int k = wave + r + da;
+              c = s_base[k] + kj - s_c0[k];
+              b = btile[hh * 64 + kk];
+            } else if (a.knull && kk == n_sp) {
+              c = cells;
+            } else {
+              const float* kp;
+              if (!temporal_key(a, hd, DH, pi, pj, fi, n_sp, kk - n_sp - (a.knull ? 1 : 0), kp,
+                                b))
+                return false;
+#pragma unroll
+              for (int e = 0; e < DH / 4; ++e) {
+                kr[e] = ldg4(kp + 4 * e);
+                vr[e] = ldg4(kp + d + 4 * e);
+              }
+              return true;
+            }
+            const float* p = smem + c * CF + 4 * (c & 7) + hh * 2 * DH;
+#pragma unroll
+            for (int e = 0; e < DH / 4; ++e) {
+              kr[e] = *reinterpret_cast<const float4*>(p + 4 * e);
+              vr[e] = *reinterpret_cast<const float4*>(p + DH + 4 * e);
+            }
+            return true;
+          };
+          attn_core<DH>(q4, n_keys, key_at, a.out + (size_t)m * a.ldo + hd * DH);
+        }
+      }
+      __syncthreads();
+    }
+    m0 += R;
+  }
+}
+
 // PREC: the projections' arithmetic (FP32 SIMT, or BF16 / FP8 on MFMA); one
 // instance per (arithmetic, head size, row tile) keeps each one's registers
 // to itself.
@@ -162,6 +331,8 @@ __global__ void __launch_bounds__(kThreads) k_persistent(PersistArgs P) {
   const int rank = bm & 0xffff, nb = G.nblocks;
   const bool tracer = P.trace && bm == 0 && threadIdx.x == 0;
   const int L = P.L, ng = 6 + 4 * L, na = 1 + L;
+  // wavefront schedule: attention from LDS-staged window tiles, if chosen
+  const bool staged = P.cycle == 0 && P.attn_staged;
   const int t_end = min(P.t_end, G.T);
   unsigned target = 0;
   int nsync = 0;
@@ -212,16 +383,22 @@ __global__ void __launch_bounds__(kThreads) k_persistent(PersistArgs P) {
     const SymArgs sy = lds_uniform(ss);
     if (sy.M == 0) continue;  // same for every block of the group
 
-    gemm_phase<A_FLOAT, true, EPI_STORE, PREC, R>(lds_uniform(g + 0), smem4, rstd, rank, nb);
-    PSWA_SYNC
-    attn_phase<DH>(lds_uniform(at + 0), smem, rank, nb);
+    // (g0, the accumulator's query projection, depends on the hyperprior
+    // tokens only: it runs for every position before the launch)
+    if (staged)
+      attn_phase_staged<DH>(lds_uniform(at + 0), smem, rank, nb);
+    else
+      attn_phase<DH>(lds_uniform(at + 0), smem, rank, nb);
     PSWA_SYNC
     gemm_phase<A_FLOAT, false, EPI_RESID, PREC, R>(lds_uniform(g + 1), smem4, rstd, rank, nb);
     PSWA_SYNC
     for (int l = 0; l < L; ++l) {
       gemm_phase<A_FLOAT, true, EPI_QKV, PREC, R>(lds_uniform(g + 2 + 4 * l), smem4, rstd, rank, nb);
       PSWA_SYNC
-      attn_phase<DH>(lds_uniform(at + 1 + l), smem, rank, nb);
+      if (staged)
+        attn_phase_staged<DH>(lds_uniform(at + 1 + l), smem, rank, nb);
+      else
+        attn_phase<DH>(lds_uniform(at + 1 + l), smem, rank, nb);
       PSWA_SYNC
       gemm_phase<A_FLOAT, false, EPI_RESID, PREC, R>(lds_uniform(g + 3 + 4 * l), smem4, rstd, rank, nb);
       PSWA_SYNC
@@ -245,8 +422,14 @@ __global__ void __launch_bounds__(kThreads) k_persistent(PersistArgs P) {
 
 }  // namespace
 
+#ifdef PSWA_STUB_INSTANCE
+// development builds of a subset of the instances: this one is absent (the
+// host reports its models as unsupported)
+PSWA_PERSISTENT_GETTER(PSWA_PREC, PSWA_DH, PSWA_R) { return nullptr; }
+#else
 PSWA_PERSISTENT_GETTER(PSWA_PREC, PSWA_DH, PSWA_R) {
   return reinterpret_cast<const void*>(&k_persistent<PSWA_PREC, PSWA_DH, PSWA_R>);
 }
+#endif
 
 }  // namespace pswa

@@ -115,7 +115,8 @@ struct AttnArgs {
   FrameInfo frame0;
   int HWt;                     // positions in the global space (temporal K/V stride)
   int r, heads, dh, d;
-  const float* q; int ldq;     // [M][d]
+  const float* q; int ldq;     // query row m at q + qrow(m) * ldq
+  const int* qrow;             // null: m
   const float* kv;             // [HWt][2d]: K then V per position
   const float* tkv;            // [2][HWt][2d] temporal K/V (or null)
   const float* bias; int nbias;  // [heads][nbias]

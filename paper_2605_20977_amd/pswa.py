@@ -101,6 +101,8 @@ def _load():
                                       P(C.c_float)]),
         "pswa_batch_set_groups": (i32, [vp, i32, i32, vp]),
         "pswa_batch_set_xcd_barrier": (i32, [vp, i32]),
+        "pswa_batch_set_attention": (i32, [vp, i32]),
+        "pswa_batch_attention": (i32, [vp]),
         "pswa_train_workspace_bytes": (sz, [P(ModelDesc), i32, i32, i32]),
         "pswa_train_create": (i32, [P(ModelDesc), vp, sz, i32, i32, i32, vp, sz, vp, P(vp)]),
         "pswa_train_step": (i32, [vp, i32, i32, vp, vp, vp, vp, vp, C.c_float, C.c_float, i32,
@@ -142,7 +144,7 @@ EXPORTED = ("pswa_model_blob_floats", "pswa_model_device_bytes", "pswa_model_cre
             "pswa_train_step", "pswa_train_read", "pswa_train_num_steps", "pswa_train_destroy",
             "pswa_student_accept", "pswa_batch_set_xcd_barrier", "pswa_act_points",
             "pswa_calibrate_workspace_bytes", "pswa_calibrate", "pswa_noalloc_scratch_bytes",
-            "pswa_encode_params_noalloc")
+            "pswa_encode_params_noalloc", "pswa_batch_set_attention", "pswa_batch_attention")
 
 
 def lib():
@@ -509,6 +511,15 @@ class Batch:
                                         _stream(), C.byref(f), C.byref(g), C.byref(r),
                                         C.byref(ms)))
         return f.value, g.value, r.value, ms.value
+
+    def set_attention(self, staged):
+        """Attention form: True = LDS-staged window tiles, False = keys from
+        global memory (same bits)."""
+        _check(_lib.pswa_batch_set_attention(self.handle, 1 if staged else 0))
+
+    @property
+    def attention_staged(self):
+        return _lib.pswa_batch_attention(self.handle) == 1
 
     def set_xcd_barrier(self, on):
         _check(_lib.pswa_batch_set_xcd_barrier(self.handle, 1 if on else 0))

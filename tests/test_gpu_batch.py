@@ -250,3 +250,29 @@ def test_batch_barrier_forms_agree(P, tiny):
             b.check()
             for k in range(len(fr)):
                 _assert_same(b.outputs(k), ref[k], f"one_xcd={on} {fpg}x{bpg} frame {k}")
+
+
+def test_batch_attention_forms_agree(P, tiny):
+    """LDS-staged window tiles and per-lane global key loads give the same
+    bits, across groupings (tiles cut at frame borders and block runs),
+    I- and P-frames, frames narrower than a window; the cyclic schedule
+    refuses the staged form."""
+    cfg, Wt, model = tiny
+    sizes = [(7, 9, 0), (16, 16, 2), (5, 13, 0), (12, 4, 2), (1, 1, 0), (3, 30, 2), (9, 2, 0)]
+    fr = _frames(cfg, sizes, 1700)
+    ref = [_per_frame(P, model, f) for f in fr]
+    b = P.Batch(model, fr)
+    for fpg, bpg in ((1, 1), (1, 3), (2, 8), (7, 5), (7, 64)):
+        for staged in (True, False):
+            print(f"case attention staged={staged} groups {fpg}x{bpg}", flush=True)
+            b.set_groups(fpg, bpg)
+            b.set_attention(staged)
+            assert b.attention_staged == staged
+            b.run()
+            b.check()
+            for k in range(len(fr)):
+                _assert_same(b.outputs(k), ref[k], f"staged={staged} {fpg}x{bpg} frame {k}")
+    cm = P.Model(synth.TINY_CYCLIC, synth.model_weights(synth.TINY_CYCLIC, 1))
+    bc = P.Batch(cm, _frames(synth.TINY_CYCLIC, [(8, 8, 0)], 1800))
+    with pytest.raises(P.PswaError):
+        bc.set_attention(True)

@@ -35,9 +35,10 @@ BITS_TARGET = {"bf16": 0.005, "fp8": 0.01}
 FORMS = [("bf16", "tensor"), ("fp8", "tensor"), ("fp8", "row")]
 IDS = ["bf16", "fp8-tensor", "fp8-row"]
 # (mean error, scale error) bounds per form at 1080p: twice the largest
-# errors measured on the 1080p-shaped frames.
-ERR_BOUND = {("bf16", "tensor"): (0.05, 0.02), ("fp8", "tensor"): (1.0, 0.3),
-             ("fp8", "row"): (0.5, 0.2)}
+# errors measured on the 1080p-shaped I- and P-frames (BF16 0.0152 / 0.0040,
+# FP8 per tensor 0.244 / 0.068, FP8 per row 0.230 / 0.064).
+ERR_BOUND = {("bf16", "tensor"): (0.03, 0.008), ("fp8", "tensor"): (0.5, 0.14),
+             ("fp8", "row"): (0.5, 0.13)}
 
 
 @pytest.fixture(scope="module")

@@ -83,6 +83,23 @@ def test_student_low_precision_batch_decode(P, frames, weights, prec, bound):
         assert ov <= bound
 
 
+def test_student_fallback_takes_the_full_model(P, frames, weights):
+    """A student whose scale offset is moved far from the data's spread
+    codes the frames with many more bits than the full model: the rule must
+    send those frames to the full model (the branch random-init weights
+    never reach)."""
+    full = P.Model(synth.FULL, synth.model_weights(synth.FULL, synth.CONFIG_SEEDS["4k_student"][1]))
+    bad_w = {k: v.copy() for k, v in weights.items()}
+    bad_w["head.bsig"][:] = np.float32(np.log(0.2))   # sigma ~ 0.2 against a spread of ~3
+    bad = P.Model(synth.STUDENT, bad_w)
+    for k, f in enumerate(frames):
+        bs = P.pswa_encode_params(bad, f["latents"], f["hyper"], f["prev"])["total_bits"]
+        bf = P.pswa_encode_params(full, f["latents"], f["hyper"], f["prev"])["total_bits"]
+        print(f"frame {k}: perturbed student {bs:.0f} bits, full {bf:.0f} bits", flush=True)
+        assert bs > 1.01 * bf
+        assert not P.pswa_student_accept(bs, bf, 0.01)
+
+
 def test_student_fallback_rule(P, frames, weights):
     full = P.Model(synth.FULL, synth.model_weights(synth.FULL, synth.CONFIG_SEEDS["4k_student"][1]))
     stud = P.Model(synth.STUDENT, weights)

@@ -25,10 +25,10 @@ pytestmark = pytest.mark.gpu
 KEYS = ("mean", "scale", "bits", "center", "index", "latents")
 
 # Error bounds of the low-precision forms against the FP64 oracle, per
-# symbol: mean error |d mu| / max(|mu|, 1) and relative scale error. Set from
-# the largest errors measured on the 1080p-shaped P-frame and the mixed batch
-# (BF16: 0.016 / 0.0055, FP8 per-tensor: 0.19 / 0.062) with a margin of 2x.
-BOUND = {"bf16": (0.05, 0.02), "fp8": (1.0, 0.3)}
+# symbol: mean error |d mu| / max(|mu|, 1) and relative scale error; twice
+# the largest errors measured on the 1080p-shaped I- and P-frames (BF16:
+# 0.0152 / 0.0040; FP8 per-tensor: 0.244 / 0.068).
+BOUND = {"bf16": (0.03, 0.008), "fp8": (0.5, 0.14)}
 
 
 @pytest.fixture(scope="module")
@@ -95,13 +95,17 @@ def test_mixed_1080p_batch_every_timed_instance(P, full, prec):
     assert b.T == 455
     for fpg, bpg in ((2, 16), (1, 8)):
         for rt in (16, 32):
-            print(f"case mixed 1080p {prec} groups {fpg}x{bpg} rtile {rt}", flush=True)
-            b.set_groups(fpg, bpg)
-            b.set_rtile(rt)
-            b.run()
-            b.check()
-            for k in range(len(fr)):
-                _assert_same(b.outputs(k), ref[k], f"{prec} {fpg}x{bpg} rtile {rt} frame {k}")
+            for staged in (False, True):
+                print(f"case mixed 1080p {prec} groups {fpg}x{bpg} rtile {rt} staged {staged}",
+                      flush=True)
+                b.set_groups(fpg, bpg)
+                b.set_rtile(rt)
+                b.set_attention(staged)
+                b.run()
+                b.check()
+                for k in range(len(fr)):
+                    _assert_same(b.outputs(k), ref[k],
+                                 f"{prec} {fpg}x{bpg} rtile {rt} staged {staged} frame {k}")
     # the 34 x 60 P-frame against the oracle
     _against_oracle(cfg, Wt, fr[3], ref[3], prec, 6, 31, f"mixed {prec} 34x60 P")
 
@@ -117,6 +121,7 @@ def test_headline_1080p_i_batch(P, full, prec):
     b = P.Batch(model, fr)
     b.set_groups(1, 8)
     b.set_rtile(32)
+    b.set_attention(True)
     b.capture()
     for rep in range(2):
         print(f"case headline 1080p {prec} replay {rep}", flush=True)
@@ -140,9 +145,11 @@ def test_student_4k_bf16_batch_row_tiles(P, rt):
     b = P.Batch(model, fr)
     b.set_groups(1, 32)
     b.set_rtile(rt)
-    print(f"case student 4K bf16 rtile {rt}", flush=True)
-    b.run()
-    b.check()
-    for k in range(len(fr)):
-        _assert_same(b.outputs(k), ref[k], f"student rtile {rt} frame {k}")
+    for staged in (False, True):
+        print(f"case student 4K bf16 rtile {rt} staged {staged}", flush=True)
+        b.set_attention(staged)
+        b.run()
+        b.check()
+        for k in range(len(fr)):
+            _assert_same(b.outputs(k), ref[k], f"student rtile {rt} staged {staged} frame {k}")
     _against_oracle(cfg, Wt, fr[1], ref[1], "bf16", 5, 51 + rt, f"student 4K bf16 P rtile {rt}")
