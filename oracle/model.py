@@ -30,6 +30,19 @@ What is computed, with the passage each part follows:
   previous frames (time-causal SWA, Sec. 3.1).
 * Head -- Sec. 3.1: two-layer MLP to the mean and scale of a Gaussian, with
   learnable channel-wise output scales.
+* Channel Transformer (models with ch_groups = N >= 2) -- Sec. 3.1 and
+  Sec. 3.2 (s spatial steps decoupled from N channel groups): the channels
+  are split into N groups and decoded group after group at every position.
+  Its input joins the spatial output with the channel-shifted latent (the
+  shift by one group means group 0 sees the spatio-temporal context only);
+  each block mixes the groups with a dense linear map whose
+  block-lower-triangular mask lets group g read groups 0..g only (a masked
+  1x1 convolution), then runs a SwiGLU MLP per group; grouped two-layer
+  heads give the mean and scale of each group's channels. Readings: every
+  norm and MLP acts on one group's slice (a norm over all groups would let
+  later groups leak into earlier ones), pre-norm residual blocks as in the
+  spatial layers, the input projection of the shifted latent is masked
+  like the mixing map.
 
 Readings where the paper is silent: per-head learned relative-position bias
 as the only positional signal; RMSNorm eps 1e-5; no biases in linears;
@@ -310,8 +323,60 @@ def forward(cfg, Wt, y, z, prev=None, keep=False):
         if keep:
             out[f"x{l + 1}"] = x
 
-    out.update(head(cfg, Wt, x))
+    out.update(ct_head(cfg, Wt, x, y) if cfg.ch_groups else head(cfg, Wt, x))
     return out
+
+
+def group_rmsnorm(x, g, N):
+    """RMSNorm of each of the N equal channel groups of x on its own."""
+    sh = x.shape
+    xg = x.reshape(sh[:-1] + (N, sh[-1] // N))
+    out = xg / np.sqrt((xg * xg).mean(-1, keepdims=True) + EPS)
+    return out.reshape(sh) * g
+
+
+def group_mask(rows: int, cols: int, N: int) -> np.ndarray:
+    """[rows, cols] 0/1 mask, block (g, j) of N x N blocks set for j <= g."""
+    gi = np.arange(rows) // (rows // N)
+    gj = np.arange(cols) // (cols // N)
+    return (gj[None, :] <= gi[:, None]).astype(np.float64)
+
+
+def ct_head(cfg, Wt, x, y):
+    """Channel Transformer and grouped heads (definition form, every
+    position and group at once): mean, scale and log-scale of every symbol.
+    x: the spatial network's output [..., d]; y: the decoded latent [..., C]
+    (group g's prediction reads its groups 0 .. g-1 only)."""
+    N, C = cfg.ch_groups, cfg.C
+    dc = cfg.ch_d
+    dg, Cg = dc // N, C // N
+    xs = rmsnorm(x, _w(Wt, "ct.gx"))
+    ys = np.asarray(y, dtype=np.float64) * _w(Wt, "ct.gy")
+    sy = np.zeros_like(ys)
+    sy[..., Cg:] = ys[..., :C - Cg]  # channel shift by one group
+    c = linear(xs, _w(Wt, "ct.Wx")) + linear(sy, _w(Wt, "ct.Wy") * group_mask(dc, C, N))
+    mask = group_mask(dc, dc, N)
+    for b in range(cfg.ch_L):
+        p = f"ct{b}."
+        c = c + linear(group_rmsnorm(c, _w(Wt, p + "g1"), N), _w(Wt, p + "M") * mask)
+        v = group_rmsnorm(c, _w(Wt, p + "g2"), N)
+        Wg, Wu, Wd = _w(Wt, p + "Wgate"), _w(Wt, p + "Wup"), _w(Wt, p + "Wdown")
+        parts = []
+        for g in range(N):
+            vg = v[..., g * dg:(g + 1) * dg]
+            parts.append(linear(silu(linear(vg, Wg[g])) * linear(vg, Wu[g]), Wd[g]))
+        c = c + np.concatenate(parts, axis=-1)
+    z = group_rmsnorm(c, _w(Wt, "ctH.g"), N)
+    W1, W2 = _w(Wt, "ctH.W1"), _w(Wt, "ctH.W2")
+    mu = np.empty(x.shape[:-1] + (C,))
+    raw = np.empty(x.shape[:-1] + (C,))
+    for g in range(N):
+        t = linear(silu(linear(z[..., g * dg:(g + 1) * dg], W1[g])), W2[g])
+        mu[..., g * Cg:(g + 1) * Cg] = t[..., :Cg]
+        raw[..., g * Cg:(g + 1) * Cg] = t[..., Cg:]
+    mu = _w(Wt, "head.gmu") * mu + _w(Wt, "head.bmu")
+    lsig = np.clip(_w(Wt, "head.gsig") * raw + _w(Wt, "head.bsig"), LN_SIGMA_MIN, LN_SIGMA_MAX)
+    return {"mu": mu, "sigma": np.exp(lsig), "lsig": lsig}
 
 
 def head(cfg, Wt, x):
@@ -339,9 +404,11 @@ def forward_sequential(cfg, Wt, y, z, groups, prev=None, on_group=None):
     every cell a layer may see must be decoded or in the same group
     (checked); each group's own latents are read only after its prediction.
     This is the decoder's view: it never touches y of undecoded positions.
-    on_group(grp, prediction), if given, runs after a group is predicted and
-    before its latents are read (prediction: dict(mu, sigma, lsig) of the
-    group's rows); it may write y at the group's positions."""
+    on_group(grp, prediction, channels), if given, runs after a group is
+    predicted and before its latents are read (prediction: dict(mu, sigma,
+    lsig) of the group's rows, final for the `channels` slice: all channels,
+    or one channel group at a time for a Channel Transformer); it may write
+    y at the group's positions and those channels."""
     H, W, C = y.shape
     d, heads, r, L = cfg.d, cfg.heads, cfg.r, cfg.L
     dh = d // heads
@@ -435,11 +502,26 @@ def forward_sequential(cfg, Wt, y, z, groups, prev=None, on_group=None):
             vn = rmsnorm(yres, _w(Wt, p + "g2"))
             mlp = silu(linear(vn, _w(Wt, p + "Wgate"))) * linear(vn, _w(Wt, p + "Wup"))
             x = yres + linear(mlp, _w(Wt, p + "Wdown"))
-        hd = head(cfg, Wt, x)
-        for k in res:
-            res[k][gi, gj] = hd[k]
-        if on_group is not None:
-            on_group(grp, hd)
+        if cfg.ch_groups:
+            # channel groups one after the other: group g is predicted from
+            # the symbols of groups < g of these positions only (the later
+            # groups are hidden), then its symbols become known
+            Cg = cfg.C // cfg.ch_groups
+            for g in range(cfg.ch_groups):
+                ys = np.array(y[gi, gj], dtype=np.int64)
+                ys[:, g * Cg:] = 0
+                hd = ct_head(cfg, Wt, x, ys)
+                sl = slice(g * Cg, (g + 1) * Cg)
+                for k in res:
+                    res[k][gi, gj, sl] = hd[k][:, sl]
+                if on_group is not None:
+                    on_group(grp, hd, sl)
+        else:
+            hd = head(cfg, Wt, x)
+            for k in res:
+                res[k][gi, gj] = hd[k]
+            if on_group is not None:
+                on_group(grp, hd, slice(0, C))
         # The group's symbols are now decoded: fill the accumulator cache.
         e = latent_embed(Wt, y[gi, gj])
         acc_cache[gi, gj] = acc_keys_values(Wt, e)
@@ -458,8 +540,9 @@ def sample_latents(cfg, Wt, z, noise, prev=None):
     H, W, C = noise.shape
     y = np.zeros((H, W, C), dtype=np.int32)
 
-    def draw(grp, pred):
-        y[grp[:, 0], grp[:, 1]] = np.rint(pred["mu"] + pred["sigma"] * noise[grp[:, 0], grp[:, 1]])
+    def draw(grp, pred, ch):
+        gi, gj = grp[:, 0], grp[:, 1]
+        y[gi, gj, ch] = np.rint(pred["mu"][:, ch] + pred["sigma"][:, ch] * noise[gi, gj][:, ch])
 
     forward_sequential(cfg, Wt, y, z, schedule_groups(cfg, H, W), prev, on_group=draw)
     return y

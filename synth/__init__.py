@@ -36,6 +36,7 @@ __all__ = [
     "bias_sizes", "weight_shapes", "model_weights",
     "latent_frame", "hyper_frame", "prev_frames", "frame_inputs",
     "BATCH_MIX", "CONFIG_SEEDS", "CYCLIC", "TINY_CYCLIC", "CALIB_SEED", "calibration_frames",
+    "TINY_CT", "FULL_CT",
 ]
 
 
@@ -45,7 +46,10 @@ class ModelCfg:
     window k x k, SwiGLU hidden width mlp_ratio * d, C latent channels and
     Ch hyperprior channels. cycle = 0: wavefront schedule t = j + s i with
     the causal half-window; cycle = s >= 2: the cyclic schedule
-    step = (i + j) mod s with the full window masked by step."""
+    step = (i + j) mod s with the full window masked by step. ch_groups =
+    N >= 2 replaces the head by a Channel Transformer over N channel groups
+    (width ch_d, ch_L blocks, grouped SwiGLU of ch_ratio * ch_d / N per
+    group) with grouped prediction heads; 0 keeps the plain head."""
     L: int
     d: int
     heads: int
@@ -54,6 +58,10 @@ class ModelCfg:
     C: int
     Ch: int
     cycle: int = 0
+    ch_groups: int = 0
+    ch_d: int = 0
+    ch_L: int = 0
+    ch_ratio: int = 4
 
     @property
     def dh(self) -> int:
@@ -96,6 +104,13 @@ STUDENT = ModelCfg(L=2, d=128, heads=4, window=9, mlp_ratio=4, C=192, Ch=128)
 # on the 1080p model's widths, and its tiny counterpart.
 CYCLIC = ModelCfg(L=6, d=384, heads=8, window=7, mlp_ratio=4, C=192, Ch=128, cycle=4)
 TINY_CYCLIC = ModelCfg(L=2, d=64, heads=4, window=5, mlp_ratio=4, C=32, Ch=16, cycle=4)
+
+# The Channel Transformer (N = 4 channel groups, 2 blocks) on the tiny and
+# the 1080p-shaped models.
+TINY_CT = ModelCfg(L=2, d=64, heads=4, window=5, mlp_ratio=4, C=32, Ch=16,
+                   ch_groups=4, ch_d=64, ch_L=2, ch_ratio=2)
+FULL_CT = ModelCfg(L=6, d=384, heads=8, window=9, mlp_ratio=4, C=192, Ch=128,
+                   ch_groups=4, ch_d=512, ch_L=2, ch_ratio=4)
 
 # Batched decode mix: 8 frames of each grid size, I and P alternating.
 BATCH_MIX = [(15, 20), (34, 60), (45, 80), (68, 120)]
@@ -171,8 +186,20 @@ def weight_shapes(cfg: ModelCfg) -> list[tuple[str, tuple[int, ...]]]:
             (p + "g2", (d,)), (p + "Wgate", (F, d)), (p + "Wup", (F, d)),
             (p + "Wdown", (d, F)),
         ]
+    if cfg.ch_groups:
+        N, dc = cfg.ch_groups, cfg.ch_d
+        dg, Cg = dc // N, C // N
+        Fg = cfg.ch_ratio * dg
+        out += [("ct.gx", (d,)), ("ct.Wx", (dc, d)), ("ct.gy", (C,)), ("ct.Wy", (dc, C))]
+        for b in range(cfg.ch_L):
+            p = f"ct{b}."
+            out += [(p + "g1", (dc,)), (p + "M", (dc, dc)), (p + "g2", (dc,)),
+                    (p + "Wgate", (N, Fg, dg)), (p + "Wup", (N, Fg, dg)),
+                    (p + "Wdown", (N, dg, Fg))]
+        out += [("ctH.g", (dc,)), ("ctH.W1", (N, dg, dg)), ("ctH.W2", (N, 2 * Cg, dg))]
+    else:
+        out += [("head.g", (d,)), ("head.W1", (d, d)), ("head.W2", (2 * C, d))]
     out += [
-        ("head.g", (d,)), ("head.W1", (d, d)), ("head.W2", (2 * C, d)),
         ("head.gmu", (C,)), ("head.bmu", (C,)),
         ("head.gsig", (C,)), ("head.bsig", (C,)),
     ]
@@ -185,9 +212,9 @@ def model_weights(cfg: ModelCfg, seed: int) -> dict[str, np.ndarray]:
     w: dict[str, np.ndarray] = {}
     for name, shape in weight_shapes(cfg):
         leaf = name.split(".")[-1]
-        if leaf.startswith("W"):
-            a = rng.standard_normal(shape) / math.sqrt(shape[1])
-        elif leaf in ("g", "gq", "gkv", "g1", "g2", "gmu"):
+        if leaf.startswith("W") or leaf == "M":
+            a = rng.standard_normal(shape) / math.sqrt(shape[-1])
+        elif leaf in ("g", "gq", "gkv", "g1", "g2", "gmu", "gx"):
             a = np.ones(shape)
         elif leaf == "bias":
             a = 0.1 * rng.standard_normal(shape)
@@ -197,11 +224,13 @@ def model_weights(cfg: ModelCfg, seed: int) -> dict[str, np.ndarray]:
             a = np.zeros(shape)
         elif leaf == "gsig":
             a = np.full(shape, 0.25)
+        elif leaf == "gy":  # set below (input scale)
+            a = np.zeros(shape)
         elif leaf == "bsig":
             a = np.full(shape, math.log(3.0))
         else:
             raise KeyError(name)
-        if name == "in.g":
+        if name in ("in.g", "ct.gy"):
             a = np.full(shape, 1.0 / 3.0)
         w[name] = np.ascontiguousarray(a, dtype=np.float32)
     return w
