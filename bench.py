@@ -115,7 +115,16 @@ def macs_per_position(cfg, n_prev=0):
     k2 = (2 * r + 1) ** 2
     acc = d * d + 2 * d * d + d * d + (n_acc + 1) * 2 * d
     layer = 3 * d * d + d * d + 2 * d * F + F * d + (n_acc + 1) * 2 * d
-    m = cfg.Ch * d + C * d + acc + L * layer + d * d + 2 * C * d
+    m = cfg.Ch * d + C * d + acc + L * layer
+    N = getattr(cfg, "ch_groups", 0)
+    if N:  # Channel Transformer: input, masked latent input and mixing, MLPs, heads
+        dg, Cg = cfg.ch_d // N, C // N
+        Fg = cfg.ch_ratio * dg
+        m += d * cfg.ch_d + Cg * dg * N * (N - 1) // 2
+        m += cfg.ch_L * (dg * dg * N * (N + 1) // 2 + N * 3 * dg * Fg)
+        m += N * (dg * dg + 2 * Cg * dg)
+    else:
+        m += d * d + 2 * C * d
     if n_prev:
         m += L * (2 * k2 * 2 * d + 2 * d * d) + C * d
     return m

@@ -77,6 +77,23 @@ typedef struct {
                     the query's own (Sec. 3.2, Fig. 2) */
   int32_t act_scaling; /* FP8 activation scaling (pswa_act_scaling); must be
                           PSWA_ACT_TENSOR for FP32 and BF16 models */
+  /* Channel Transformer (Sec. 3.1; Sec. 3.2: N channel groups decoded one
+   * after the other at every step). ch_groups = 0: the plain head (ch_d and
+   * ch_L must be 0). ch_groups = N in [1, 8]: the latent's C channels are N
+   * groups of C/N (a multiple of 4); the head is replaced by a channel
+   * transformer of width ch_d (ch_d/N a multiple of 16 in [16, 512]) with
+   * ch_L in [1, 4] blocks and a SwiGLU of ch_ratio (1..4) * ch_d/N per group,
+   * and grouped two-layer heads. Its input is the spatial output (RMSNorm,
+   * then a linear map) plus a linear map of the latent shifted by one group
+   * (input scale first); each block adds a mixing map of the per-group
+   * RMSNorm of its input, masked block-lower-triangular so that group g
+   * reads groups 0..g only, then a per-group pre-norm SwiGLU. Group g's mean
+   * and scale therefore depend on the symbols of groups < g of the same
+   * position only. The channel transformer runs in FP32 in every precision;
+   * models with channel groups serve pswa_encode_params and the
+   * device-source decode (bitstream decoding, the batched decode and
+   * training return PSWA_E_UNSUPPORTED). */
+  int32_t ch_groups, ch_d, ch_L, ch_ratio;
 } pswa_model_desc;
 
 /* How a PSWA_FP8_E4M3 model scales each projection input before rounding it
@@ -113,6 +130,16 @@ typedef struct pswa_state pswa_state;
  *     Wo [d][d], g2 [d], Wgate [F][d], Wup [F][d], Wdown [d][F],
  *   head.g [d], head.W1 [d][d], head.W2 [2C][d], head.gmu [C], head.bmu [C],
  *   head.gsig [C], head.bsig [C];
+ * With channel groups (N = ch_groups, dc = ch_d, dg = dc/N, Cg = C/N,
+ * Fg = ch_ratio*dg) head.g, head.W1 and head.W2 are replaced by
+ *   ct.gx [d], ct.Wx [dc][d], ct.gy [C], ct.Wy [dc][C] (acting on the latent
+ *   shifted by one group: its column block j holds latent group j-1, block 0
+ *   zeros; only row group g's column blocks 0..g are used),
+ *   per block b = 0..ch_L-1: ct<b>.g1 [dc], ct<b>.M [dc][dc] (only blocks
+ *   (g, j) with j <= g are used), ct<b>.g2 [dc], ct<b>.Wgate [N][Fg][dg],
+ *   ct<b>.Wup [N][Fg][dg], ct<b>.Wdown [N][dg][Fg],
+ *   ctH.g [dc], ctH.W1 [N][dg][dg], ctH.W2 [N][2Cg][dg] (group g's means then
+ *   scales);
  * with r = (window-1)/2, F = mlp_ratio*d, nS = 2r(r+1)+1 spatial bias slots
  * (the causal window in row-major order, then the query itself) and
  * nT = 2(2r+1)^2 temporal slots (previous frame 1 then 2, each its full

@@ -158,6 +158,9 @@ void lay_out(const NetDims& x, const Plan& p, int n, void* base, pswa_batch* b) 
 
 pswa_status check_frames(const pswa_model* m, int n, const pswa_batch_frame* fr) {
   if (!m) return fail(PSWA_E_ARG, "model is null");
+  if (m->x.cg)
+    return fail(PSWA_E_UNSUPPORTED,
+                "the persistent decode of models with channel groups is not built");
   if (n < 1 || !fr) return fail(PSWA_E_ARG, "need at least one frame");
   for (int f = 0; f < n; ++f) {
     std::string why;

@@ -195,11 +195,12 @@ __device__ __forceinline__ void epilogue(const GemmArgs& a, int row, int n, floa
     stg(a.Y + (size_t)map_row(a.yrow, row) * a.ldy + n, silu(v) * v2);
   } else if (EPI == EPI_HEAD) {
     const HeadOut& h = a.head;
-    const float mu = fmaf(ldg(h.gmu + n), v, ldg(h.bmu + n));
-    const float raw = fmaf(ldg(h.gsig + n), v2, ldg(h.bsig + n));
+    const int cn = h.col0 + n;  // the output channel
+    const float mu = fmaf(ldg(h.gmu + cn), v, ldg(h.bmu + cn));
+    const float raw = fmaf(ldg(h.gsig + cn), v2, ldg(h.bsig + cn));
     const float ls = fminf(h.ln_smax, fmaxf(h.ln_smin, raw));
     const float sg = expf(ls);
-    const size_t o = (size_t)map_row(a.yrow, row) * a.N + n;
+    const size_t o = (size_t)map_row(a.yrow, row) * h.ldo + cn;
     stg(h.mean + o, mu);
     stg(h.scale + o, sg);
     int32_t c;
@@ -208,11 +209,11 @@ __device__ __forceinline__ void epilogue(const GemmArgs& a, int row, int n, floa
     stg(h.center + o, c);
     stg(h.index + o, x);
     if (h.center_c) {
-      stg(h.center_c + (size_t)row * a.N + n, c);
-      stg(h.index_c + (size_t)row * a.N + n, x);
+      stg(h.center_c + (size_t)row * h.ldo + cn, c);
+      stg(h.index_c + (size_t)row * h.ldo + cn, x);
     }
     if (h.ydec) {  // the row's symbol and its bits, from the values just computed
-      const int32_t y = ldg(h.ysrc + (h.src_compact ? (size_t)row * a.N + n : o));
+      const int32_t y = ldg(h.ysrc + (h.src_compact ? (size_t)row * h.ldo + cn : o));
       stg(h.ydec + o, y);
       stg(h.bits + o, symbol_bits_of(y, mu, sg));
     }
@@ -662,10 +663,11 @@ __device__ __forceinline__ void attn_item_any(const AttnArgs& a, int item, bool 
 }
 
 // ------------------------------------------------------------ symbol items
-// ydec[pos(m)][c] = src[(compact ? m : pos(m))][c]
+// ydec[pos(m)][c0 + c] = src[(compact ? m : pos(m))][c0 + c], idx = m * nc + c
 __device__ __forceinline__ void gather_item(const int32_t* src, int compact, const int* pos, int C,
-                                            int32_t* ydec, long idx) {
-  const int m = idx / C, c = idx % C;
+                                            int32_t* ydec, long idx, int c0 = 0, int nc = -1) {
+  if (nc < 0) nc = C;
+  const int m = idx / nc, c = c0 + idx % nc;
   const int p = map_row(pos, m);
   stg(ydec + (size_t)p * C + c, ldg(src + (size_t)(compact ? m : p) * C + c));
 }

@@ -6,6 +6,9 @@
 // kernel, so every path computes a row the same way.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+#include <cstdlib>
+
 #include "device_ops.h"
 #include "mfma_ops.h"
 #include "pswa_internal.h"
@@ -69,9 +72,24 @@ __global__ void k_hyper_embed(const int32_t* z, int Hh, int Wh, int Ch, const fl
 }
 
 __global__ void k_gather_symbols(const int32_t* src, int compact, const int* pos, int M, int C,
-                                 int32_t* ydec) {
+                                 int32_t* ydec, int c0, int nc) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx < (long)M * C) gather_item(src, compact, pos, C, ydec, idx);
+  if (idx < (long)M * nc) gather_item(src, compact, pos, C, ydec, idx, c0, nc);
+}
+
+// One wave per row: the sum of squares of the row's K-slice at col0, lane l
+// over elements l, l + 64, ... in order, then a fixed xor tree.
+__global__ void __launch_bounds__(256) k_group_rms(const float* X, int ldx, int M, int K, int col0,
+                                                   const float* gain, float* Y, int ldy) {
+  const int lane = threadIdx.x & 63;
+  const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (m >= M) return;
+  const float* x = X + (size_t)m * ldx + col0;
+  float ss = 0.f;
+  for (int k = lane; k < K; k += 64) ss = fmaf(x[k], x[k], ss);
+  ss = wave_sum(ss);
+  const float rs = 1.0f / sqrtf(ss / float(K) + kEps);
+  for (int k = lane; k < K; k += 64) Y[(size_t)m * ldy + col0 + k] = x[k] * rs * gain[col0 + k];
 }
 
 __global__ void k_symbol_bits(const int* pos, int M, int C, const int32_t* ydec,
@@ -138,21 +156,7 @@ void launch_big_any(const GemmArgs& a, hipStream_t s) {
 constexpr int kBigM = 256;  // rows from which the large tile pays
 
 template <int AK, bool RMS, int EPI>
-void launch_gemm(const GemmArgs& a, hipStream_t s) {
-  if (a.prec != PSWA_PREC_F32 && a.M >= kBigM) {
-    if (a.prec == PSWA_PREC_BF16) launch_big_any<AK, RMS, EPI, PSWA_PREC_BF16>(a, s);
-    else launch_big_any<AK, RMS, EPI, PSWA_PREC_FP8>(a, s);
-    return;
-  }
-  if (a.prec != PSWA_PREC_F32) {
-    static const bool attr_set =
-        allow_big_lds(reinterpret_cast<const void*>(&k_gemm_q<AK, RMS, EPI>));
-    (void)attr_set;
-    dim3 grid(qgemm_col_tiles(a.N, EPI), qgemm_row_tiles(a.M));
-    hipLaunchKernelGGL((k_gemm_q<AK, RMS, EPI>), grid, dim3(kThreads),
-                       qgemm_lds_bytes(a.K, a.prec), s, a);
-    return;
-  }
+void launch_gemm_f32(const GemmArgs& a, hipStream_t s) {
   dim3 grid(gemm_col_tiles(a.N, EPI), gemm_row_tiles(a.M));
   const size_t lds = gemm_lds_bytes(a.K);
 #define PSWA_KC(n)                                                                  \
@@ -173,6 +177,30 @@ void launch_gemm(const GemmArgs& a, hipStream_t s) {
 #undef PSWA_KC
 }
 
+template <int AK, bool RMS, int EPI>
+void launch_gemm(const GemmArgs& a, hipStream_t s) {
+  if (a.prec != PSWA_PREC_F32 && a.M >= kBigM) {
+    if (a.prec == PSWA_PREC_BF16) launch_big_any<AK, RMS, EPI, PSWA_PREC_BF16>(a, s);
+    else launch_big_any<AK, RMS, EPI, PSWA_PREC_FP8>(a, s);
+    return;
+  }
+  if (a.prec != PSWA_PREC_F32) {
+    static const bool attr_set =
+        allow_big_lds(reinterpret_cast<const void*>(&k_gemm_q<AK, RMS, EPI>));
+    (void)attr_set;
+    dim3 grid(qgemm_col_tiles(a.N, EPI), qgemm_row_tiles(a.M));
+    hipLaunchKernelGGL((k_gemm_q<AK, RMS, EPI>), grid, dim3(kThreads),
+                       qgemm_lds_bytes(a.K, a.prec), s, a);
+    return;
+  }
+  launch_gemm_f32<AK, RMS, EPI>(a, s);
+}
+
+[[noreturn]] void no_instance(const char* what, int a, int b, int c) {
+  std::fprintf(stderr, "pswa: no %s instance for (%d, %d, %d)\n", what, a, b, c);
+  std::abort();
+}
+
 void gemm_dispatch(AKind ak, bool rms, Epi epi, const GemmArgs& a, hipStream_t s) {
 #define PSWA_G(AK_, R_, E_) \
   if (ak == AK_ && rms == R_ && epi == E_) return launch_gemm<AK_, R_, E_>(a, s)
@@ -185,6 +213,11 @@ void gemm_dispatch(AKind ak, bool rms, Epi epi, const GemmArgs& a, hipStream_t s
   PSWA_G(A_FLOAT, true, EPI_SWIGLU);
   PSWA_G(A_FLOAT, false, EPI_HEAD);
 #undef PSWA_G
+  // symbols of earlier channel groups added to the channel transformer's
+  // stream (FP32 in every precision)
+  if (ak == A_INT && !rms && epi == EPI_RESID && a.prec == PSWA_PREC_F32)
+    return launch_gemm_f32<A_INT, false, EPI_RESID>(a, s);
+  no_instance("GEMM", int(ak) * 10 + int(rms), int(epi), a.prec);
 }
 
 void attention_dispatch(const AttnArgs& a, hipStream_t s) {
@@ -195,7 +228,7 @@ void attention_dispatch(const AttnArgs& a, hipStream_t s) {
     case 32: hipLaunchKernelGGL(k_attn<32>, grid, dim3(kThreads), lds, s, a); break;
     case 48: hipLaunchKernelGGL(k_attn<48>, grid, dim3(kThreads), lds, s, a); break;
     case 64: hipLaunchKernelGGL(k_attn<64>, grid, dim3(kThreads), lds, s, a); break;
-    default: break;
+    default: no_instance("attention", a.dh, 0, 0);
   }
 }
 
@@ -255,12 +288,20 @@ void hyper_embed(const int32_t* z, int Hh, int Wh, int Ch, const float* Wm, cons
 }
 
 void gather_symbols(const int32_t* src, int compact, const int* pos, int M, int C,
-                    int32_t* ydec, hipStream_t s) {
-  if (M <= 0) return;
+                    int32_t* ydec, hipStream_t s, int c0, int nc) {
+  if (nc < 0) nc = C;
+  if (M <= 0 || nc <= 0) return;
   const int ev = prof_begin(s);
-  hipLaunchKernelGGL(k_gather_symbols, dim3(blocks_for((long)M * C, 256)), dim3(256), 0, s, src,
-                     compact, pos, M, C, ydec);
-  prof_end(ev, s, R_GATHER, 8.0 * M * C + 4.0 * M, 0.0);
+  hipLaunchKernelGGL(k_gather_symbols, dim3(blocks_for((long)M * nc, 256)), dim3(256), 0, s, src,
+                     compact, pos, M, C, ydec, c0, nc);
+  prof_end(ev, s, R_GATHER, 8.0 * M * nc + 4.0 * M, 0.0);
+}
+
+void group_rmsnorm(const float* X, int ldx, int M, int K, int col0, const float* gain, float* Y,
+                   int ldy, hipStream_t s) {
+  if (M <= 0) return;
+  hipLaunchKernelGGL(k_group_rms, dim3((M + 3) / 4), dim3(256), 0, s, X, ldx, M, K, col0, gain, Y,
+                     ldy);
 }
 
 void symbol_bits(const int* pos, int M, int C, const int32_t* ydec, const float* mean,

@@ -34,6 +34,22 @@ struct LayerWeights {
   QW qkv, o, gate, up, down;
 };
 
+// Channel Transformer (models with channel groups): FP32 weights in the
+// blob, plus per-group compacted copies of the masked maps made at upload:
+// wy_g[g] = the shifted latent input rows of group g, [dg][g * Cg] (latent
+// groups 0 .. g-1; null for g = 0), m_g[b][g] = block b's mixing rows of
+// group g, [dg][(g + 1) * dg].
+constexpr int kMaxChGroups = 8;
+constexpr int kMaxChBlocks = 4;
+struct CtWeights {
+  const float *gx, *Wx, *gy, *Wy;
+  const float *g1[kMaxChBlocks], *M[kMaxChBlocks], *g2[kMaxChBlocks];
+  const float *Wgate[kMaxChBlocks], *Wup[kMaxChBlocks], *Wdown[kMaxChBlocks];
+  const float *hg, *W1, *W2;
+  const float* wy_g[kMaxChGroups];
+  const float* m_g[kMaxChBlocks][kMaxChGroups];
+};
+
 struct DevWeights {
   const float *hyperW, *P4, *ing, *inW, *acc_gq, *acc_Wq, *acc_gkv, *acc_Wkv, *knull, *vnull,
       *acc_bias, *acc_Wo;
@@ -42,6 +58,7 @@ struct DevWeights {
   int prec;  // PSWA_PREC_*: arithmetic of every projection below
   QW in, acc_q, acc_kv, acc_o, head1, head2;
   float* calib = nullptr;  // calibration: per-input maxima (FP32 models only)
+  CtWeights ct{};          // channel groups only
 };
 
 // Projection inputs, in calibration-slot order: latent embedding,
@@ -53,6 +70,9 @@ struct NetDims {
   int L, d, heads, dh, r, s, F, C, Ch, n_acc, n_sp, n_tm;
   int cycle;  // 0: wavefront schedule; c: cyclic schedule of c steps
   float ln_smin, ln_smax, inv_delta;
+  // Channel Transformer: groups (0: plain head), width, per-group width,
+  // channels per group, per-group SwiGLU width, blocks
+  int cg, cd, cdg, cCg, cFg, cL;
 };
 
 // Buffers and row maps of one pass.
@@ -70,6 +90,8 @@ struct PassCtx {
   const float* tkv;           // layer 0 temporal K/V [2][HWt][2d] (or null)
   size_t tkv_stride;
   float *x, *q, *att, *e, *t1, *hmid;  // row activations
+  float *ct_c, *ct_u, *ct_h, *ct_t1;   // Channel Transformer rows: stream [M][cd], block
+                                       // inputs [cL][M][cd], SwiGLU [M][cFg], head [M][cdg]
   float *mean, *scale, *bits;          // [HWt][C]
   int32_t* center;
   uint16_t* index;
@@ -216,11 +238,69 @@ __host__ __device__ inline GemmArgs args_head2(const NetDims& x, const DevWeight
   g.X = c.t1; g.ldx = x.d; g.W = w.W2; g.W2 = w.W2 + (size_t)x.C * x.d; g.yrow = c.gpos;
   g.head.gmu = w.gmu; g.head.bmu = w.bmu; g.head.gsig = w.gsig; g.head.bsig = w.bsig;
   g.head.ln_smin = x.ln_smin; g.head.ln_smax = x.ln_smax; g.head.inv_delta = x.inv_delta;
+  g.head.ldo = x.C; g.head.col0 = 0;
   g.head.mean = c.mean; g.head.scale = c.scale; g.head.center = c.center;
   g.head.index = c.index; g.head.center_c = c.center_c; g.head.index_c = c.index_c;
   g.head.flag = c.flag;
   use_q(g, w, w.head2, w.head2, 0, (size_t)x.C * x.d);
   return g;
+}
+
+// ---- Channel Transformer, channel group g (each GEMM on the group's slice
+// of the [M][cd] stream; the rows' positions index ydec)
+__host__ __device__ inline GemmArgs args_ct_in(const NetDims& x, const DevWeights& w,
+                                               const PassCtx& c, int g) {
+  GemmArgs a = gemm_base(c.M, x.cdg, x.d, R_HEAD1);
+  a.X = c.x; a.ldx = x.d; a.gain = w.ct.gx; a.W = w.ct.Wx + (size_t)g * x.cdg * x.d;
+  a.Y = c.ct_c + (size_t)g * x.cdg; a.ldy = x.cd;
+  return a;
+}
+__host__ __device__ inline GemmArgs args_ct_latent(const NetDims& x, const DevWeights& w,
+                                                   const PassCtx& c, int g) {
+  GemmArgs a = gemm_base(c.M, x.cdg, g * x.cCg, R_HEAD1);
+  a.Xi = c.ydec; a.ldx = x.C; a.xrow = c.gpos; a.xscale = w.ct.gy; a.W = w.ct.wy_g[g];
+  a.R = c.ct_c + (size_t)g * x.cdg; a.ldr = x.cd; a.Y = c.ct_c + (size_t)g * x.cdg; a.ldy = x.cd;
+  return a;
+}
+__host__ __device__ inline GemmArgs args_ct_mix(const NetDims& x, const DevWeights& w,
+                                                const PassCtx& c, int b, int g) {
+  GemmArgs a = gemm_base(c.M, x.cdg, (g + 1) * x.cdg, R_HEAD1);
+  a.X = c.ct_u + (size_t)b * c.M * x.cd; a.ldx = x.cd; a.W = w.ct.m_g[b][g];
+  a.R = c.ct_c + (size_t)g * x.cdg; a.ldr = x.cd; a.Y = c.ct_c + (size_t)g * x.cdg; a.ldy = x.cd;
+  return a;
+}
+__host__ __device__ inline GemmArgs args_ct_gateup(const NetDims& x, const DevWeights& w,
+                                                   const PassCtx& c, int b, int g) {
+  GemmArgs a = gemm_base(c.M, x.cFg, x.cdg, R_HEAD1);
+  a.X = c.ct_c + (size_t)g * x.cdg; a.ldx = x.cd; a.gain = w.ct.g2[b] + (size_t)g * x.cdg;
+  a.W = w.ct.Wgate[b] + (size_t)g * x.cFg * x.cdg; a.W2 = w.ct.Wup[b] + (size_t)g * x.cFg * x.cdg;
+  a.Y = c.ct_h; a.ldy = x.cFg;
+  return a;
+}
+__host__ __device__ inline GemmArgs args_ct_down(const NetDims& x, const DevWeights& w,
+                                                 const PassCtx& c, int b, int g) {
+  GemmArgs a = gemm_base(c.M, x.cdg, x.cFg, R_HEAD1);
+  a.X = c.ct_h; a.ldx = x.cFg; a.W = w.ct.Wdown[b] + (size_t)g * x.cdg * x.cFg;
+  a.R = c.ct_c + (size_t)g * x.cdg; a.ldr = x.cd; a.Y = c.ct_c + (size_t)g * x.cdg; a.ldy = x.cd;
+  return a;
+}
+__host__ __device__ inline GemmArgs args_ct_head1(const NetDims& x, const DevWeights& w,
+                                                  const PassCtx& c, int g) {
+  GemmArgs a = gemm_base(c.M, x.cdg, x.cdg, R_HEAD1);
+  a.X = c.ct_c + (size_t)g * x.cdg; a.ldx = x.cd; a.gain = w.ct.hg + (size_t)g * x.cdg;
+  a.W = w.ct.W1 + (size_t)g * x.cdg * x.cdg; a.Y = c.ct_t1; a.ldy = x.cdg;
+  return a;
+}
+__host__ __device__ inline GemmArgs args_ct_head2(const NetDims& x, const DevWeights& w,
+                                                  const PassCtx& c, int g) {
+  GemmArgs a = args_head2(x, w, c);
+  const float* W2g = w.ct.W2 + (size_t)g * 2 * x.cCg * x.cdg;
+  a.N = x.cCg; a.K = x.cdg;
+  a.X = c.ct_t1; a.ldx = x.cdg; a.W = W2g; a.W2 = W2g + (size_t)x.cCg * x.cdg;
+  a.prec = 0; a.Wq = nullptr; a.W2q = nullptr; a.wscale = a.w2scale = 1.f; a.ascale = 0.f;
+  a.amax = nullptr;
+  a.head.col0 = g * x.cCg;
+  return a;
 }
 
 // ---- embedding of decoded symbols (rows read from ydec at their positions)

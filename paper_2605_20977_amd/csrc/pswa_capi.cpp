@@ -61,6 +61,13 @@ Acts take_acts(Layout& L, const NetDims& x, size_t rows) {
   a.e = L.take<float>(rows * x.d);
   a.t1 = L.take<float>(rows * x.d);
   a.hmid = L.take<float>(rows * x.F);
+  a.ct_c = a.ct_u = a.ct_h = a.ct_t1 = nullptr;
+  if (x.cg) {
+    a.ct_c = L.take<float>(rows * x.cd);
+    a.ct_u = L.take<float>((size_t)x.cL * rows * x.cd);
+    a.ct_h = L.take<float>(rows * x.cFg);
+    a.ct_t1 = L.take<float>(rows * x.cdg);
+  }
   return a;
 }
 
@@ -132,6 +139,19 @@ bool valid_desc(const pswa_model_desc* d, std::string* why) {
   if (d->act_scaling != PSWA_ACT_TENSOR &&
       !(d->prec == PSWA_FP8_E4M3 && d->act_scaling == PSWA_ACT_ROW))
     return *why = "act_scaling must be PSWA_ACT_TENSOR, or PSWA_ACT_ROW for FP8 models", false;
+  if (d->ch_groups == 0) {
+    if (d->ch_d != 0 || d->ch_L != 0)
+      return *why = "ch_d and ch_L must be 0 without channel groups", false;
+  } else {
+    const int N = d->ch_groups;
+    if (N < 1 || N > kMaxChGroups) return *why = "ch_groups must be in [1, 8]", false;
+    if (d->C % N != 0 || (d->C / N) % 4 != 0)
+      return *why = "C / ch_groups must be a multiple of 4", false;
+    if (d->ch_d % N != 0 || d->ch_d / N < 16 || d->ch_d / N > 512 || (d->ch_d / N) % 16 != 0)
+      return *why = "ch_d / ch_groups must be a multiple of 16 in [16, 512]", false;
+    if (d->ch_L < 1 || d->ch_L > kMaxChBlocks) return *why = "ch_L must be in [1, 4]", false;
+    if (d->ch_ratio < 1 || d->ch_ratio > 4) return *why = "ch_ratio must be in [1, 4]", false;
+  }
   return true;
 }
 
@@ -159,6 +179,14 @@ NetDims dims_of(const pswa_model_desc& m) {
   x.ln_smin = ln_sigma_min_f32();
   x.ln_smax = float(std::log(kSigmaMax));
   x.inv_delta = inv_delta_f32();
+  x.cg = m.ch_groups;
+  if (x.cg) {
+    x.cd = m.ch_d;
+    x.cdg = m.ch_d / m.ch_groups;
+    x.cCg = m.C / m.ch_groups;
+    x.cFg = m.ch_ratio * x.cdg;
+    x.cL = m.ch_L;
+  }
   return x;
 }
 
@@ -200,9 +228,30 @@ size_t blob_layout(const NetDims& x, const float* base, DevWeights* w, size_t al
     L.Wup = t(F * d);
     L.Wdown = t(d * F);
   }
-  W.head_g = t(d);
-  W.W1 = t(d * d);
-  W.W2 = t(2 * C * d);
+  if (x.cg) {  // Channel Transformer in place of the plain head
+    const size_t N = x.cg, dc = x.cd, dg = x.cdg, Cg = x.cCg, Fg = x.cFg;
+    CtWeights& T = W.ct;
+    T.gx = t(d);
+    T.Wx = t(dc * d);
+    T.gy = t(C);
+    T.Wy = t(dc * C);
+    for (int b = 0; b < x.cL; ++b) {
+      T.g1[b] = t(dc);
+      T.M[b] = t(dc * dc);
+      T.g2[b] = t(dc);
+      T.Wgate[b] = t(N * Fg * dg);
+      T.Wup[b] = t(N * Fg * dg);
+      T.Wdown[b] = t(N * dg * Fg);
+    }
+    T.hg = t(dc);
+    T.W1 = t(N * dg * dg);
+    T.W2 = t(N * 2 * Cg * dg);
+    W.head_g = W.W1 = W.W2 = nullptr;
+  } else {
+    W.head_g = t(d);
+    W.W1 = t(d * d);
+    W.W2 = t(2 * C * d);
+  }
   W.gmu = t(C);
   W.bmu = t(C);
   W.gsig = t(C);
@@ -247,8 +296,10 @@ std::vector<QuantTarget> quant_targets(DevWeights& w, const NetDims& x) {
     t.push_back({18 + 8 * l, &Ly.up, x.d});
     t.push_back({19 + 8 * l, &Ly.down, x.F});
   }
-  t.push_back({13 + 8 * x.L, &w.head1, x.d});
-  t.push_back({14 + 8 * x.L, &w.head2, x.d});
+  if (!x.cg) {  // (the Channel Transformer runs in FP32)
+    t.push_back({13 + 8 * x.L, &w.head1, x.d});
+    t.push_back({14 + 8 * x.L, &w.head2, x.d});
+  }
   return t;
 }
 
@@ -430,18 +481,37 @@ int pswa_act_points(const pswa_model_desc* desc) {
 
 // Device layout: the FP32 weights (each tensor 256-byte aligned), then for
 // BF16 / FP8 models a low-precision copy of every projection weight.
-size_t device_layout(const pswa_model_desc& desc, std::vector<std::pair<int, size_t>>* qoff) {
+// Per-group compacted copies of the Channel Transformer's masked maps (FP32),
+// placed from byte `at`: wy[g] ([dg][g Cg], g >= 1) and m[b * N + g]
+// ([dg][(g + 1) dg]). Returns the end.
+size_t ct_layout(const NetDims& x, size_t at, std::vector<size_t>* wy, std::vector<size_t>* m) {
+  if (!x.cg) return at;
+  for (int g = 0; g < x.cg; ++g) {
+    if (wy) wy->push_back(at);
+    at += align_up((size_t)x.cdg * g * x.cCg * sizeof(float));
+  }
+  for (int b = 0; b < x.cL; ++b)
+    for (int g = 0; g < x.cg; ++g) {
+      if (m) m->push_back(at);
+      at += align_up((size_t)x.cdg * (g + 1) * x.cdg * sizeof(float));
+    }
+  return at;
+}
+
+size_t device_layout(const pswa_model_desc& desc, std::vector<std::pair<int, size_t>>* qoff,
+                     std::vector<size_t>* ct_wy = nullptr, std::vector<size_t>* ct_m = nullptr) {
   const NetDims x = dims_of(desc);
   std::vector<std::pair<size_t, size_t>> spans;
   size_t bytes = align_up(blob_layout(x, nullptr, nullptr, kTensorAlign, &spans) * sizeof(float));
-  if (desc.prec == PSWA_FP32) return bytes;
-  const size_t eb = desc.prec == PSWA_BF16 ? 2 : 1;
-  DevWeights tmp{};
-  for (auto& t : quant_targets(tmp, x)) {
-    if (qoff) qoff->push_back({t.tensor, bytes});
-    bytes += align_up(spans[t.tensor].second * eb);
+  if (desc.prec != PSWA_FP32) {
+    const size_t eb = desc.prec == PSWA_BF16 ? 2 : 1;
+    DevWeights tmp{};
+    for (auto& t : quant_targets(tmp, x)) {
+      if (qoff) qoff->push_back({t.tensor, bytes});
+      bytes += align_up(spans[t.tensor].second * eb);
+    }
   }
-  return bytes;
+  return ct_layout(x, bytes, ct_wy, ct_m);
 }
 
 size_t pswa_model_device_bytes(const pswa_model_desc* desc) {
@@ -536,6 +606,41 @@ pswa_status pswa_model_create(const pswa_model_desc* desc, const float* h_blob,
       staging.push_back(std::move(q));
     }
   }
+  if (x.cg) {  // compacted per-group copies of the masked maps
+    std::vector<size_t> wy_off, m_off;
+    device_layout(*desc, nullptr, &wy_off, &m_off);
+    const size_t base = 12 + 8 * (size_t)x.L;  // first Channel Transformer tensor
+    const float* Wy = h_blob + src[base + 3].first;
+    const size_t dg = x.cdg, Cg = x.cCg, C = x.C, dc = x.cd;
+    // (each host copy lives in `staging` until the uploads are waited for)
+    auto host_copy = [&](size_t floats) {
+      staging.emplace_back(floats * sizeof(float));
+      return reinterpret_cast<float*>(staging.back().data());
+    };
+    for (int g = 1; g < x.cg; ++g) {
+      // rows of group g over latent groups 0 .. g-1: latent column c sits
+      // at column c + Cg of the shifted input
+      const size_t n = dg * g * Cg;
+      float* q = host_copy(n);
+      for (size_t r = 0; r < dg; ++r)
+        for (size_t c = 0; c < g * Cg; ++c) q[r * g * Cg + c] = Wy[(g * dg + r) * C + c + Cg];
+      char* dst = static_cast<char*>(d_mem) + wy_off[g];
+      PSWA_HIP_TRY(hipMemcpyAsync(dst, q, n * sizeof(float), hipMemcpyHostToDevice, st));
+      m->w.ct.wy_g[g] = reinterpret_cast<const float*>(dst);
+    }
+    for (int b = 0; b < x.cL; ++b) {
+      const float* Mb = h_blob + src[base + 5 + 6 * b].first;
+      for (int g = 0; g < x.cg; ++g) {
+        const size_t k = (g + 1) * dg;
+        float* q = host_copy(dg * k);
+        for (size_t r = 0; r < dg; ++r)
+          for (size_t c = 0; c < k; ++c) q[r * k + c] = Mb[(g * dg + r) * dc + c];
+        char* dst = static_cast<char*>(d_mem) + m_off[b * x.cg + g];
+        PSWA_HIP_TRY(hipMemcpyAsync(dst, q, dg * k * sizeof(float), hipMemcpyHostToDevice, st));
+        m->w.ct.m_g[b][g] = reinterpret_cast<const float*>(dst);
+      }
+    }
+  }
   PSWA_HIP_TRY(hipStreamSynchronize(st));
   *out = m.release();
   return PSWA_OK;
@@ -605,6 +710,7 @@ pswa_status encode_impl(const pswa_model* model, const pswa_frame_desc* frame,
   c.tkv = frame->n_prev ? ws.tkv : nullptr;
   c.tkv_stride = 0;
   c.x = ws.a.x; c.q = ws.a.q; c.att = ws.a.att; c.e = ws.a.e; c.t1 = ws.a.t1; c.hmid = ws.a.hmid;
+  c.ct_c = ws.a.ct_c; c.ct_u = ws.a.ct_u; c.ct_h = ws.a.ct_h; c.ct_t1 = ws.a.ct_t1;
   c.mean = d_mean; c.scale = d_scale; c.bits = d_bits; c.center = d_cdf_center;
   c.index = d_cdf_index; c.flag = ws.flag;
   c.ydec = const_cast<int32_t*>(d_latents);  // only read: the encoder knows every symbol
@@ -616,7 +722,7 @@ pswa_status encode_impl(const pswa_model* model, const pswa_frame_desc* frame,
       [&](int l) {
         if (pf) temporal_kv_layer(model, HW, HW, 0, ws.e_prev, l, ws.tkv, st);
       },
-      st);
+      [](int) {}, st);
   symbol_bits(nullptr, HW, x.C, d_latents, d_mean, d_scale, d_bits, st);
   PSWA_HIP_TRY(hipGetLastError());
   if (h_total_bits)
@@ -718,6 +824,9 @@ pswa_status pswa_decode_begin(const pswa_model* model, const pswa_frame_desc* fr
   if (!d_hyper || !src || !d_state_mem) return fail(PSWA_E_ARG, "null pointer argument");
   if (symbol_source != PSWA_SRC_DEVICE && symbol_source != PSWA_SRC_BITSTREAM)
     return fail(PSWA_E_ARG, "unknown symbol source %d", symbol_source);
+  if (symbol_source == PSWA_SRC_BITSTREAM && model->x.cg)
+    return fail(PSWA_E_UNSUPPORTED,
+                "bitstream decoding of models with channel groups is not built (device source only)");
   if (frame->n_prev == 2 && !d_prev) return fail(PSWA_E_ARG, "P-frame needs d_prev");
   if (frame->n_prev == 0 && d_prev) return fail(PSWA_E_ARG, "I-frame must pass d_prev = NULL");
   if ((reinterpret_cast<uintptr_t>(d_state_mem) % kAlign) != 0)
@@ -792,14 +901,25 @@ pswa_status pswa_decode_step(pswa_state* S, int t, void* stream) {
   c.tkv = S->tkv;
   c.tkv_stride = (size_t)2 * HW * 2 * x.d;
   c.x = S->a.x; c.q = S->a.q; c.att = S->a.att; c.e = S->a.e; c.t1 = S->a.t1; c.hmid = S->a.hmid;
+  c.ct_c = S->a.ct_c; c.ct_u = S->a.ct_u; c.ct_h = S->a.ct_h; c.ct_t1 = S->a.ct_t1;
   c.mean = S->mean; c.scale = S->scale; c.bits = S->bits; c.center = S->center;
   c.index = S->index; c.flag = S->flag;
   c.center_c = bs ? S->cc : nullptr;
   c.index_c = bs ? S->ci : nullptr;
   c.ydec = S->ydec;
-  run_pass(m, c, [](int) {}, st);
+  if (x.cg) {
+    // channel groups one after the other, each group's symbols read before
+    // the next group is predicted (device symbol source)
+    run_pass(m, c, [](int) {},
+             [&](int g) { gather_symbols(S->d_src, 0, pos, n, x.C, S->ydec, st, g * x.cCg, x.cCg); },
+             st);
+  } else {
+    run_pass(m, c, [](int) {}, [](int) {}, st);
+  }
 
-  if (!bs) {
+  if (x.cg) {
+    // (symbols already gathered group by group)
+  } else if (!bs) {
     gather_symbols(S->d_src, 0, pos, n, x.C, S->ydec, st);
   } else {
     const size_t cnt = (size_t)n * x.C;

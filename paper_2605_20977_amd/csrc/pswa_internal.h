@@ -41,7 +41,9 @@ enum Epi {
 struct HeadOut {
   const float *gmu, *bmu, *gsig, *bsig;  // [C]
   float ln_smin, ln_smax, inv_delta;
-  float *mean, *scale;                   // [HW][C] rows yrow(m)
+  int ldo, col0;                         // output (row, n) at yrow(row) * ldo + col0 + n
+                                         // (the column also indexes gmu .. bsig)
+  float *mean, *scale;                   // [HW][ldo] rows yrow(m)
   int32_t* center;                       // [HW][C]
   uint16_t* index;                       // [HW][C]
   int32_t* center_c;                     // compact [M][C] copies (or null)
@@ -139,9 +141,13 @@ double attn_alg_bytes(const AttnArgs& a);
 // ----------------------------------------------------------------- misc
 void hyper_embed(const int32_t* z, int Hh, int Wh, int Ch, const float* Wh_, const float* P4,
                  int H, int W, int d, float* h, hipStream_t s);
-// ydec[pos(m)][c] = src[(compact ? m : pos(m))][c]
+// ydec[pos(m)][c] = src[(compact ? m : pos(m))][c] for c in [c0, c0 + nc)
 void gather_symbols(const int32_t* src, int compact, const int* pos, int M, int C,
-                    int32_t* ydec, hipStream_t s);
+                    int32_t* ydec, hipStream_t s, int c0 = 0, int nc = -1);
+// Y[m][col0 + k] = RMSNorm of X[m][col0 .. col0 + K) times gain[col0 + k]
+// (one channel group's slice normalized on its own), rows m < M
+void group_rmsnorm(const float* X, int ldx, int M, int K, int col0, const float* gain, float* Y,
+                   int ldy, hipStream_t s);
 // bits[pos(m)][c] = -log2(max(P, 1e-9)) of ydec under N(mean, scale)
 void symbol_bits(const int* pos, int M, int C, const int32_t* ydec, const float* mean,
                  const float* scale, float* bits, hipStream_t s);

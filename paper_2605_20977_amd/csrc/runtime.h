@@ -75,17 +75,42 @@ inline int sched_len(const NetDims& x, int H, int W, int t) {
   return n;
 }
 
-// Row activations for `rows` rows.
+// Row activations for `rows` rows (and the Channel Transformer's, if any).
 struct Acts {
   float *x, *q, *att, *e, *t1, *hmid;
+  float *ct_c, *ct_u, *ct_h, *ct_t1;
 };
 Acts take_acts(Layout& L, const NetDims& x, size_t rows);
 
+// Channel group g of the Channel Transformer over c's rows: its input
+// (spatial output, and the latent's groups 0 .. g-1 read from c.ydec at the
+// rows' positions), the blocks (per-group RMSNorm, masked mixing over groups
+// 0 .. g, per-group SwiGLU) and the group's head (mean, scale and CDF
+// selection of its channels).
+inline void run_ct_group(const pswa_model* m, const PassCtx& c, int g, hipStream_t st) {
+  const NetDims& x = m->x;
+  const DevWeights& w = m->w;
+  gemm_run(A_FLOAT, true, EPI_STORE, args_ct_in(x, w, c, g), st);
+  if (g > 0) gemm_run(A_INT, false, EPI_RESID, args_ct_latent(x, w, c, g), st);
+  for (int b = 0; b < x.cL; ++b) {
+    group_rmsnorm(c.ct_c, x.cd, c.M, x.cdg, g * x.cdg, w.ct.g1[b], c.ct_u + (size_t)b * c.M * x.cd,
+                  x.cd, st);
+    gemm_run(A_FLOAT, false, EPI_RESID, args_ct_mix(x, w, c, b, g), st);
+    gemm_run(A_FLOAT, true, EPI_SWIGLU, args_ct_gateup(x, w, c, b, g), st);
+    gemm_run(A_FLOAT, false, EPI_RESID, args_ct_down(x, w, c, b, g), st);
+  }
+  gemm_run(A_FLOAT, true, EPI_SILU, args_ct_head1(x, w, c, g), st);
+  gemm_run(A_FLOAT, false, EPI_HEAD, args_ct_head2(x, w, c, g), st);
+}
+
 // One pass of the network over c's rows with per-phase launches.
 // before_layer(l) runs before layer l's QKV (the encode form builds the
-// layer's temporal K/V there).
-template <class BeforeLayer>
-void run_pass(const pswa_model* m, const PassCtx& c, BeforeLayer before_layer, hipStream_t st) {
+// layer's temporal K/V there); after_group(g) runs after channel group g's
+// prediction (a decoder reads the group's symbols there; models without
+// channel groups call it once, g = 0).
+template <class BeforeLayer, class AfterGroup>
+void run_pass(const pswa_model* m, const PassCtx& c, BeforeLayer before_layer,
+              AfterGroup after_group, hipStream_t st) {
   const NetDims& x = m->x;
   const DevWeights& w = m->w;
   gemm_run(A_FLOAT, true, EPI_STORE, args_acc_q(x, w, c), st);
@@ -99,8 +124,16 @@ void run_pass(const pswa_model* m, const PassCtx& c, BeforeLayer before_layer, h
     gemm_run(A_FLOAT, true, EPI_SWIGLU, args_gateup(x, w, c, l), st);
     gemm_run(A_FLOAT, false, EPI_RESID, args_down(x, w, c, l), st);
   }
+  if (x.cg) {
+    for (int g = 0; g < x.cg; ++g) {
+      run_ct_group(m, c, g, st);
+      after_group(g);
+    }
+    return;
+  }
   gemm_run(A_FLOAT, true, EPI_SILU, args_head1(x, w, c), st);
   gemm_run(A_FLOAT, false, EPI_HEAD, args_head2(x, w, c), st);
+  after_group(0);
 }
 
 // Embedding of decoded symbols (read from c.ydec at the rows' positions) and

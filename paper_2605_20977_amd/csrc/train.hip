@@ -797,7 +797,8 @@ extern "C" {
 
 size_t pswa_train_workspace_bytes(const pswa_model_desc* student, int max_crops, int H, int W) {
   std::string why;
-  if (!model_desc_valid(student, &why) || student->prec != PSWA_FP32 || student->cycle != 0)
+  if (!model_desc_valid(student, &why) || student->prec != PSWA_FP32 || student->cycle != 0 ||
+      student->ch_groups != 0)
     return 0;
   if (max_crops < 1 || H < 1 || W < 1 || (long)max_crops * H * W > (1L << 22)) return 0;
   pswa_trainer t;
@@ -825,6 +826,8 @@ pswa_status pswa_train_create(const pswa_model_desc* student, const float* h_blo
   if (student->prec != PSWA_FP32) return fail(PSWA_E_UNSUPPORTED, "training runs in FP32");
   if (student->cycle != 0)
     return fail(PSWA_E_UNSUPPORTED, "training supports the wavefront schedule only");
+  if (student->ch_groups != 0)
+    return fail(PSWA_E_UNSUPPORTED, "training supports models without channel groups only");
   const size_t need_ws = pswa_train_workspace_bytes(student, max_crops, H, W);
   if (need_ws == 0) return fail(PSWA_E_SHAPE, "invalid crop shape or count");
   if (!h_blob || !d_ws || (reinterpret_cast<uintptr_t>(d_ws) % kAlign) != 0)

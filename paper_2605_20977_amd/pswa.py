@@ -36,7 +36,7 @@ class PswaError(RuntimeError):
 class ModelDesc(C.Structure):
     _fields_ = [(n, C.c_int32) for n in
                 ("L", "d", "heads", "window", "mlp_ratio", "C", "Ch", "prec", "cycle",
-                 "act_scaling")]
+                 "act_scaling", "ch_groups", "ch_d", "ch_L", "ch_ratio")]
 
 
 class FrameDesc(C.Structure):
@@ -173,9 +173,11 @@ def _stream():
 # ------------------------------------------------------------------ shapes
 
 def model_desc(cfg, prec="fp32", act="tensor") -> ModelDesc:
+    cg = getattr(cfg, "ch_groups", 0)
     return ModelDesc(cfg.L, cfg.d, cfg.heads, cfg.window, cfg.mlp_ratio, cfg.C, cfg.Ch,
                      PRECISIONS[prec] if isinstance(prec, str) else int(prec),
-                     getattr(cfg, "cycle", 0), ACT_SCALING[act])
+                     getattr(cfg, "cycle", 0), ACT_SCALING[act], cg,
+                     cfg.ch_d if cg else 0, cfg.ch_L if cg else 0, cfg.ch_ratio if cg else 0)
 
 
 def frame_desc(H, W, n_prev=0) -> FrameDesc:
@@ -201,8 +203,21 @@ def blob_shapes(cfg) -> list[tuple[str, tuple]]:
         out += [(p + "g1", (d,)), (p + "Wqkv", (3 * d, d)), (p + "bias", (h, n_lay)),
                 (p + "Wo", (d, d)), (p + "g2", (d,)), (p + "Wgate", (F, d)),
                 (p + "Wup", (F, d)), (p + "Wdown", (d, F))]
-    out += [("head.g", (d,)), ("head.W1", (d, d)), ("head.W2", (2 * C, d)),
-            ("head.gmu", (C,)), ("head.bmu", (C,)), ("head.gsig", (C,)), ("head.bsig", (C,))]
+    N = getattr(cfg, "ch_groups", 0)
+    if N:  # Channel Transformer and grouped heads in place of the plain head
+        dc = cfg.ch_d
+        dg, Cg = dc // N, C // N
+        Fg = cfg.ch_ratio * dg
+        out += [("ct.gx", (d,)), ("ct.Wx", (dc, d)), ("ct.gy", (C,)), ("ct.Wy", (dc, C))]
+        for b in range(cfg.ch_L):
+            p = f"ct{b}."
+            out += [(p + "g1", (dc,)), (p + "M", (dc, dc)), (p + "g2", (dc,)),
+                    (p + "Wgate", (N, Fg, dg)), (p + "Wup", (N, Fg, dg)),
+                    (p + "Wdown", (N, dg, Fg))]
+        out += [("ctH.g", (dc,)), ("ctH.W1", (N, dg, dg)), ("ctH.W2", (N, 2 * Cg, dg))]
+    else:
+        out += [("head.g", (d,)), ("head.W1", (d, d)), ("head.W2", (2 * C, d))]
+    out += [("head.gmu", (C,)), ("head.bmu", (C,)), ("head.gsig", (C,)), ("head.bsig", (C,))]
     return out
 
 

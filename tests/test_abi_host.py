@@ -31,7 +31,8 @@ def test_every_declared_symbol_is_exported():
     assert set(names) == set(P.EXPORTED)
 
 
-@pytest.mark.parametrize("cfg", [synth.TINY, synth.FULL, synth.STUDENT])
+@pytest.mark.parametrize("cfg", [synth.TINY, synth.FULL, synth.STUDENT, synth.TINY_CT,
+                                 synth.FULL_CT])
 def test_blob_size_matches_weight_shapes(cfg):
     d = P.model_desc(cfg)
     n = P.lib().pswa_model_blob_floats(C.byref(d))
@@ -223,3 +224,21 @@ def test_fp8_activation_scaling_descs():
         assert b"activation maximum 3" in lib.pswa_last_error()
     with pytest.raises(P.PswaError):
         P.Model(cfg, synth.model_weights(cfg, 1), "fp8", device="cpu")  # no maxima given
+
+
+def test_channel_group_descs_validated():
+    lib = P.lib()
+    good = P.model_desc(synth.TINY_CT)
+    assert lib.pswa_model_blob_floats(C.byref(good)) > 0
+    base = dict(L=2, d=64, heads=4, window=5, mlp_ratio=4, C=32, Ch=16, prec=0, cycle=0,
+                act_scaling=0, ch_groups=4, ch_d=64, ch_L=2, ch_ratio=2)
+    bad = [dict(ch_groups=9), dict(ch_groups=3), dict(ch_d=60), dict(ch_d=4 * 528),
+           dict(ch_L=0), dict(ch_L=5), dict(ch_ratio=0), dict(ch_ratio=5),
+           dict(ch_groups=0)]   # ch_d / ch_L must then be 0
+    names = ("L", "d", "heads", "window", "mlp_ratio", "C", "Ch", "prec", "cycle", "act_scaling",
+             "ch_groups", "ch_d", "ch_L", "ch_ratio")
+    for b in bad:
+        kw = dict(base)
+        kw.update(b)
+        d = P.ModelDesc(*[kw[k] for k in names])
+        assert lib.pswa_model_blob_floats(C.byref(d)) == 0, b
