@@ -19,6 +19,11 @@ frame); inputs resident in HBM, symbols read from device memory. Paths
                       alternating) decoded by the student and by the full
                       model (the student's speed-up);
   encode:<prec>    -- the parallel encode form of one 1080p I-frame;
+  ctplain:<prec>, ctencode:<prec> -- the plain and encode paths of a model
+                      of the same spatial widths whose head is the Channel
+                      Transformer (4 channel groups of 48 symbols, width 512,
+                      2 blocks) with grouped heads: each diagonal's groups
+                      are predicted one after the other;
   bitstream:<prec> -- one 1080p I-frame decoded step by step from its range-
                       coded bitstream (host range decoder, one thread, in
                       the loop at every diagonal);
@@ -63,7 +68,7 @@ FP32_VECTOR_TFLOPS = 157.3
 METRIC = "decoded latent symbols/sec (1080p-shaped) vs plain FP32, at stated bits overhead"
 DEFAULT_PATHS = ("plain:fp32,batch32:bf16,batch256:bf16,batch32:fp8,mixed32:bf16,student4k:bf16,"
                  "student4k8:bf16,full4k8:bf16,encode:fp32,encode:bf16,bitstream:fp32,"
-                 "cyclic32:bf16")
+                 "cyclic32:bf16,ctplain:fp32,ctencode:fp32")
 BITS_BOUND = {"fp32": None, "bf16": 0.005, "fp8": 0.01}
 # The paper's own runtime comparison (Table 2; no GPU or CPU named).
 PAPER_CONTEXT = {
@@ -115,40 +120,48 @@ def macs_per_position(cfg, n_prev=0):
     k2 = (2 * r + 1) ** 2
     acc = d * d + 2 * d * d + d * d + (n_acc + 1) * 2 * d
     layer = 3 * d * d + d * d + 2 * d * F + F * d + (n_acc + 1) * 2 * d
-    m = cfg.Ch * d + C * d + acc + L * layer
-    N = getattr(cfg, "ch_groups", 0)
-    if N:  # Channel Transformer: input, masked latent input and mixing, MLPs, heads
-        dg, Cg = cfg.ch_d // N, C // N
-        Fg = cfg.ch_ratio * dg
-        m += d * cfg.ch_d + Cg * dg * N * (N - 1) // 2
-        m += cfg.ch_L * (dg * dg * N * (N + 1) // 2 + N * 3 * dg * Fg)
-        m += N * (dg * dg + 2 * Cg * dg)
-    else:
-        m += d * d + 2 * C * d
+    m = cfg.Ch * d + C * d + acc + L * layer + head_macs(cfg)
     if n_prev:
         m += L * (2 * k2 * 2 * d + 2 * d * d) + C * d
     return m
 
 
+def head_macs(cfg):
+    """Multiply-adds (= weights read) of the head of one position: the plain
+    head (W1, W2), or with channel groups the Channel Transformer (input map,
+    the live blocks of the masked latent map and mixing maps, per-group
+    SwiGLUs) and the grouped heads."""
+    d, C = cfg.d, cfg.C
+    N = getattr(cfg, "ch_groups", 0)
+    if not N:
+        return d * d + 2 * C * d
+    dg, Cg = cfg.ch_d // N, C // N
+    Fg = cfg.ch_ratio * dg
+    m = d * cfg.ch_d + Cg * dg * N * (N - 1) // 2
+    m += cfg.ch_L * (dg * dg * N * (N + 1) // 2 + N * 3 * dg * Fg)
+    return m + N * (dg * dg + 2 * Cg * dg)
+
+
 def projection_params(cfg):
     """Weights the projections read at every step (latent embedding,
-    accumulator q/kv/o, per layer QKV/O/gate/up/down, head W1/W2)."""
+    accumulator q/kv/o, per layer QKV/O/gate/up/down, head)."""
     d, C, F, L = cfg.d, cfg.C, cfg.F, cfg.L
-    return C * d + 4 * d * d + L * (4 * d * d + 3 * d * F) + d * d + 2 * C * d
+    return C * d + 4 * d * d + L * (4 * d * d + 3 * d * F) + head_macs(cfg)
 
 
-def resident_bytes(cfg, H, W, n_prev=0):
+def resident_bytes(cfg, H, W, n_prev=0, kvb=4):
     """Bytes of one frame's own data at their algorithmic minimum: latents
-    (and previous latents) and hyperprior read once; hyper tokens,
-    accumulator K/V, layer K/V (and temporal K/V) caches (FP32) written and
-    read once; mean, scale, bits, centre, decoded latent (4 B) and table
-    index (2 B) written once."""
+    (and previous latents) and hyperprior read once; hyper tokens (FP32),
+    accumulator K/V, layer K/V (and temporal K/V) caches (kvb bytes per
+    value: FP32, or BF16 in the reduced-precision forms) written and read
+    once; mean, scale, bits, centre, decoded latent (4 B) and table index
+    (2 B) written once."""
     HW = H * W
     b = 4 * HW * cfg.C + 4 * (-(-H // 4)) * (-(-W // 4)) * cfg.Ch
-    b += 2 * 4 * HW * cfg.d + 2 * 4 * HW * 2 * cfg.d + 2 * 4 * cfg.L * HW * 2 * cfg.d
+    b += 2 * 4 * HW * cfg.d + 2 * kvb * HW * 2 * cfg.d + 2 * kvb * cfg.L * HW * 2 * cfg.d
     b += 22 * HW * cfg.C
     if n_prev:
-        b += 2 * 4 * HW * cfg.C + 2 * 4 * cfg.L * 2 * HW * 2 * cfg.d
+        b += 2 * 4 * HW * cfg.C + 2 * kvb * cfg.L * 2 * HW * 2 * cfg.d
     return b
 
 
@@ -157,7 +170,8 @@ def alg_work(cfg, frames, prec, steps):
     `steps` global steps, weights read once per step."""
     wb = {"fp32": 4, "bf16": 2, "fp8": 1}[prec]
     flops = sum(2.0 * macs_per_position(cfg, npv) * H * W for H, W, npv in frames)
-    byts = steps * wb * projection_params(cfg) + sum(resident_bytes(cfg, H, W, npv)
+    kvb = 4 if prec == "fp32" else 2
+    byts = steps * wb * projection_params(cfg) + sum(resident_bytes(cfg, H, W, npv, kvb)
                                                      for H, W, npv in frames)
     return flops, float(byts)
 
@@ -364,6 +378,8 @@ def main():
             elif kind == "cyclic":
                 mc, mw = synth.CYCLIC, synth.model_weights(
                     synth.CYCLIC, synth.CONFIG_SEEDS["1080p_cyclic"][1])
+            elif kind == "ct":
+                mc, mw = synth.FULL_CT, synth.model_weights(synth.FULL_CT, wseed)
             else:
                 mc, mw = cfg, Wt
             calib = synth.calibration_frames(mc) if prec == "fp8" else None
@@ -374,9 +390,10 @@ def main():
     for spec in args.paths.split(","):
         kind, prec = spec.split(":")
         mkind = ("student" if kind.startswith("student") else
-                 "cyclic" if kind.startswith("cyclic") else "full")
+                 "cyclic" if kind.startswith("cyclic") else
+                 "ct" if kind.startswith("ct") else "full")
         model, mc = model_for(prec, mkind)
-        if kind == "plain":
+        if kind in ("plain", "ctplain"):
             mem = torch.empty(pswa.pswa_state_bytes(model, H, W), dtype=torch.uint8,
                               device="cuda")
 
@@ -391,7 +408,7 @@ def main():
                            "ms_per_step": 1e3 * dt / args.steps,
                            "value": sym_frame * args.steps / dt}
             runners[spec] = plain
-        elif kind == "encode":
+        elif kind in ("encode", "ctencode"):
             ws = torch.empty(pswa.lib().pswa_encode_workspace_bytes(
                 model.handle, pswa.C.byref(pswa.frame_desc(H, W))), dtype=torch.uint8,
                 device="cuda")
@@ -400,7 +417,7 @@ def main():
                 pswa.pswa_encode_params(model, yd, zd, total_bits=False, ws=ws)
             dt = timed(enc, 3 * args.steps, args.warmup)
             sec = dt / (3 * args.steps)
-            fl, by = alg_work(cfg, [(H, W, 0)], prec, 1)
+            fl, by = alg_work(mc, [(H, W, 0)], prec, 1)
             paths[spec] = {"frames": 1, "symbols_per_step": sym_frame, "ms_per_step": 1e3 * sec,
                            "value": sym_frame / sec,
                            "roofline": roofline_of(fl, by, sec, prec)}

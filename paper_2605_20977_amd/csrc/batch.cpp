@@ -89,6 +89,9 @@ struct pswa_batch {
 
 namespace {
 
+// LDS-staged window tiles serve the wavefront schedule of models whose
+// key/value caches are FP32.
+bool staged_ok(const pswa_model* m) { return !m->x.cycle && !m->w.kv16; }
 
 // Frame layout of a batch and the worst-case sizes of any grouping: rows of
 // all groups together (at most the sum of each frame's longest diagonal)
@@ -262,7 +265,7 @@ PersistArgs persist_args(const pswa_batch* b) {
   P.xcd_tab = b->xcd_tab;
   P.xcd_local = b->xcd_local;
   P.cycle = b->model->x.cycle;
-  P.attn_staged = b->attn_staged;
+  P.attn_staged = b->attn_staged && staged_ok(b->model);
   return P;
 }
 
@@ -602,7 +605,7 @@ pswa_status pswa_batch_autotune(pswa_batch* b, const char* cache_path, int reps,
           (r == 16 || r == 32) && (r == 32 || m->w.prec) && (sa == 0 || sa == 1)) {
         const int r_old = b->rtile;
         b->rtile = r;
-        b->attn_staged = x.cycle ? 0 : sa;
+        b->attn_staged = staged_ok(m) ? sa : 0;
         const pswa_status s2 = apply_groups(b, f, g, st);
         if (s2 != PSWA_OK) {  // a stale entry (another device limit): retune
           b->rtile = r_old;
@@ -688,7 +691,7 @@ pswa_status pswa_batch_autotune(pswa_batch* b, const char* cache_path, int reps,
   if (gs != PSWA_OK) return gs;
   // the attention form on the winner (wavefront schedule only)
   int bs = b->attn_staged;
-  if (!x.cycle) {
+  if (staged_ok(b->model)) {
     for (int sa : {0, 1}) {
       if (sa == bs) continue;
       const int keep = b->attn_staged;
@@ -781,8 +784,9 @@ pswa_status pswa_batch_set_xcd_barrier(pswa_batch* b, int on) {
 
 pswa_status pswa_batch_set_attention(pswa_batch* b, int staged) {
   if (!b) return fail(PSWA_E_ARG, "batch is null");
-  if (staged && b->model->x.cycle)
-    return fail(PSWA_E_UNSUPPORTED, "LDS-staged window tiles serve the wavefront schedule");
+  if (staged && !staged_ok(b->model))
+    return fail(PSWA_E_UNSUPPORTED,
+                "LDS-staged window tiles serve the wavefront schedule with FP32 key/value caches");
   b->attn_staged = staged ? 1 : 0;
   drop_graph(b);
   return PSWA_OK;

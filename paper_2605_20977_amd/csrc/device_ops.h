@@ -51,6 +51,16 @@ __device__ __forceinline__ void stg(T* p, T v) {
 __device__ __forceinline__ float4 ldg4(const float* p) {
   return ldg(reinterpret_cast<const float4*>(p));
 }
+
+// FP32 -> BF16, round to nearest even (finite inputs).
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+// Two BF16 values packed in a word (element 2j in the low half) -> floats.
+__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
 __device__ __forceinline__ int4 ldg4(const int32_t* p) {
   return ldg(reinterpret_cast<const int4*>(p));
 }
@@ -180,15 +190,20 @@ __device__ __forceinline__ float symbol_bits_of(int32_t y, float mean, float sca
 template <int EPI>
 __device__ __forceinline__ void epilogue(const GemmArgs& a, int row, int n, float v, float v2) {
   if (EPI == EPI_STORE) {
-    stg(a.Y + (size_t)map_row(a.yrow, row) * a.ldy + n, v);
+    const size_t o = (size_t)map_row(a.yrow, row) * a.ldy + n;
+    if (a.kv16) stg(reinterpret_cast<uint16_t*>(a.Y) + o, bf16_rne(v));
+    else stg(a.Y + o, v);
   } else if (EPI == EPI_RESID) {
     const float r = ldg(a.R + (size_t)map_row(a.rrow, row) * a.ldr + n);
     stg(a.Y + (size_t)map_row(a.yrow, row) * a.ldy + n, r + v);
   } else if (EPI == EPI_QKV) {
-    if (n < a.nsplit)
+    if (n < a.nsplit) {
       stg(a.Y + (size_t)row * a.ldy + n, v);
-    else
-      stg(a.Y2 + (size_t)map_row(a.y2row, row) * a.ldy2 + (n - a.nsplit), v);
+    } else {
+      const size_t o = (size_t)map_row(a.y2row, row) * a.ldy2 + (n - a.nsplit);
+      if (a.kv16) stg(reinterpret_cast<uint16_t*>(a.Y2) + o, bf16_rne(v));
+      else stg(a.Y2 + o, v);
+    }
   } else if (EPI == EPI_SILU) {
     stg(a.Y + (size_t)map_row(a.yrow, row) * a.ldy + n, silu(v));
   } else if (EPI == EPI_SWIGLU) {
@@ -538,18 +553,43 @@ __device__ __forceinline__ int attn_n_sp(const AttnArgs& a) {
 }
 
 // Temporal slot t (previous frame tau = t / k1^2 + 1, window in raster
-// order) of a query at (pi, pj): K/V row pointer and bias, false outside the
-// frame.
+// order) of a query at (pi, pj): element offset of its K row in a.tkv and
+// its bias, false outside the frame.
 __device__ __forceinline__ bool temporal_key(const AttnArgs& a, int hd, int dh, int pi, int pj,
                                              const FrameInfo& fi, int n_sp, int t,
-                                             const float*& kp, float& b) {
+                                             size_t& e, float& b) {
   const int r = a.r, k1 = 2 * r + 1;
   const int tau = t / (k1 * k1), rem = t % (k1 * k1);
   const int ki = pi + rem / k1 - r, kj = pj + rem % k1 - r;
   if (ki < 0 || ki >= fi.H || kj < 0 || kj >= fi.W) return false;
-  kp = a.tkv + ((size_t)tau * a.HWt + (size_t)(fi.off + ki * fi.W + kj)) * 2 * a.d + hd * dh;
+  e = ((size_t)tau * a.HWt + (size_t)(fi.off + ki * fi.W + kj)) * 2 * a.d + hd * dh;
   b = ldg(a.bias + hd * a.nbias + n_sp + t);
   return true;
+}
+
+// K and V rows (DH values each, V d elements after K) of a K/V cache at
+// element offset e, as floats: FP32 rows, or BF16 rows (kv16) widened.
+template <int DH>
+__device__ __forceinline__ void load_kv(const float* base, size_t e, int d, int kv16, float4* kr,
+                                        float4* vr) {
+  if (kv16) {
+    const uint16_t* p = reinterpret_cast<const uint16_t*>(base) + e;
+#pragma unroll
+    for (int c = 0; c < DH / 8; ++c) {
+      const int4 k8 = ldg(reinterpret_cast<const int4*>(p) + c);
+      const int4 v8 = ldg(reinterpret_cast<const int4*>(p + d) + c);
+      kr[2 * c] = make_float4(bf16_lo(k8.x), bf16_hi(k8.x), bf16_lo(k8.y), bf16_hi(k8.y));
+      kr[2 * c + 1] = make_float4(bf16_lo(k8.z), bf16_hi(k8.z), bf16_lo(k8.w), bf16_hi(k8.w));
+      vr[2 * c] = make_float4(bf16_lo(v8.x), bf16_hi(v8.x), bf16_lo(v8.y), bf16_hi(v8.y));
+      vr[2 * c + 1] = make_float4(bf16_lo(v8.z), bf16_hi(v8.z), bf16_lo(v8.w), bf16_hi(v8.w));
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < DH / 4; ++c) {
+      kr[c] = ldg4(base + e + 4 * c);
+      vr[c] = ldg4(base + e + d + 4 * c);
+    }
+  }
 }
 
 // attn_item with the row's global position gp and frame fi already known:
@@ -574,7 +614,6 @@ __device__ __forceinline__ void attn_item_at(const AttnArgs& a, int m, int hd, i
   for (int e = 0; e < DH / 4; ++e) q4[e] = ldg4(qp + 4 * e);
 
   auto key_at = [&](int kk, float4* kr, float4* vr, float& b) -> bool {
-    const float* kp;
     if (kk < n_sp) {
       int da, db;
       window_offset(a, kk, da, db);
@@ -584,25 +623,22 @@ __device__ __forceinline__ void attn_item_at(const AttnArgs& a, int m, int hd, i
         const int step_k = (ki + kj) % a.cycle;
         if (a.include_self ? step_k > step_p : step_k >= step_p) return false;
       }
-      kp = a.kv + (size_t)(fi.off + ki * fi.W + kj) * 2 * d + hd * DH;
       b = ldg(a.bias + hd * a.nbias + kk);
-    } else if (a.knull && kk == n_sp) {
-      kp = a.knull + hd * DH;
+      load_kv<DH>(a.kv, (size_t)(fi.off + ki * fi.W + kj) * 2 * d + hd * DH, d, a.kv16, kr, vr);
+      return true;
+    }
+    if (a.knull && kk == n_sp) {  // the null slot (FP32 parameters)
 #pragma unroll
       for (int e = 0; e < DH / 4; ++e) {
-        kr[e] = ldg4(kp + 4 * e);
+        kr[e] = ldg4(a.knull + hd * DH + 4 * e);
         vr[e] = ldg4(a.vnull + hd * DH + 4 * e);
       }
       return true;
-    } else {
-      if (!temporal_key(a, hd, DH, pi, pj, fi, n_sp, kk - n_sp - (a.knull ? 1 : 0), kp, b))
-        return false;
     }
-#pragma unroll
-    for (int e = 0; e < DH / 4; ++e) {
-      kr[e] = ldg4(kp + 4 * e);
-      vr[e] = ldg4(kp + d + 4 * e);
-    }
+    size_t e;
+    if (!temporal_key(a, hd, DH, pi, pj, fi, n_sp, kk - n_sp - (a.knull ? 1 : 0), e, b))
+      return false;
+    load_kv<DH>(a.tkv, e, d, a.kv16, kr, vr);
     return true;
   };
   attn_core<DH>(q4, n_keys, key_at, a.out + (size_t)m * a.ldo + hd * DH);

@@ -255,7 +255,7 @@ double attn_alg_bytes(const AttnArgs& a) {
   // step mask hides part of the window)
   const double keys = attn_slots(a);
   // K and V rows of every window slot, the query and the output
-  return double(a.M) * (keys * 2.0 * a.d * 4.0 + 2.0 * a.d * 4.0);
+  return double(a.M) * (keys * 2.0 * a.d * (a.kv16 ? 2.0 : 4.0) + 2.0 * a.d * 4.0);
 }
 
 void gemm_run(AKind ak, bool rms, Epi epi, const GemmArgs& a, hipStream_t s) {

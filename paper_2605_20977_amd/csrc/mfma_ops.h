@@ -100,12 +100,6 @@ __device__ __forceinline__ size_t wfrag_offset(int n, int kg, int ksteps) {
   return ((size_t)(n >> 3) * ksteps) * 256 + (size_t)(8 * kg + (n & 7)) * 8;
 }
 
-__device__ __forceinline__ uint16_t bf16_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return uint16_t(u >> 16);
-}
-
 // Steps 1 and 2 of a low-precision tile for rows m0 .. m0+rows-1 of A, one
 // wave per row (rows wave, wave + 4, ...): lane l loads the row's float4
 // chunks l, l+64, ... (CPR of them; RPB = 16 / CPR rows per wave in flight

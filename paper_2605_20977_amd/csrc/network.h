@@ -56,6 +56,7 @@ struct DevWeights {
   LayerWeights layers[kMaxLayers];
   const float *head_g, *W1, *W2, *gmu, *bmu, *gsig, *bsig;
   int prec;  // PSWA_PREC_*: arithmetic of every projection below
+  int kv16;  // key/value caches (accumulator, layers, temporal) stored in BF16
   QW in, acc_q, acc_kv, acc_o, head1, head2;
   float* calib = nullptr;  // calibration: per-input maxima (FP32 models only)
   CtWeights ct{};          // channel groups only
@@ -166,7 +167,7 @@ __host__ __device__ inline GemmArgs args_acc_q(const NetDims& x, const DevWeight
 __host__ __device__ inline AttnArgs args_acc_attn(const NetDims& x, const DevWeights& w,
                                                   const PassCtx& c) {
   AttnArgs a = attn_base(x, c, R_ACC_ATTN);
-  a.kv = c.acc_kv; a.tkv = nullptr; a.bias = w.acc_bias; a.nbias = x.n_acc;
+  a.kv = c.acc_kv; a.tkv = nullptr; a.kv16 = w.kv16; a.bias = w.acc_bias; a.nbias = x.n_acc;
   a.knull = w.knull; a.vnull = w.vnull; a.include_self = 0;
   return a;
 }
@@ -187,6 +188,7 @@ __host__ __device__ inline GemmArgs args_qkv(const NetDims& x, const DevWeights&
   g.X = c.x; g.ldx = x.d; g.gain = L.g1; g.W = L.Wqkv;
   g.Y = c.q; g.ldy = x.d; g.Y2 = c.kv + l * c.kv_stride; g.ldy2 = 2 * x.d; g.y2row = c.gpos;
   g.nsplit = x.d;
+  g.kv16 = w.kv16;
   use_q(g, w, L.qkv);
   return g;
 }
@@ -195,6 +197,7 @@ __host__ __device__ inline AttnArgs args_attn(const NetDims& x, const DevWeights
   AttnArgs a = attn_base(x, c, R_ATTN);
   a.kv = c.kv + l * c.kv_stride;
   a.tkv = c.tkv ? c.tkv + l * c.tkv_stride : nullptr;
+  a.kv16 = w.kv16;
   a.bias = w.layers[l].bias; a.nbias = x.n_sp + x.n_tm;
   a.knull = nullptr; a.vnull = nullptr; a.include_self = 1;
   return a;
@@ -316,7 +319,7 @@ __host__ __device__ inline GemmArgs args_acc_kv(const NetDims& x, const DevWeigh
                                                 const PassCtx& c) {
   GemmArgs g = gemm_base(c.M, 2 * x.d, x.d, R_ACCKV);
   g.X = c.e; g.ldx = x.d; g.gain = w.acc_gkv; g.W = w.acc_Wkv;
-  g.Y = c.acc_kv; g.ldy = 2 * x.d; g.yrow = c.gpos;
+  g.Y = c.acc_kv; g.ldy = 2 * x.d; g.yrow = c.gpos; g.kv16 = w.kv16;
   use_q(g, w, w.acc_kv);
   return g;
 }

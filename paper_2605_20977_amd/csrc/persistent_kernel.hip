@@ -290,15 +290,11 @@ __device__ __forceinline__ void attn_phase_staged(const AttnArgs& a, float* smem
             } else if (a.knull && kk == n_sp) {
               c = cells;
             } else {
-              const float* kp;
-              if (!temporal_key(a, hd, DH, pi, pj, fi, n_sp, kk - n_sp - (a.knull ? 1 : 0), kp,
+              size_t e;
+              if (!temporal_key(a, hd, DH, pi, pj, fi, n_sp, kk - n_sp - (a.knull ? 1 : 0), e,
                                 b))
                 return false;
-#pragma unroll
-              for (int e = 0; e < DH / 4; ++e) {
-                kr[e] = ldg4(kp + 4 * e);
-                vr[e] = ldg4(kp + d + 4 * e);
-              }
+              load_kv<DH>(a.tkv, e, d, a.kv16, kr, vr);
               return true;
             }
             const float* p = smem + c * CF + 4 * (c & 7) + hh * 2 * DH;

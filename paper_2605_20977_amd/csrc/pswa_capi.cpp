@@ -95,7 +95,11 @@ void temporal_kv_layer(const pswa_model* m, int HW, int HWt, int off, const floa
     GemmArgs a = gemm_base(HW, 2 * x.d, x.d, R_TKV);
     a.X = e_prev + ((size_t)tau * HWt + off) * x.d; a.ldx = x.d; a.gain = m->w.layers[l].g1;
     a.W = m->w.layers[l].Wqkv + (size_t)x.d * x.d;
-    a.Y = tkv_l + ((size_t)tau * HWt + off) * 2 * x.d; a.ldy = 2 * x.d;
+    const size_t e0 = ((size_t)tau * HWt + off) * 2 * x.d;  // element offset of the rows
+    a.Y = m->w.kv16 ? reinterpret_cast<float*>(reinterpret_cast<uint16_t*>(tkv_l) + e0)
+                    : tkv_l + e0;
+    a.ldy = 2 * x.d;
+    a.kv16 = m->w.kv16;
     use_q(a, m->w, m->w.layers[l].qkv, QW{}, (size_t)x.d * x.d);
     gemm_run(A_FLOAT, true, EPI_STORE, a, st);
   }
@@ -562,6 +566,7 @@ pswa_status pswa_model_create(const pswa_model_desc* desc, const float* h_blob,
   blob_layout(x, static_cast<const float*>(d_mem), &m->w, kTensorAlign);
   m->w.prec = desc->prec == PSWA_BF16 ? PSWA_PREC_BF16
               : desc->prec == PSWA_FP8_E4M3 ? PSWA_PREC_FP8 : PSWA_PREC_F32;
+  m->w.kv16 = desc->prec != PSWA_FP32;  // reduced-precision models keep K/V in BF16
   assign_slots(m->w, x);
   std::vector<std::vector<uint8_t>> staging;
   if (desc->prec != PSWA_FP32) {

@@ -90,6 +90,9 @@ struct GemmArgs {
   int ldy2 = 0;
   const int* y2row = nullptr;
   int nsplit = 0;
+  // EPI_STORE's Y, or EPI_QKV's Y2, is a key/value cache stored in BF16
+  // (element offsets as for FP32; the buffer's FP32 layout is half used)
+  int kv16 = 0;
   HeadOut head{};
 };
 
@@ -121,6 +124,7 @@ struct AttnArgs {
   const int* qrow;             // null: m
   const float* kv;             // [HWt][2d]: K then V per position
   const float* tkv;            // [2][HWt][2d] temporal K/V (or null)
+  int kv16;                    // kv and tkv hold BF16 (element offsets as for FP32)
   const float* bias; int nbias;  // [heads][nbias]
   const float* knull;          // accumulator null slot (null in layer mode)
   const float* vnull;

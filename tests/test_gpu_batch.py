@@ -119,13 +119,16 @@ def test_batch_1080p_mix_equals_step_decode(P):
     model = P.Model(cfg, Wt)
     sizes = [(68, 120, 0), (34, 60, 2), (15, 20, 2), (45, 80, 0)]
     fr = _frames(cfg, sizes, synth.CONFIG_SEEDS["batch"][0])
-    print("case batch 1080p mix", flush=True)
     b = P.Batch(model, fr)
     assert b.T == 455
-    b.run()
-    b.check()
-    for k in range(len(fr)):
-        _assert_same(b.outputs(k), _per_frame(P, model, fr[k]), f"frame {k}")
+    ref = [_per_frame(P, model, f) for f in fr]
+    for staged in (False, True):  # FP32 caches: both attention forms
+        print(f"case batch 1080p mix staged={staged}", flush=True)
+        b.set_attention(staged)
+        b.run()
+        b.check()
+        for k in range(len(fr)):
+            _assert_same(b.outputs(k), ref[k], f"staged={staged} frame {k}")
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp8"])
@@ -255,8 +258,8 @@ def test_batch_barrier_forms_agree(P, tiny):
 def test_batch_attention_forms_agree(P, tiny):
     """LDS-staged window tiles and per-lane global key loads give the same
     bits, across groupings (tiles cut at frame borders and block runs),
-    I- and P-frames, frames narrower than a window; the cyclic schedule
-    refuses the staged form."""
+    I- and P-frames, frames narrower than a window; the cyclic schedule and
+    models with BF16 key/value caches refuse the staged form."""
     cfg, Wt, model = tiny
     sizes = [(7, 9, 0), (16, 16, 2), (5, 13, 0), (12, 4, 2), (1, 1, 0), (3, 30, 2), (9, 2, 0)]
     fr = _frames(cfg, sizes, 1700)
@@ -276,3 +279,7 @@ def test_batch_attention_forms_agree(P, tiny):
     bc = P.Batch(cm, _frames(synth.TINY_CYCLIC, [(8, 8, 0)], 1800))
     with pytest.raises(P.PswaError):
         bc.set_attention(True)
+    bm = P.Batch(P.Model(cfg, Wt, "bf16"), fr[:1])
+    with pytest.raises(P.PswaError):
+        bm.set_attention(True)
+    assert not bm.attention_staged

@@ -3,7 +3,8 @@ autotuner time, through the C ABI.
 
 The persistent decode kernel is built once per (projection arithmetic, head
 size, row tile). The 1080p-shaped model (8 heads of 48) runs in
-  <BF16, 48, 32>  32 I-frames in groups of one frame x 8 workgroups,
+  <BF16, 48, 32>  I-frames in groups of one frame x 8 workgroups and of four
+                  frames x 4 workgroups,
   <BF16, 48, 16>  the mixed batch (grid sizes 15x20 .. 68x120, I and P) in
                   groups of two frames x 16 workgroups,
   <FP8, 48, 32>, <FP8, 48, 16>  the same with FP8 projections,
@@ -95,40 +96,38 @@ def test_mixed_1080p_batch_every_timed_instance(P, full, prec):
     assert b.T == 455
     for fpg, bpg in ((2, 16), (1, 8)):
         for rt in (16, 32):
-            for staged in (False, True):
-                print(f"case mixed 1080p {prec} groups {fpg}x{bpg} rtile {rt} staged {staged}",
-                      flush=True)
-                b.set_groups(fpg, bpg)
-                b.set_rtile(rt)
-                b.set_attention(staged)
-                b.run()
-                b.check()
-                for k in range(len(fr)):
-                    _assert_same(b.outputs(k), ref[k],
-                                 f"{prec} {fpg}x{bpg} rtile {rt} staged {staged} frame {k}")
+            print(f"case mixed 1080p {prec} groups {fpg}x{bpg} rtile {rt}", flush=True)
+            b.set_groups(fpg, bpg)
+            b.set_rtile(rt)
+            b.run()
+            b.check()
+            for k in range(len(fr)):
+                _assert_same(b.outputs(k), ref[k], f"{prec} {fpg}x{bpg} rtile {rt} frame {k}")
     # the 34 x 60 P-frame against the oracle
     _against_oracle(cfg, Wt, fr[3], ref[3], prec, 6, 31, f"mixed {prec} 34x60 P")
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp8"])
 def test_headline_1080p_i_batch(P, full, prec):
-    """1080p-shaped I-frames in groups of one frame x 8 workgroups, row tile
-    32, replayed from a HIP graph: the headline configuration."""
+    """1080p-shaped I-frames, row tile 32, replayed from a HIP graph, in the
+    groupings the headline batches use: one frame x 8 workgroups, and four
+    frames sharing 4 workgroups."""
     cfg, Wt = full
     model = P.make_model(cfg, Wt, prec, synth.calibration_frames(cfg))
     fr = _frames(cfg, [(68, 120, 0)] * 4, synth.CONFIG_SEEDS["1080p_I"][0])
     ref = [_encode(P, model, f) for f in fr]
     b = P.Batch(model, fr)
-    b.set_groups(1, 8)
-    b.set_rtile(32)
-    b.set_attention(True)
-    b.capture()
-    for rep in range(2):
-        print(f"case headline 1080p {prec} replay {rep}", flush=True)
-        b.run()
-        b.check()
-        for k in range(len(fr)):
-            _assert_same(b.outputs(k), ref[k], f"{prec} headline replay {rep} frame {k}")
+    for fpg, bpg in ((1, 8), (4, 4)):
+        b.set_groups(fpg, bpg)
+        b.set_rtile(32)
+        b.capture()
+        for rep in range(2):
+            print(f"case headline 1080p {prec} groups {fpg}x{bpg} replay {rep}", flush=True)
+            b.run()
+            b.check()
+            for k in range(len(fr)):
+                _assert_same(b.outputs(k), ref[k],
+                             f"{prec} {fpg}x{bpg} replay {rep} frame {k}")
     _against_oracle(cfg, Wt, fr[0], ref[0], prec, 5, 41, f"headline {prec} 68x120 I")
 
 
@@ -145,11 +144,9 @@ def test_student_4k_bf16_batch_row_tiles(P, rt):
     b = P.Batch(model, fr)
     b.set_groups(1, 32)
     b.set_rtile(rt)
-    for staged in (False, True):
-        print(f"case student 4K bf16 rtile {rt} staged {staged}", flush=True)
-        b.set_attention(staged)
-        b.run()
-        b.check()
-        for k in range(len(fr)):
-            _assert_same(b.outputs(k), ref[k], f"student rtile {rt} staged {staged} frame {k}")
+    print(f"case student 4K bf16 rtile {rt}", flush=True)
+    b.run()
+    b.check()
+    for k in range(len(fr)):
+        _assert_same(b.outputs(k), ref[k], f"student rtile {rt} frame {k}")
     _against_oracle(cfg, Wt, fr[1], ref[1], "bf16", 5, 51 + rt, f"student 4K bf16 P rtile {rt}")
