@@ -135,7 +135,7 @@ void lay_out(const NetDims& x, const Plan& p, int n, void* base, pswa_batch* b) 
   b->fid_all = L.take<int>(HWt);
   b->h = L.take<float>(HWt * x.d);
   b->q_acc = L.take<float>(HWt * x.d);
-  b->acc_kv = L.take<float>(HWt * 2 * x.d);
+  b->acc_kv = L.take<float>((HWt + 1) * 2 * x.d);  // + the null row
   b->kv = L.take<float>((size_t)x.L * HWt * 2 * x.d);
   b->tkv = p.any_p ? L.take<float>((size_t)x.L * 2 * HWt * 2 * x.d) : nullptr;
   b->e_prev = p.any_p ? L.take<float>(2 * HWt * x.d) : nullptr;
@@ -381,6 +381,7 @@ pswa_status run(pswa_batch* b, hipStream_t st) {
   const NetDims& x = m->x;
   zero_ints(b->ctl, 3, st);
   zero_ints(b->bars, (int)b->groups.size() * kBarStride, st);
+  null_row(b->acc_kv, b->HWt, m->w.knull, m->w.vnull, x.d, m->w.kv16, st);
   for (size_t f = 0; f < b->frames.size(); ++f) {
     const pswa_batch_frame& fr = b->frames[f];
     const FrameInfo& fi = b->finfo[f];

@@ -447,18 +447,41 @@ __device__ __forceinline__ void merge_lanes(float* v, int lane, int& off, int& g
   }
 }
 
-// One 64-lane wave per (query row, head). Lane l owns keys l, l+64, ... in
-// slot order (spatial window, then the null slot or the temporal windows)
-// and runs an online softmax over them, loading each key's K and V rows
-// together. The lanes are then merged: common max and rescaled exp-sum by
-// wave reductions, the rescaled value vectors by the butterfly of
-// merge_lanes (a fixed tree, in registers). Waves work independently (no
-// block synchronisation and no LDS); a wave with `live` false or an item
-// past the end returns at once. Every lane loads the query row itself,
-// together with its first key, so one memory round trip serves both.
+// Attention items: one 64-lane wave per (query row, pair of heads); lanes
+// 0-31 compute head 2p and lanes 32-63 head 2p + 1 (idle when the head count
+// is odd and 2p + 1 is past it). In its half, lane l owns the key slots
+// l, l + 32, ... (spatial window, then the null slot or the temporal
+// windows) and runs an online softmax over them, in slot order. The K and V
+// rows of NK of a lane's slots are requested together before any is used
+// (NK = 2 for BF16 caches, 1 for FP32 ones), so one round trip to memory
+// serves two slots. The half's lanes are then merged: common maximum and
+// rescaled exp-sum by reductions over the half, the rescaled value vectors
+// by the butterfly of merge_lanes (a fixed tree, in registers). Waves work
+// independently (no block synchronisation and no LDS).
 // Key positions: a row's frame (fid, else the single frame0) gives its grid
 // and its offset in the global position space; temporal K/V of frame
-// position g in previous frame tau is at (tau * HWt + g) * 2d.
+// position g in previous frame tau is at (tau * HWt + g) * 2d; the
+// accumulator's null key and value are the row after the last position
+// (HWt) of its cache.
+constexpr int kHalf = 32;
+
+__device__ __forceinline__ float half_max(float v) {
+#pragma unroll
+  for (int o = kHalf / 2; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ float half_sum(float v) {
+#pragma unroll
+  for (int o = kHalf / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+// lanes sharing each merged element at the end of merge_lanes<LEN, MASK>
+template <int LEN, int MASK>
+__host__ __device__ constexpr int merge_group() {
+  if constexpr (MASK > 0 && LEN % 2 == 0) return merge_group<LEN / 2, MASK / 2>();
+  else return 2 * MASK > 0 ? 2 * MASK : 1;
+}
+
 // The frame of query row m.
 __device__ __forceinline__ FrameInfo attn_frame(const AttnArgs& a, int m) {
   if (!a.fid) return a.frame0;
@@ -467,66 +490,116 @@ __device__ __forceinline__ FrameInfo attn_frame(const AttnArgs& a, int m) {
                    ldg(&a.frames[f].n_prev)};
 }
 
-// The arithmetic of one (query row, head) item, shared by every path: lane
-// l owns key slots l, l+64, ... in slot order and runs an online softmax over
-// them; the lanes are then merged (common max and rescaled exp-sum by wave
-// reductions, the rescaled value vectors by the fixed butterfly of
-// merge_lanes). key_at(kk, kr, vr, b) fills key slot kk's K and V rows
-// (DH/4 float4 each) and its bias and returns false for a slot that is out
-// of the frame or masked; where a key comes from (global memory or an LDS
-// tile) never changes the arithmetic.
-template <int DH, class KeyAt>
-__device__ __forceinline__ void attn_core(const float4* q4, int n_keys, KeyAt& key_at,
+// Raw K and V rows of one key slot as loaded (BF16 pairs, or FP32 bit
+// patterns) and its bias: the loads are in flight until kv_widen reads them.
+template <int DH>
+struct KeyRaw {
+  int4 k[DH / 4], v[DH / 4];  // BF16 rows use the first DH / 8 of each
+  float b;
+};
+template <int DH, bool KV16>
+__device__ __forceinline__ void kv_issue(const float* base, size_t e, int d, KeyRaw<DH>& r) {
+  if constexpr (KV16) {
+    const uint16_t* p = reinterpret_cast<const uint16_t*>(base) + e;
+#pragma unroll
+    for (int c = 0; c < DH / 8; ++c) {
+      r.k[c] = ldg(reinterpret_cast<const int4*>(p) + c);
+      r.v[c] = ldg(reinterpret_cast<const int4*>(p + d) + c);
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < DH / 4; ++c) {
+      r.k[c] = ldg(reinterpret_cast<const int4*>(base + e) + c);
+      r.v[c] = ldg(reinterpret_cast<const int4*>(base + e + d) + c);
+    }
+  }
+}
+template <int DH, bool KV16>
+__device__ __forceinline__ void kv_widen(const KeyRaw<DH>& r, float4* kr, float4* vr) {
+  if constexpr (KV16) {
+#pragma unroll
+    for (int c = 0; c < DH / 8; ++c) {
+      const int4 k8 = r.k[c], v8 = r.v[c];
+      kr[2 * c] = make_float4(bf16_lo(k8.x), bf16_hi(k8.x), bf16_lo(k8.y), bf16_hi(k8.y));
+      kr[2 * c + 1] = make_float4(bf16_lo(k8.z), bf16_hi(k8.z), bf16_lo(k8.w), bf16_hi(k8.w));
+      vr[2 * c] = make_float4(bf16_lo(v8.x), bf16_hi(v8.x), bf16_lo(v8.y), bf16_hi(v8.y));
+      vr[2 * c + 1] = make_float4(bf16_lo(v8.z), bf16_hi(v8.z), bf16_lo(v8.w), bf16_hi(v8.w));
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < DH / 4; ++c) {
+      kr[c] = make_float4(__int_as_float(r.k[c].x), __int_as_float(r.k[c].y),
+                          __int_as_float(r.k[c].z), __int_as_float(r.k[c].w));
+      vr[c] = make_float4(__int_as_float(r.v[c].x), __int_as_float(r.v[c].y),
+                          __int_as_float(r.v[c].z), __int_as_float(r.v[c].w));
+    }
+  }
+}
+
+// The arithmetic of one attention item, shared by every path. src.issue(kk,
+// slot) requests key slot kk (false: masked or outside the frame) and
+// src.get(slot, kr, vr, b) delivers its K and V rows and bias; q4 is the
+// lane's head's query, out its output row. live = false idles the half.
+template <int DH, int NK, class Source>
+__device__ __forceinline__ void attn_core(const float4* q4, int n_keys, bool live, Source& src,
                                           float* out) {
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, l32 = lane & (kHalf - 1);
   const float scale = 1.0f / sqrtf(float(DH));
   float mx = -INFINITY, sum = 0.f;
   float o[DH];
 #pragma unroll
   for (int e = 0; e < DH; ++e) o[e] = 0.f;
 
-  // one key per iteration: its K and V rows are the lane's loads in flight
-  // (most lanes own a single key)
 #pragma unroll 1
-  for (int u = 0; u < kMaxKeys / 64; ++u) {
-    const int kk = lane + 64 * u;
-    if (kk >= n_keys) break;
-    float4 kr[DH / 4], vr[DH / 4];
-    float b = 0.f;
-    if (!key_at(kk, kr, vr, b)) continue;
-    float dot = 0.f;
+  for (int u = 0; u < kMaxKeys / kHalf; u += NK) {
+    if (kHalf * u >= n_keys) break;  // the same for the whole wave
+    typename Source::Slot sl[NK];
+    bool ok[NK];
 #pragma unroll
-    for (int e = 0; e < DH / 4; ++e) dot = dot4(q4[e], kr[e], dot);
-    const float lg = dot * scale + b;
-    const float mn = fmaxf(mx, lg);
-    const float c_old = expf(mx - mn);  // 0 for the first key (mx = -inf)
-    const float pk = expf(lg - mn);
-    sum = sum * c_old + pk;
-#pragma unroll
-    for (int e = 0; e < DH / 4; ++e) {
-      o[4 * e + 0] = fmaf(pk, vr[e].x, o[4 * e + 0] * c_old);
-      o[4 * e + 1] = fmaf(pk, vr[e].y, o[4 * e + 1] * c_old);
-      o[4 * e + 2] = fmaf(pk, vr[e].z, o[4 * e + 2] * c_old);
-      o[4 * e + 3] = fmaf(pk, vr[e].w, o[4 * e + 3] * c_old);
+    for (int j = 0; j < NK; ++j) {
+      const int kk = l32 + kHalf * (u + j);
+      ok[j] = live && kk < n_keys && src.issue(kk, sl[j]);
     }
-    mx = mn;
+#pragma unroll
+    for (int j = 0; j < NK; ++j) {
+      if (!ok[j]) continue;
+      float4 kr[DH / 4], vr[DH / 4];
+      float b;
+      src.get(sl[j], kr, vr, b);
+      float dot = 0.f;
+#pragma unroll
+      for (int e = 0; e < DH / 4; ++e) dot = dot4(q4[e], kr[e], dot);
+      const float lg = dot * scale + b;
+      const float mn = fmaxf(mx, lg);
+      const float c_old = expf(mx - mn);  // 0 for the lane's first key (mx = -inf)
+      const float pk = expf(lg - mn);
+      sum = sum * c_old + pk;
+#pragma unroll
+      for (int e = 0; e < DH / 4; ++e) {
+        o[4 * e + 0] = fmaf(pk, vr[e].x, o[4 * e + 0] * c_old);
+        o[4 * e + 1] = fmaf(pk, vr[e].y, o[4 * e + 1] * c_old);
+        o[4 * e + 2] = fmaf(pk, vr[e].z, o[4 * e + 2] * c_old);
+        o[4 * e + 3] = fmaf(pk, vr[e].w, o[4 * e + 3] * c_old);
+      }
+      mx = mn;
+    }
   }
 
-  const float gmx = wave_max(mx);
+  const float gmx = half_max(mx);
   const float f = mx == -INFINITY ? 0.f : expf(mx - gmx);
-  const float tot = wave_sum(sum * f);
-  // lanes' rescaled value vectors summed over the 64 lanes by a fixed
-  // butterfly (see merge_lanes)
+  const float tot = half_sum(sum * f);
+  // lanes' rescaled value vectors summed over the half by a fixed butterfly
   float v[DH];
 #pragma unroll
   for (int e = 0; e < DH; ++e) v[e] = o[e] * f;
   int off = 0, group = 1;
-  merge_lanes<DH, 32>(v, lane, off, group);
-  const int k = lane & (group - 1);
-  float val = v[0];  // v[k], by constant indices (a variable index would put v in scratch)
+  merge_lanes<DH, kHalf / 2>(v, lane, off, group);
+  constexpr int ML = merge_len<DH, kHalf / 2>(), MG = merge_group<DH, kHalf / 2>();
+  const int k = lane & (MG - 1);
+  if (!live) return;
 #pragma unroll
-  for (int j = 1; j < merge_len<DH, 32>(); ++j) val = k == j ? v[j] : val;
-  if (k < merge_len<DH, 32>()) stg(out + off + k, val / tot);
+  for (int j = 0; j < ML; ++j)  // element j of the group's run, by constant index
+    if (j % MG == k) stg(out + off + j, v[j] / tot);
 }
 
 // Spatial window slot kk of a query at (pi, pj): its offset (da, db) (the
@@ -546,110 +619,108 @@ __device__ __forceinline__ void window_offset(const AttnArgs& a, int kk, int& da
   }
 }
 
-// Slot counts of a row: spatial (with self for layers), null, temporal.
+// Spatial slots of a row (with self for layers).
 __device__ __forceinline__ int attn_n_sp(const AttnArgs& a) {
   const int k1 = 2 * a.r + 1;
   return a.cycle ? k1 * k1 : 2 * a.r * (a.r + 1) + (a.include_self ? 1 : 0);
 }
 
-// Temporal slot t (previous frame tau = t / k1^2 + 1, window in raster
-// order) of a query at (pi, pj): element offset of its K row in a.tkv and
-// its bias, false outside the frame.
-__device__ __forceinline__ bool temporal_key(const AttnArgs& a, int hd, int dh, int pi, int pj,
-                                             const FrameInfo& fi, int n_sp, int t,
-                                             size_t& e, float& b) {
+// Where key slot kk of the query at (pi, pj) lives: the cache (kv or tkv)
+// and element offset of its K row for head hd, and its bias index (-1: no
+// bias, the null slot); false when the slot is masked or outside the frame.
+struct SlotAddr {
+  const float* base;
+  size_t e;
+  int bias;
+};
+__device__ __forceinline__ bool slot_addr(const AttnArgs& a, int kk, int hd, int dh, int pi,
+                                          int pj, const FrameInfo& fi, int n_sp, int step_p,
+                                          SlotAddr& s) {
+  const int d = a.d;
+  if (kk < n_sp) {
+    int da, db;
+    window_offset(a, kk, da, db);
+    const int ki = pi + da, kj = pj + db;
+    if (ki < 0 || ki >= fi.H || kj < 0 || kj >= fi.W) return false;
+    if (a.cycle) {  // decoded early enough: strictly (accumulator) or not
+      const int step_k = (ki + kj) % a.cycle;
+      if (a.include_self ? step_k > step_p : step_k >= step_p) return false;
+    }
+    s = SlotAddr{a.kv, (size_t)(fi.off + ki * fi.W + kj) * 2 * d + hd * dh, hd * a.nbias + kk};
+    return true;
+  }
+  if (a.knull && kk == n_sp) {
+    s = SlotAddr{a.kv, (size_t)a.HWt * 2 * d + hd * dh, -1};
+    return true;
+  }
   const int r = a.r, k1 = 2 * r + 1;
+  const int t = kk - n_sp - (a.knull ? 1 : 0);
   const int tau = t / (k1 * k1), rem = t % (k1 * k1);
   const int ki = pi + rem / k1 - r, kj = pj + rem % k1 - r;
   if (ki < 0 || ki >= fi.H || kj < 0 || kj >= fi.W) return false;
-  e = ((size_t)tau * a.HWt + (size_t)(fi.off + ki * fi.W + kj)) * 2 * a.d + hd * dh;
-  b = ldg(a.bias + hd * a.nbias + n_sp + t);
+  s = SlotAddr{a.tkv, ((size_t)tau * a.HWt + (size_t)(fi.off + ki * fi.W + kj)) * 2 * d + hd * dh,
+               hd * a.nbias + n_sp + t};
   return true;
 }
 
-// K and V rows (DH values each, V d elements after K) of a K/V cache at
-// element offset e, as floats: FP32 rows, or BF16 rows (kv16) widened.
-template <int DH>
-__device__ __forceinline__ void load_kv(const float* base, size_t e, int d, int kv16, float4* kr,
-                                        float4* vr) {
-  if (kv16) {
-    const uint16_t* p = reinterpret_cast<const uint16_t*>(base) + e;
-#pragma unroll
-    for (int c = 0; c < DH / 8; ++c) {
-      const int4 k8 = ldg(reinterpret_cast<const int4*>(p) + c);
-      const int4 v8 = ldg(reinterpret_cast<const int4*>(p + d) + c);
-      kr[2 * c] = make_float4(bf16_lo(k8.x), bf16_hi(k8.x), bf16_lo(k8.y), bf16_hi(k8.y));
-      kr[2 * c + 1] = make_float4(bf16_lo(k8.z), bf16_hi(k8.z), bf16_lo(k8.w), bf16_hi(k8.w));
-      vr[2 * c] = make_float4(bf16_lo(v8.x), bf16_hi(v8.x), bf16_lo(v8.y), bf16_hi(v8.y));
-      vr[2 * c + 1] = make_float4(bf16_lo(v8.z), bf16_hi(v8.z), bf16_lo(v8.w), bf16_hi(v8.w));
-    }
-  } else {
-#pragma unroll
-    for (int c = 0; c < DH / 4; ++c) {
-      kr[c] = ldg4(base + e + 4 * c);
-      vr[c] = ldg4(base + e + d + 4 * c);
-    }
-  }
+// Key slots of a query row: spatial window (with self for layers), the null
+// slot, the temporal windows of P-frames.
+__device__ __forceinline__ int attn_n_keys(const AttnArgs& a, const FrameInfo& fi) {
+  const int k1 = 2 * a.r + 1;
+  return attn_n_sp(a) + (a.knull ? 1 : 0) + (a.tkv && fi.n_prev > 0 ? 2 * k1 * k1 : 0);
 }
 
-// attn_item with the row's global position gp and frame fi already known:
-// every key read from global memory. Every lane loads the query row itself
-// (the same addresses, served once), issued together with its first key.
-template <int DH>
-__device__ __forceinline__ void attn_item_at(const AttnArgs& a, int m, int hd, int gp,
-                                             const FrameInfo& fi, float* tr_all) {
-  (void)tr_all;  // no LDS: the merge runs in registers
+// Keys read from the caches in global memory.
+template <int DH, bool KV16>
+struct GlobalKeys {
+  struct Slot {
+    KeyRaw<DH> raw;
+  };
+  const AttnArgs& a;
+  int hd, pi, pj, n_sp, step_p;
+  FrameInfo fi;
+  __device__ __forceinline__ bool issue(int kk, Slot& sl) {
+    SlotAddr s;
+    if (!slot_addr(a, kk, hd, DH, pi, pj, fi, n_sp, step_p, s)) return false;
+    sl.raw.b = s.bias >= 0 ? ldg(a.bias + s.bias) : 0.f;
+    kv_issue<DH, KV16>(s.base, s.e, a.d, sl.raw);
+    return true;
+  }
+  __device__ __forceinline__ void get(const Slot& sl, float4* kr, float4* vr, float& b) {
+    kv_widen<DH, KV16>(sl.raw, kr, vr);
+    b = sl.raw.b;
+  }
+};
+
+// Item (row m, head pair p) with the row's global position gp and frame fi
+// already known, every key from global memory.
+template <int DH, bool KV16>
+__device__ __forceinline__ void attn_pair_at(const AttnArgs& a, int m, int p, int gp,
+                                             const FrameInfo& fi) {
+  const int hd = 2 * p + ((threadIdx.x >> 5) & 1);
+  const bool live = hd < a.heads;
   const int lp = gp - fi.off;
   const int pi = lp / fi.W, pj = lp % fi.W;
   const int n_sp = attn_n_sp(a);
-  const int step_p = a.cycle ? (pi + pj) % a.cycle : 0;
-  const bool temporal = a.tkv && fi.n_prev > 0;
-  const int k1 = 2 * a.r + 1;
-  const int n_keys = n_sp + (a.knull ? 1 : 0) + (temporal ? 2 * k1 * k1 : 0);
-  const int d = a.d;
-
-  const float* qp = a.q + (size_t)map_row(a.qrow, m) * a.ldq + hd * DH;
+  const float* qp = a.q + (size_t)map_row(a.qrow, m) * a.ldq + min(hd, a.heads - 1) * DH;
   float4 q4[DH / 4];
 #pragma unroll
   for (int e = 0; e < DH / 4; ++e) q4[e] = ldg4(qp + 4 * e);
-
-  auto key_at = [&](int kk, float4* kr, float4* vr, float& b) -> bool {
-    if (kk < n_sp) {
-      int da, db;
-      window_offset(a, kk, da, db);
-      const int ki = pi + da, kj = pj + db;
-      if (ki < 0 || ki >= fi.H || kj < 0 || kj >= fi.W) return false;
-      if (a.cycle) {  // decoded early enough: strictly (accumulator) or not
-        const int step_k = (ki + kj) % a.cycle;
-        if (a.include_self ? step_k > step_p : step_k >= step_p) return false;
-      }
-      b = ldg(a.bias + hd * a.nbias + kk);
-      load_kv<DH>(a.kv, (size_t)(fi.off + ki * fi.W + kj) * 2 * d + hd * DH, d, a.kv16, kr, vr);
-      return true;
-    }
-    if (a.knull && kk == n_sp) {  // the null slot (FP32 parameters)
-#pragma unroll
-      for (int e = 0; e < DH / 4; ++e) {
-        kr[e] = ldg4(a.knull + hd * DH + 4 * e);
-        vr[e] = ldg4(a.vnull + hd * DH + 4 * e);
-      }
-      return true;
-    }
-    size_t e;
-    if (!temporal_key(a, hd, DH, pi, pj, fi, n_sp, kk - n_sp - (a.knull ? 1 : 0), e, b))
-      return false;
-    load_kv<DH>(a.tkv, e, d, a.kv16, kr, vr);
-    return true;
-  };
-  attn_core<DH>(q4, n_keys, key_at, a.out + (size_t)m * a.ldo + hd * DH);
+  GlobalKeys<DH, KV16> src{a, hd, pi, pj, n_sp, a.cycle ? (pi + pj) % a.cycle : 0, fi};
+  attn_core<DH, KV16 ? 2 : 1>(q4, attn_n_keys(a, fi), live, src,
+                              a.out + (size_t)m * a.ldo + hd * DH);
 }
 
-template <int DH>
-__device__ __forceinline__ void attn_item(const AttnArgs& a, int item, bool live, float* tr_all) {
-  live = live && item < a.M * a.heads;
-  if (!live) return;
-  const int m = item / a.heads, hd = item % a.heads;
-  attn_item_at<DH>(a, m, hd, map_row(a.pos, m), attn_frame(a, m), tr_all);
+// Head pairs of a row.
+__host__ __device__ inline int attn_pairs(int heads) { return (heads + 1) / 2; }
+
+// Per-launch item `item` = m * pairs + p (rows past M idle).
+template <int DH, bool KV16>
+__device__ __forceinline__ void attn_item(const AttnArgs& a, int item) {
+  const int np = attn_pairs(a.heads);
+  if (item >= a.M * np) return;
+  const int m = item / np, p = item % np;
+  attn_pair_at<DH, KV16>(a, m, p, map_row(a.pos, m), attn_frame(a, m));
 }
 
 // Attention needs no LDS (the lanes are merged in registers).
@@ -685,17 +756,6 @@ __host__ __device__ inline constexpr size_t stage_bias_off(int dh) {
 }
 __host__ __device__ inline size_t attn_stage_lds_bytes(int dh) {
   return stage_bias_off(dh) + (size_t)stage_heads(dh) * 64 * 4;
-}
-
-template <int DH_dummy = 0>
-__device__ __forceinline__ void attn_item_any(const AttnArgs& a, int item, bool live,
-                                              float* tr_all) {
-  switch (a.dh) {  // other head sizes are rejected when the model is created
-    case 16: attn_item<16>(a, item, live, tr_all); break;
-    case 32: attn_item<32>(a, item, live, tr_all); break;
-    case 48: attn_item<48>(a, item, live, tr_all); break;
-    default: attn_item<64>(a, item, live, tr_all); break;
-  }
 }
 
 // ------------------------------------------------------------ symbol items

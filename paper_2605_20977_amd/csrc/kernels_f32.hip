@@ -42,11 +42,22 @@ __global__ void __launch_bounds__(kThreads) k_gemm_q(GemmArgs a) {
                                 rstd, rmul);
 }
 
-template <int DH>
+// One wave per (row, head pair); KV16: BF16 key/value caches.
+template <int DH, bool KV16>
 __global__ void __launch_bounds__(kThreads) k_attn(AttnArgs a) {
-  extern __shared__ float4 smem4[];
-  attn_item<DH>(a, blockIdx.x * kWaves + (threadIdx.x >> 6), true,
-                reinterpret_cast<float*>(smem4));
+  attn_item<DH, KV16>(a, blockIdx.x * kWaves + (threadIdx.x >> 6));
+}
+
+// The accumulator's null key and value as row `row` of its cache (BF16 when
+// kv16), so that attention reads the null slot like any other key.
+__global__ void k_null_row(float* acc_kv, size_t row, const float* knull, const float* vnull,
+                           int d, int kv16) {
+  for (int i = threadIdx.x; i < 2 * d; i += blockDim.x) {
+    const float v = i < d ? knull[i] : vnull[i - d];
+    const size_t o = row * 2 * d + i;
+    if (kv16) reinterpret_cast<uint16_t*>(acc_kv)[o] = bf16_rne(v);
+    else acc_kv[o] = v;
+  }
 }
 
 // One block per hyperprior cell: W_h z is shared by the cell's (up to) 4x4
@@ -221,15 +232,20 @@ void gemm_dispatch(AKind ak, bool rms, Epi epi, const GemmArgs& a, hipStream_t s
 }
 
 void attention_dispatch(const AttnArgs& a, hipStream_t s) {
-  const dim3 grid(blocks_for((long)a.M * a.heads, kWaves));
-  const size_t lds = attn_lds_bytes(a.dh);
+  const dim3 grid(blocks_for((long)a.M * attn_pairs(a.heads), kWaves));
+#define PSWA_ATTN(D_)                                                                    \
+  case D_:                                                                               \
+    if (a.kv16) hipLaunchKernelGGL((k_attn<D_, true>), grid, dim3(kThreads), 0, s, a);   \
+    else hipLaunchKernelGGL((k_attn<D_, false>), grid, dim3(kThreads), 0, s, a);         \
+    break;
   switch (a.dh) {  // other head sizes are rejected when the model is created
-    case 16: hipLaunchKernelGGL(k_attn<16>, grid, dim3(kThreads), lds, s, a); break;
-    case 32: hipLaunchKernelGGL(k_attn<32>, grid, dim3(kThreads), lds, s, a); break;
-    case 48: hipLaunchKernelGGL(k_attn<48>, grid, dim3(kThreads), lds, s, a); break;
-    case 64: hipLaunchKernelGGL(k_attn<64>, grid, dim3(kThreads), lds, s, a); break;
+    PSWA_ATTN(16)
+    PSWA_ATTN(32)
+    PSWA_ATTN(48)
+    PSWA_ATTN(64)
     default: no_instance("attention", a.dh, 0, 0);
   }
+#undef PSWA_ATTN
 }
 
 }  // namespace
@@ -302,6 +318,11 @@ void group_rmsnorm(const float* X, int ldx, int M, int K, int col0, const float*
   if (M <= 0) return;
   hipLaunchKernelGGL(k_group_rms, dim3((M + 3) / 4), dim3(256), 0, s, X, ldx, M, K, col0, gain, Y,
                      ldy);
+}
+
+void null_row(float* acc_kv, size_t row, const float* knull, const float* vnull, int d, int kv16,
+              hipStream_t s) {
+  hipLaunchKernelGGL(k_null_row, dim3(1), dim3(256), 0, s, acc_kv, row, knull, vnull, d, kv16);
 }
 
 void symbol_bits(const int* pos, int M, int C, const int32_t* ydec, const float* mean,

@@ -118,33 +118,38 @@ __device__ __forceinline__ void gemm_phase(const GemmArgs& a, float4* smem4, flo
   }
 }
 
-// Items in head-major order (item = head * M + row): a wave takes a
-// contiguous run of them, so its consecutive items are adjacent rows of one
-// head, whose key windows overlap (their K/V rows are then still in cache).
-// The positions and frames of up to 8 items are loaded together before they
-// run, so an item waits only on its own keys.
-template <int DH>
-__device__ __forceinline__ void attn_phase(const AttnArgs& a, float* smem, int rank, int nb) {
+// Items (row, head pair) in head-major order (item = pair * M + row): a wave
+// takes a contiguous run of them, so its consecutive items are adjacent rows
+// of one head pair, whose key windows overlap (their K/V rows are then still
+// in cache). The positions and frames of up to 8 items are read together
+// before they run, with scalar loads from the launch's read-only row and
+// frame tables (all positions, then all frames: two round trips per 8
+// items), so an item waits only on its own keys. KV16: BF16 caches.
+template <int DH, bool KV16>
+__device__ __forceinline__ void attn_phase(const AttnArgs& a, int rank, int nb) {
   constexpr int PF = 8;
-  const int items = a.M * a.heads;
+  const int items = a.M * attn_pairs(a.heads);
   const int nw = nb * kWaves;
   const int per = (items + nw - 1) / nw;
-  const int i0 = min(items, (rank * kWaves + (int)(threadIdx.x >> 6)) * per);
+  const int i0 = __builtin_amdgcn_readfirstlane(
+      min(items, (rank * kWaves + (int)(threadIdx.x >> 6)) * per));
   const int i1 = min(items, i0 + per);
   for (int b0 = i0; b0 < i1; b0 += PF) {
-    int gp[PF];
+    int gp[PF], fr[PF];
     FrameInfo fi[PF];
 #pragma unroll
     for (int i = 0; i < PF; ++i) {
       const int m = min(b0 + i, i1 - 1) % a.M;
-      gp[i] = map_row(a.pos, m);
-      fi[i] = attn_frame(a, m);
+      gp[i] = a.pos ? load_uniform(a.pos + m) : m;
+      fr[i] = a.fid ? load_uniform(a.fid + m) : 0;
     }
+#pragma unroll
+    for (int i = 0; i < PF; ++i) fi[i] = a.fid ? load_uniform(a.frames + fr[i]) : a.frame0;
 #pragma unroll
     for (int i = 0; i < PF; ++i) {
       const int item = b0 + i;
       if (item >= i1) break;  // uniform across the wave
-      attn_item_at<DH>(a, item % a.M, item / a.M, gp[i], fi[i], smem);
+      attn_pair_at<DH, KV16>(a, item % a.M, item / a.M, gp[i], fi[i]);
     }
   }
 }
@@ -159,6 +164,59 @@ __device__ __forceinline__ void lds_load4(const float* src, float* lds) {
   __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
                                    (__attribute__((address_space(3))) void*)lds, 4, 0, 0);
 }
+
+// Keys of a staged tile: window cells and the null slot from LDS (cell slot
+// of kStageCellBytes, data 16 (cell mod 8) bytes in, head hh's K then V row),
+// temporal keys of P-frames from global memory (FP32 caches).
+template <int DH>
+struct StagedKeys {
+  struct Slot {
+    int cell;  // -1: a temporal key, in raw
+    KeyRaw<DH> raw;
+  };
+  const AttnArgs& a;
+  const float* smem;
+  const float* btile;
+  const int *s_base, *s_c0;
+  int hd, hh, wave, pi, pj, n_sp, cells;
+  FrameInfo fi;
+  __device__ __forceinline__ bool issue(int kk, Slot& sl) {
+    if (kk < n_sp) {
+      int da, db;
+      window_offset(a, kk, da, db);
+      const int ki = pi + da, kj = pj + db;
+      if (ki < 0 || ki >= fi.H || kj < 0 || kj >= fi.W) return false;
+      const int k = wave + a.r + da;  // the key's image row within the tile
+      sl.cell = s_base[k] + kj - s_c0[k];
+      sl.raw.b = btile[hh * 64 + kk];
+      return true;
+    }
+    if (a.knull && kk == n_sp) {
+      sl.cell = cells;
+      sl.raw.b = 0.f;
+      return true;
+    }
+    SlotAddr s;
+    if (!slot_addr(a, kk, hd, DH, pi, pj, fi, n_sp, 0, s)) return false;
+    sl.cell = -1;
+    sl.raw.b = ldg(a.bias + s.bias);
+    kv_issue<DH, false>(s.base, s.e, a.d, sl.raw);
+    return true;
+  }
+  __device__ __forceinline__ void get(const Slot& sl, float4* kr, float4* vr, float& b) {
+    b = sl.raw.b;
+    if (sl.cell < 0) {
+      kv_widen<DH, false>(sl.raw, kr, vr);
+      return;
+    }
+    const float* p = smem + sl.cell * (kStageCellBytes / 4) + 4 * (sl.cell & 7) + hh * 2 * DH;
+#pragma unroll
+    for (int e = 0; e < DH / 4; ++e) {
+      kr[e] = *reinterpret_cast<const float4*>(p + 4 * e);
+      vr[e] = *reinterpret_cast<const float4*>(p + DH + 4 * e);
+    }
+  }
+};
 
 // Wavefront attention from LDS-staged window tiles (see device_ops.h): the
 // phase's rows are split into contiguous runs over the group's blocks; a
@@ -178,7 +236,6 @@ __device__ __forceinline__ void attn_phase_staged(const AttnArgs& a, float* smem
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = a.r, s = r + 1, d = a.d;
   const int n_sp = attn_n_sp(a);
-  const int k1 = 2 * r + 1;
   float* qtile = smem + kStageQOff / 4;
   float* btile = smem + stage_bias_off(DH) / 4;
   // this lane's piece of a cell: head lh of the group, 16 bytes lq of that
@@ -248,8 +305,7 @@ __device__ __forceinline__ void attn_phase_staged(const AttnArgs& a, float* smem
     const int m = m0 + min(wave, R - 1);
     const int qr = map_row(a.qrow, m);
     const int pi = i0 + wave, pj = j0 - s * wave;
-    const bool temporal = a.tkv && fi.n_prev > 0;
-    const int n_keys = n_sp + (a.knull ? 1 : 0) + (temporal ? 2 * k1 * k1 : 0);
+    const int n_keys = attn_n_keys(a, fi);
     for (int h0 = 0; h0 < a.heads; h0 += HT) {
       const int nh = min(HT, a.heads - h0);
       // K/V rows of the heads: cell c by wave c mod 4, 16 bytes per lane
@@ -271,41 +327,19 @@ __device__ __forceinline__ void attn_phase_staged(const AttnArgs& a, float* smem
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
       if (live) {
-        for (int hh = 0; hh < nh; ++hh) {
-          const int hd = h0 + hh;
+        // the stage's heads in pairs, one per half-wave (FP32 caches: one key
+        // per round, as in attn_pair_at)
+        for (int hp = 0; hp < nh; hp += 2) {
+          const int hs = hp + ((threadIdx.x >> 5) & 1);
+          const bool hlive = hs < nh;
+          const int hh = min(hs, nh - 1);
           float4 q4[DH / 4];
 #pragma unroll
           for (int e = 0; e < DH / 4; ++e)
             q4[e] = *reinterpret_cast<const float4*>(qtile + wave * HT * DH + hh * DH + 4 * e);
-          auto key_at = [&](int kk, float4* kr, float4* vr, float& b) -> bool {
-            int c;
-            if (kk < n_sp) {
-              int da, db;
-              window_offset(a, kk, da, db);
-              const int ki = pi + da, kj = pj + db;
-              if (ki < 0 || ki >= fi.H || kj < 0 || kj >= fi.W) return false;
-              const int k = wave + r + da;
-              c = s_base[k] + kj - s_c0[k];
-              b = btile[hh * 64 + kk];
-            } else if (a.knull && kk == n_sp) {
-              c = cells;
-            } else {
-              size_t e;
-              if (!temporal_key(a, hd, DH, pi, pj, fi, n_sp, kk - n_sp - (a.knull ? 1 : 0), e,
-                                b))
-                return false;
-              load_kv<DH>(a.tkv, e, d, a.kv16, kr, vr);
-              return true;
-            }
-            const float* p = smem + c * CF + 4 * (c & 7) + hh * 2 * DH;
-#pragma unroll
-            for (int e = 0; e < DH / 4; ++e) {
-              kr[e] = *reinterpret_cast<const float4*>(p + 4 * e);
-              vr[e] = *reinterpret_cast<const float4*>(p + DH + 4 * e);
-            }
-            return true;
-          };
-          attn_core<DH>(q4, n_keys, key_at, a.out + (size_t)m * a.ldo + hd * DH);
+          StagedKeys<DH> src{a, smem, btile, s_base, s_c0, h0 + hh, hh, wave, pi, pj, n_sp, cells,
+                             fi};
+          attn_core<DH, 1>(q4, n_keys, hlive, src, a.out + (size_t)m * a.ldo + (h0 + hh) * DH);
         }
       }
       __syncthreads();
@@ -384,7 +418,7 @@ __global__ void __launch_bounds__(kThreads) k_persistent(PersistArgs P) {
     if (staged)
       attn_phase_staged<DH>(lds_uniform(at + 0), smem, rank, nb);
     else
-      attn_phase<DH>(lds_uniform(at + 0), smem, rank, nb);
+      attn_phase<DH, PREC != PSWA_PREC_F32>(lds_uniform(at + 0), rank, nb);
     PSWA_SYNC
     gemm_phase<A_FLOAT, false, EPI_RESID, PREC, R>(lds_uniform(g + 1), smem4, rstd, rank, nb);
     PSWA_SYNC
@@ -394,7 +428,7 @@ __global__ void __launch_bounds__(kThreads) k_persistent(PersistArgs P) {
       if (staged)
         attn_phase_staged<DH>(lds_uniform(at + 1 + l), smem, rank, nb);
       else
-        attn_phase<DH>(lds_uniform(at + 1 + l), smem, rank, nb);
+        attn_phase<DH, PREC != PSWA_PREC_F32>(lds_uniform(at + 1 + l), rank, nb);
       PSWA_SYNC
       gemm_phase<A_FLOAT, false, EPI_RESID, PREC, R>(lds_uniform(g + 3 + 4 * l), smem4, rstd, rank, nb);
       PSWA_SYNC

@@ -370,7 +370,7 @@ EncodeWs plan_encode(const NetDims& x, const pswa_frame_desc& f, void* base) {
   const size_t HW = (size_t)f.H * f.W;
   EncodeWs w;
   w.h = L.take<float>(HW * x.d);
-  w.acc_kv = L.take<float>(HW * 2 * x.d);
+  w.acc_kv = L.take<float>((HW + 1) * 2 * x.d);  // + the null row
   w.kv = L.take<float>(HW * 2 * x.d);
   w.tkv = f.n_prev ? L.take<float>(2 * HW * 2 * x.d) : nullptr;
   w.e_prev = f.n_prev ? L.take<float>(2 * HW * x.d) : nullptr;
@@ -437,7 +437,7 @@ void plan_state(const NetDims& x, const pswa_frame_desc& f, void* base, pswa_sta
   for (int t = 0; t < st->T; ++t) nmax = std::max(nmax, sched_len(x, f.H, f.W, t));
   st->nmax = nmax;
   st->h = L.take<float>(HW * x.d);
-  st->acc_kv = L.take<float>(HW * 2 * x.d);
+  st->acc_kv = L.take<float>((HW + 1) * 2 * x.d);  // + the null row
   st->kv = L.take<float>((size_t)x.L * HW * 2 * x.d);
   st->tkv = f.n_prev ? L.take<float>((size_t)x.L * 2 * HW * 2 * x.d) : nullptr;
   st->e_prev = f.n_prev ? L.take<float>(2 * HW * x.d) : nullptr;
@@ -706,6 +706,7 @@ pswa_status encode_impl(const pswa_model* model, const pswa_frame_desc* frame,
   zero_ints(ws.flag, 1, st);
   hyper_embed(d_hyper, frame->Hh, frame->Wh, x.Ch, model->w.hyperW, model->w.P4, frame->H,
               frame->W, x.d, ws.h, st);
+  null_row(ws.acc_kv, HW, model->w.knull, model->w.vnull, x.d, model->w.kv16, st);
   PassCtx c = frame_ctx(*frame);
   c.M = HW;
   c.h = ws.h;
@@ -871,6 +872,7 @@ pswa_status pswa_decode_begin(const pswa_model* model, const pswa_frame_desc* fr
   }
   hyper_embed(d_hyper, frame->Hh, frame->Wh, x.Ch, model->w.hyperW, model->w.P4, frame->H,
               frame->W, x.d, S->h, st);
+  null_row(S->acc_kv, HW, model->w.knull, model->w.vnull, x.d, model->w.kv16, st);
   if (frame->n_prev) {
     embed_prev(model, HW, HW, 0, d_prev, S->e_prev, st);
     for (int l = 0; l < x.L; ++l)

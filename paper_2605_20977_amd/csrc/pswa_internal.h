@@ -126,7 +126,8 @@ struct AttnArgs {
   const float* tkv;            // [2][HWt][2d] temporal K/V (or null)
   int kv16;                    // kv and tkv hold BF16 (element offsets as for FP32)
   const float* bias; int nbias;  // [heads][nbias]
-  const float* knull;          // accumulator null slot (null in layer mode)
+  const float* knull;          // accumulator null slot (null in layer mode): its key and value
+                               // are read from row HWt of kv (the LDS-staged form reads them here)
   const float* vnull;
   int include_self;            // layer mode: the query's own key
   int cycle;                   // 0: causal half-window; c: full window, masked by
@@ -140,6 +141,10 @@ __host__ __device__ inline int attn_slots(const AttnArgs& a) {
   return sp + (a.knull ? 1 : 0) + (a.tkv ? 2 * k1 * k1 : 0);
 }
 void attention_f32(const AttnArgs& a, hipStream_t s);
+// Row `row` of an accumulator K/V cache [.][2d] := the null key and value
+// (BF16 when kv16): the accumulator reads its null slot there.
+void null_row(float* acc_kv, size_t row, const float* knull, const float* vnull, int d, int kv16,
+              hipStream_t s);
 double attn_alg_bytes(const AttnArgs& a);
 
 // ----------------------------------------------------------------- misc
