@@ -30,8 +30,10 @@ frame); inputs resident in HBM, symbols read from device memory. Paths
 with <prec> one of fp32, bf16, fp8 (FP8 activations scaled per tensor from
 maxima calibrated on frames no path decodes). Persistent paths split their
 frames into groups that run behind their own barriers; the library's
-autotuner picks the grouping and row tile, and runs replay a captured HIP
-graph, unless told not to. One step = one pass of a path over its batch.
+autotuner picks the grouping and row tile (its winners on MI355X are kept in
+the package's tune cache; --tune-cache '' retunes), and runs replay a
+captured HIP graph, unless told not to. One step = one pass of a path over
+its batch.
 
 The headline `value` is the BF16 1080p batch; `paths` gives every path's rate
 and its ratio to plain FP32. After timing, frame 0 of the headline batch is
@@ -70,6 +72,7 @@ DEFAULT_PATHS = ("plain:fp32,batch32:bf16,batch256:bf16,batch32:fp8,mixed32:bf16
                  "student4k8:bf16,full4k8:bf16,encode:fp32,encode:bf16,bitstream:fp32,"
                  "cyclic32:bf16,ctplain:fp32,ctencode:fp32")
 BITS_BOUND = {"fp32": None, "bf16": 0.005, "fp8": 0.01}
+TUNE_CACHE = os.path.join(ROOT, "paper_2605_20977_amd", "tune_cache.jsonl")
 # The paper's own runtime comparison (Table 2; no GPU or CPU named).
 PAPER_CONTEXT = {
     "claim": "P-SWA entropy-model decoding 36 % faster than VCT (409 ms vs 301 ms per frame, "
@@ -94,7 +97,9 @@ def parse():
                     help="F frames per group, B blocks per group (default: autotuner)")
     ap.add_argument("--attention", choices=("auto", "staged", "global"), default="auto",
                     help="wavefront attention form (default: the autotuner's)")
-    ap.add_argument("--tune-cache", default=None, help="autotuner JSON-lines cache file")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE,
+                    help="autotuner JSON-lines cache file (default: the winners recorded on "
+                         "MI355X, shipped with the package; '' retunes)")
     ap.add_argument("--no-graph", action="store_true", help="issue runs without a HIP graph")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="first run one device-to-device copy of BYTES bytes (a known-size "
@@ -465,7 +470,7 @@ def main():
                 b.set_attention(args.attention == "staged")
             if not args.grid and not args.rtile and not args.groups:
                 print(f"{spec}: autotuning", file=sys.stderr, flush=True)
-                f, g, r, est = b.autotune(args.tune_cache, reps=2)
+                f, g, r, est = b.autotune(args.tune_cache or None, reps=2)
                 tuned = {"frames_per_group": f, "blocks_per_group": g, "rtile": r,
                          "est_ms": round(est, 2)}
             if not args.no_graph:

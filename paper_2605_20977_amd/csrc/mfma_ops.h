@@ -50,6 +50,11 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMBq = 32;        // largest A-row count of a low-precision tile
+// The persistent kernel stages all A rows of a phase at once (up to
+// kMBqWide of them) when K <= kWideMaxK, and runs each column tile against
+// all of them with its weights loaded once.
+constexpr int kMBqWide = 96;
+constexpr int kWideMaxK = 512;
 constexpr float kFp8Max = 448.0f;
 
 __host__ __device__ inline int qgemm_col_tiles(int N, int epi) {
@@ -404,6 +409,126 @@ __device__ __forceinline__ void gemm_tile_q(const GemmArgs& a, int bx, int by, u
   }
 }
 
+// A column tile against every row of a phase whose A rows (all M <= 96 of
+// them, K <= 512) the block has staged once in LDS (stage_a with R = 96):
+// each wave's weight rows for all k-steps (K / 32 <= kKchunk) are loaded
+// once into b (coltile_weights), and the R-row tiles 0 .. rt - 1 run with
+// them in turn. Every output's arithmetic is gemm_tile_q's: the same MFMA
+// chain over the k-steps in order from zero, the same row statistics,
+// scales and epilogue.
+template <int EPI, int PREC, int KS>
+__device__ __forceinline__ void coltile_weights(const GemmArgs& a, int bx,
+                                                typename QOp<PREC>::T (&b)[kKchunk]) {
+  constexpr bool PAIRED = paired_epi(EPI);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, kg = lane >> 4;
+  const int per_wave = PAIRED ? 8 : 16;
+  const int nbase = bx * kWaves * per_wave + wave * per_wave;
+  const int ksteps = KS ? KS : a.K / 32;
+  const void* wb;
+  int wn;
+  if (PAIRED) {
+    wn = min(nbase + (col & 7), a.N - 1);
+    wb = col < 8 ? a.Wq : a.W2q;
+  } else {
+    wn = min(nbase + col, a.N - 1);
+    wb = a.Wq;
+  }
+  const size_t wofs = wfrag_offset(wn, kg, ksteps);
+#pragma unroll
+  for (int u = 0; u < kKchunk; ++u)
+    if (u < ksteps) b[u] = load_w8<PREC>(wb, wofs + 256 * u);
+}
+template <int AK, bool RMS, int EPI, int PREC, int R, int KS>
+__device__ __forceinline__ void gemm_coltile_q(const GemmArgs& a, int bx, int rt, uint8_t* lds,
+                                               const float* rstd, const float* rmul,
+                                               const typename QOp<PREC>::T (&b)[kKchunk]) {
+  const uint8_t* smem = lds + kQRedBytes;
+  constexpr bool PAIRED = paired_epi(EPI);
+  constexpr int RB = R / 16;
+  constexpr int kMaxRt = kMBqWide / R;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int pitch = qgemm_pitch(a.K, PREC);
+  typedef typename QOp<PREC>::T WT;
+  const int col = lane & 15, kg = lane >> 4;
+  const int per_wave = PAIRED ? 8 : 16;
+  const int nbase = bx * kWaves * per_wave + wave * per_wave;
+  const int ksteps = KS ? KS : a.K / 32;
+  const float wsc = (PAIRED && col >= 8) ? a.w2scale : a.wscale;
+  const int n = nbase + col;
+#pragma unroll
+  for (int r = 0; r < kMaxRt; ++r) {
+    if (r >= rt) break;  // the same for the whole block
+    const int m0 = r * R;
+    const int rows = min(R, a.M - m0);
+    float rres[RB][4];
+    if constexpr (EPI == EPI_RESID) {
+      const int nc = min(n, a.N - 1);
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = m0 + min(16 * rb + 4 * kg + i, rows - 1);
+          rres[rb][i] = ldg(a.R + (size_t)map_row(a.rrow, row) * a.ldr + nc);
+        }
+    }
+    f32x4 acc[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) acc[rb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int u0 = 0; u0 < kKchunk; u0 += 4) {
+      WT af[RB][4];
+#pragma unroll
+      for (int u = u0; u < u0 + 4; ++u) {
+        if (u < ksteps) {
+          const int k = 32 * u + 8 * kg;
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+            af[rb][u - u0] = load_s8<PREC>(smem, (size_t)(m0 + 16 * rb + col) * pitch + k);
+        }
+      }
+#pragma unroll
+      for (int u = u0; u < u0 + 4; ++u) {
+        if (u < ksteps) {
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) acc[rb] = mfma_q(af[rb][u - u0], b[u], acc[rb]);
+        }
+      }
+    }
+    float vv[RB][4], v2v[RB][4];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int mrc = m0 + min(16 * rb + 4 * kg + i, rows - 1);
+        float v = acc[rb][i] * wsc;
+        if (PREC == PSWA_PREC_FP8) v = v / rmul[mrc];
+        if (RMS) v *= rstd[mrc];
+        vv[rb][i] = v;
+      }
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        v2v[rb][i] = PAIRED ? __shfl(vv[rb][i], (lane & ~15) | ((col + 8) & 15), 64) : 0.f;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int mr = 16 * rb + 4 * kg + i;
+        if (mr >= rows) continue;
+        if (PAIRED && col >= 8) continue;
+        if (n >= a.N) continue;
+        const int row = m0 + mr;
+        if constexpr (EPI == EPI_RESID)
+          stg(a.Y + (size_t)map_row(a.yrow, row) * a.ldy + n, rres[rb][i] + vv[rb][i]);
+        else
+          epilogue<EPI>(a, row, n, vv[rb][i], v2v[rb][i]);
+      }
+    }
+  }
+}
+
 // Column tiles of a small tile with CB groups per wave.
 __host__ __device__ inline int qgemm_col_tiles_cb(int N, int epi, int cb) {
   const int per = kWaves * (paired_epi(epi) ? 8 : 16) * cb;
@@ -516,6 +641,14 @@ __host__ __device__ inline int qgemm_big_col_tiles(int N, int epi, int cb) {
 
 // Runtime K to the compile-time k-step counts of the model shapes in use
 // (K = 128, 192, 384, 512, 1536); other K run the generic loop.
+#define PSWA_KS_DISPATCH_WIDE(K, CALL) \
+  switch ((K) / 32) {                  \
+    case 4: CALL(4); break;            \
+    case 6: CALL(6); break;            \
+    case 12: CALL(12); break;          \
+    case 16: CALL(16); break;          \
+    default: CALL(0); break;           \
+  }
 #define PSWA_KS_DISPATCH(K, CALL) \
   switch ((K) / 32) {             \
     case 4: CALL(4); break;       \

@@ -3,6 +3,8 @@
 // persistent_kernel.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device_ops.h"
 #include "mfma_ops.h"
 #include "network.h"
@@ -28,7 +30,8 @@ __global__ void k_zero_ints(int* p, int n) {
 size_t persistent_args_lds_offset(const NetDims& x, int prec, int rtile) {
   size_t b = x.cycle ? attn_lds_bytes(x.dh) : attn_stage_lds_bytes(x.dh);
   for (int K : {x.F, x.d, x.C}) {
-    const size_t g = prec ? qgemm_lds_bytes(K, prec, rtile) : gemm_lds_bytes(K);
+    size_t g = prec ? qgemm_lds_bytes(K, prec, rtile) : gemm_lds_bytes(K);
+    if (prec && rtile == 16 && K <= kWideMaxK) g = std::max(g, qgemm_lds_bytes(K, prec, kMBqWide));
     b = b > g ? b : g;
   }
   return (b + 255) & ~size_t(255);

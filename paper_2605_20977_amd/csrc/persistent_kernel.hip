@@ -93,11 +93,36 @@ __device__ __forceinline__ int xcd_id() {
 template <int AK, bool RMS, int EPI, int PREC, int R>
 __device__ __forceinline__ void gemm_phase(const GemmArgs& a, float4* smem4, float* rstd,
                                            int rank, int nb) {
-  __shared__ float rmul[kMBq];
+  __shared__ float rmul[kMBqWide];
   if constexpr (PREC != PSWA_PREC_F32) {
+    const int rt = qgemm_row_tiles(a.M, R);
+    // 16-row instances: when a phase has several row tiles (K <= 512, at
+    // most 96 rows) and the column tiles spread over the blocks as evenly as
+    // the tiles would, every row is staged once and each of the block's
+    // column tiles runs against all of them with its weights loaded once
+    // (measured faster there; slower in the 32-row instances, which keep the
+    // row-tile-major path below)
+    if constexpr (R == 16) {
+      const int ct = qgemm_col_tiles(a.N, EPI);
+      if (rt > 1 && a.M <= kMBqWide && a.K <= kWideMaxK &&
+          (ct + nb - 1) / nb * rt <= (ct * rt + nb - 1) / nb) {
+        uint8_t* lds = reinterpret_cast<uint8_t*>(smem4);
+        typedef typename QOp<PREC>::T WT;
+        auto none = [] {};
+        stage_a<AK, RMS, PREC, kMBqWide>(a, 0, a.M, lds + kQRedBytes, rstd, rmul, none);
+#define PSWA_COLS(KSV)                                                          \
+  for (int c = rank; c < ct; c += nb) {                                         \
+    WT w[kKchunk];                                                              \
+    coltile_weights<EPI, PREC, KSV>(a, c, w);                                   \
+    gemm_coltile_q<AK, RMS, EPI, PREC, R, KSV>(a, c, rt, lds, rstd, rmul, w);   \
+  }
+        PSWA_KS_DISPATCH_WIDE(a.K, PSWA_COLS)
+#undef PSWA_COLS
+        return;
+      }
+    }
     // tiles in row-tile-major order: a block re-stages A only when its next
     // tile starts a new row tile
-    const int rt = qgemm_row_tiles(a.M, R);
 #define PSWA_TILES(KSV)                                                                        \
   {                                                                                            \
     const int ct = qgemm_col_tiles(a.N, EPI);                                                  \
@@ -354,7 +379,7 @@ __device__ __forceinline__ void attn_phase_staged(const AttnArgs& a, float* smem
 template <int PREC, int DH, int R>
 __global__ void __launch_bounds__(kThreads) k_persistent(PersistArgs P) {
   extern __shared__ float4 smem4[];
-  __shared__ float rstd[kMBq];
+  __shared__ float rstd[kMBqWide];
   float* smem = reinterpret_cast<float*>(smem4);
   const int bm = __builtin_amdgcn_readfirstlane(ldg(P.block_map + blockIdx.x));
   const GroupInfo G = load_uniform(P.groups + (bm >> 16));
