@@ -213,3 +213,26 @@ def test_1080p_pframe_encode_matches_oracle(P, full):
     enc = P.pswa_encode_params(model, y, z, prev)
     ref = om.forward(cfg, Wt, y, z, prev)
     assert_matches_oracle(enc, ref, y, "1080p-P-enc")
+
+
+@pytest.mark.parametrize("prec,npv", [("fp32", 2), ("bf16", 0)])
+def test_1080p_bitstream_round_trip(P, full, prec, npv):
+    """A 1080p-shaped frame range-coded from its encode-form tables and
+    decoded step by step from the bytes (the host decoder in the loop at
+    every diagonal): the latent comes back exactly and every output equals
+    the encode form bit for bit; the stream stays within 2 % of the ideal
+    bits."""
+    cfg, Wt, model32 = full
+    model = model32 if prec == "fp32" else P.make_model(cfg, Wt, prec)
+    H, W = 68, 120
+    print(f"case 1080p bitstream {prec} P={npv}", flush=True)
+    y, z, prev = synth.frame_inputs(cfg, synth.FrameCfg(H, W, npv), 77 + npv)
+    enc = P.pswa_encode_params(model, y, z, prev)
+    data = P.pswa_range_encode(H, W, cfg.C, cfg.window, y, _np(enc["center"]),
+                               _np(enc["index"]))
+    dec = P.decode_frame(model, H, W, z, prev=prev, source="bitstream", src=data)
+    assert np.array_equal(_np(dec["latents"]), y)
+    assert_bitwise(enc, dec)
+    print(f"[1080p bitstream {prec}] {len(data)} bytes = {8 * len(data)} bits vs ideal "
+          f"{enc['total_bits']:.0f}", flush=True)
+    assert 8 * len(data) < 1.02 * enc["total_bits"] + 64
