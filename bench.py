@@ -69,7 +69,7 @@ HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp8": 5000.0}
 FP32_VECTOR_TFLOPS = 157.3
 METRIC = "decoded latent symbols/sec (1080p-shaped) vs plain FP32, at stated bits overhead"
-DEFAULT_PATHS = ("plain:fp32,batch32:bf16,batch256:bf16,batch512:bf16,batch32:fp8,mixed32:bf16,student4k:bf16,"
+DEFAULT_PATHS = ("plain:fp32,batch1:bf16,batch32:bf16,batch256:bf16,batch512:bf16,batch32:fp8,mixed32:bf16,student4k:bf16,"
                  "student4k8:bf16,full4k8:bf16,encode:fp32,encode:bf16,bitstream:fp32,"
                  "cyclic32:bf16,ctplain:fp32,ctencode:fp32")
 BITS_BOUND = {"fp32": None, "bf16": 0.005, "fp8": 0.01}
