@@ -164,7 +164,10 @@ size_t pswa_model_device_bytes(const pswa_model_desc* desc);
  * For PSWA_BF16 / PSWA_FP8_E4M3 the projection and MLP weights are rounded
  * once (RNE; FP8 saturating, one static scale per tensor) and stored in the
  * matrix-core fragment order (private to the library; the FP32 weights stay
- * row-major). */
+ * row-major); such models also keep every key/value cache (accumulator,
+ * layers, temporal) in BF16, rounded to nearest even from the projection
+ * output, with attention arithmetic in FP32 (state and workspace sizes are
+ * those of FP32 caches). */
 pswa_status pswa_model_create(const pswa_model_desc* desc, const float* h_blob,
                               size_t blob_floats, void* d_mem, size_t d_bytes,
                               void* stream, pswa_model** out);
@@ -335,9 +338,10 @@ int pswa_batch_rtile(const pswa_batch* batch);
 /* Autotuner: times every grouping candidate (frames per group and blocks
  * per group in powers of two) with 32-row tiles, then 16-row tiles on the
  * best grouping (BF16/FP8), then the other attention form on the winner
- * (pswa_batch_set_attention), each on a window of the widest global steps
- * (reps timed runs, median), and keeps the fastest. With cache_path, a
- * result for the same device, model and frame mix is read from that file
+ * (pswa_batch_set_attention; FP32 caches only), each on a window of the
+ * widest global steps (reps timed runs, median), and keeps the fastest. With
+ * cache_path, a result for the same device, model shape, schedule,
+ * precision and frame mix is read from that file
  * (JSON lines) instead of timing, and new results are appended. Reports the
  * choice and the estimated whole-run time. Waits. */
 pswa_status pswa_batch_autotune(pswa_batch* batch, const char* cache_path, int reps,
@@ -362,7 +366,8 @@ pswa_status pswa_batch_set_xcd_barrier(pswa_batch* batch, int on);
  * of a few heads at a time, the queries and the window biases) in LDS with
  * direct global-to-LDS loads and computes the rows' items from LDS; 0 lets
  * every lane load its key's rows from global memory. The cyclic schedule
- * rejects staged != 0 (PSWA_E_UNSUPPORTED). Drops a captured graph.
+ * and models with BF16 key/value caches (BF16, FP8) reject staged != 0
+ * (PSWA_E_UNSUPPORTED). Drops a captured graph.
  * pswa_batch_attention returns the current form (-1 for a null batch). */
 pswa_status pswa_batch_set_attention(pswa_batch* batch, int staged);
 int pswa_batch_attention(const pswa_batch* batch);
