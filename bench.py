@@ -20,11 +20,12 @@ frame); inputs resident in HBM, symbols read from device memory. Paths
                       alternating) decoded by the student and by the full
                       model (the student's speed-up);
   encode:<prec>    -- the parallel encode form of one 1080p I-frame;
-  ctplain:<prec>, ctencode:<prec> -- the plain and encode paths of a model
-                      of the same spatial widths whose head is the Channel
-                      Transformer (4 channel groups of 48 symbols, width 512,
-                      2 blocks) with grouped heads: each diagonal's groups
-                      are predicted one after the other;
+  ctplain:<prec>, ctencode:<prec>, ctbatch<N>:fp32 -- the plain, encode and
+                      persistent batch paths of a model of the same spatial
+                      widths whose head is the Channel Transformer (4
+                      channel groups of 48 symbols, width 512, 2 blocks) with
+                      grouped heads: each diagonal's groups are predicted one
+                      after the other;
   bitstream:<prec> -- one 1080p I-frame decoded step by step from its range-
                       coded bitstream (host range decoder, one thread, in
                       the loop at every diagonal);
@@ -71,7 +72,7 @@ FP32_VECTOR_TFLOPS = 157.3
 METRIC = "decoded latent symbols/sec (1080p-shaped) vs plain FP32, at stated bits overhead"
 DEFAULT_PATHS = ("plain:fp32,batch1:bf16,batch32:bf16,batch256:bf16,batch512:bf16,batch32:fp8,mixed32:bf16,student4k:bf16,"
                  "student4k8:bf16,full4k8:bf16,encode:fp32,encode:bf16,bitstream:fp32,"
-                 "cyclic32:bf16,ctplain:fp32,ctencode:fp32")
+                 "cyclic32:bf16,ctplain:fp32,ctencode:fp32,ctbatch32:fp32")
 BITS_BOUND = {"fp32": None, "bf16": 0.005, "fp8": 0.01}
 TUNE_CACHE = os.path.join(ROOT, "paper_2605_20977_amd", "tune_cache.jsonl")
 # The paper's own runtime comparison (Table 2; no GPU or CPU named).
@@ -328,7 +329,7 @@ def batch_frames(synth, cfg, kind, n, dseed):
     from concurrent.futures import ThreadPoolExecutor
 
     def one(k):
-        if kind in ("batch", "cyclic"):
+        if kind in ("batch", "cyclic", "ctbatch"):
             fc, seed = synth.FrameCfg(68, 120), dseed + 1000 * k
         elif kind in ("student4k", "full4k"):
             fc, seed = synth.FrameCfg(135, 240, 2 if k % 2 else 0), \
@@ -452,8 +453,8 @@ def main():
                            "round_trip_exact": bool(torch.equal(out["y"], yd))}
             runners[spec] = bits_dec
         else:
-            base = next(b_ for b_ in ("batch", "mixed", "cyclic", "student4k", "full4k")
-                        if kind.startswith(b_))
+            base = next(b_ for b_ in ("batch", "mixed", "cyclic", "student4k", "full4k",
+                                      "ctbatch") if kind.startswith(b_))
             n = int(kind[len(base):] or 2)
             frames = batch_frames(synth, mc, base, n, dseed)
             nsym = sum(f["latents"].size for f in frames)

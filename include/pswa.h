@@ -90,9 +90,11 @@ typedef struct {
    * reads groups 0..g only, then a per-group pre-norm SwiGLU. Group g's mean
    * and scale therefore depend on the symbols of groups < g of the same
    * position only. The channel transformer runs in FP32 in every precision;
-   * models with channel groups serve pswa_encode_params and the
-   * device-source decode (bitstream decoding, the batched decode and
-   * training return PSWA_E_UNSUPPORTED). */
+   * models with channel groups serve pswa_encode_params, the device-source
+   * decode and (FP32 models) the batched decode, where each step runs the
+   * input map of every group, then group by group the latent map, the blocks
+   * and the group's head (bitstream decoding, the batched decode of BF16 /
+   * FP8 models and training return PSWA_E_UNSUPPORTED). */
   int32_t ch_groups, ch_d, ch_L, ch_ratio;
 } pswa_model_desc;
 
@@ -378,7 +380,8 @@ pswa_status pswa_batch_set_spin_limit(pswa_batch* batch, int64_t spins);
  * persistent kernel (rank 0 of group 0) writes the device wall clock
  * (100 MHz) when it reaches and when it leaves each of its group's barriers:
  * d_trace[2k] and d_trace[2k + 1] for barrier k, for 2k + 1 < n (device
- * int64). Barriers per step: 2 + 5 L + 4. n = 0 turns the trace off. */
+ * int64). Barriers per step: 2 + 5 L + 4 (with channel groups N and
+ * blocks B: 2 + 5 L + 2 + 1 + N (3 + 4 B) - 1). n = 0 turns the trace off. */
 pswa_status pswa_batch_trace(pswa_batch* batch, int64_t* d_trace, int n);
 void pswa_batch_destroy(pswa_batch* batch);
 

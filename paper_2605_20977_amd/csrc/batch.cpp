@@ -153,7 +153,7 @@ void lay_out(const NetDims& x, const Plan& p, int n, void* base, pswa_batch* b) 
   b->block_map = L.take<int>(kMaxBlocks);
   b->xcd_tab = L.take<int>(kMaxBlocks);
   b->sum = L.take<float>(64);
-  b->gtab = L.take<GemmArgs>(p.steps_cap * gemm_phases(x.L));
+  b->gtab = L.take<GemmArgs>(p.steps_cap * gemm_phases(x.L, ct_phases(x)));
   b->atab = L.take<AttnArgs>(p.steps_cap * attn_phases(x.L));
   b->stab = L.take<SymArgs>(p.steps_cap);
   b->bytes = L.used;
@@ -161,9 +161,9 @@ void lay_out(const NetDims& x, const Plan& p, int n, void* base, pswa_batch* b) 
 
 pswa_status check_frames(const pswa_model* m, int n, const pswa_batch_frame* fr) {
   if (!m) return fail(PSWA_E_ARG, "model is null");
-  if (m->x.cg)
+  if (m->x.cg && m->w.prec != PSWA_PREC_F32)
     return fail(PSWA_E_UNSUPPORTED,
-                "the persistent decode of models with channel groups is not built");
+                "the persistent decode of models with channel groups runs FP32 models only");
   if (n < 1 || !fr) return fail(PSWA_E_ARG, "need at least one frame");
   for (int f = 0; f < n; ++f) {
     std::string why;
@@ -200,6 +200,13 @@ PassCtx batch_ctx(const pswa_batch* b, const GroupPlan& g) {
   c.e = b->a.e + r * x.d;
   c.t1 = b->a.t1 + r * x.d;
   c.hmid = b->a.hmid + r * x.F;
+  if (x.cg) {
+    c.ct_c = b->a.ct_c + r * x.cd;
+    c.ct_u = b->a.ct_u + r * x.cd;
+    c.ct_u_stride = b->rows_cap * x.cd;  // blocks of [rows_cap][cd]
+    c.ct_h = b->a.ct_h + r * x.cFg;
+    c.ct_t1 = b->a.ct_t1 + r * x.cdg;
+  }
   c.mean = b->mean; c.scale = b->scale; c.bits = b->bits;
   c.center = b->center; c.index = b->index;
   c.center_c = nullptr; c.index_c = nullptr;
@@ -246,6 +253,27 @@ void build_tables(const pswa_batch* b, const GroupPlan& g, std::vector<GemmArgs>
     gt->push_back(h2);
     gt->push_back(args_embed(x, w, c));
     gt->push_back(args_acc_kv(x, w, c));
+    if (x.cg) {  // the Channel Transformer's entries (the head entries above go unused)
+      GemmArgs in = args_ct_in(x, w, c, 0);  // every group's input map at once
+      in.N = x.cd;
+      gt->push_back(in);
+      for (int g = 0; g < x.cg; ++g) {
+        gt->push_back(g > 0 ? args_ct_latent(x, w, c, g) : gemm_base(0, x.cdg, x.cCg, R_HEAD1));
+        for (int bl = 0; bl < x.cL; ++bl) {
+          gt->push_back(args_ct_rms(x, w, c, bl, g));
+          gt->push_back(args_ct_mix(x, w, c, bl, g));
+          gt->push_back(args_ct_gateup(x, w, c, bl, g));
+          gt->push_back(args_ct_down(x, w, c, bl, g));
+        }
+        gt->push_back(args_ct_head1(x, w, c, g));
+        GemmArgs ch2 = args_ct_head2(x, w, c, g);  // also gathers the group's symbols
+        ch2.head.ysrc = c.ysrc;
+        ch2.head.src_compact = c.src_compact;
+        ch2.head.ydec = c.ydec;
+        ch2.head.bits = c.bits;
+        gt->push_back(ch2);
+      }
+    }
     stb->push_back(SymArgs{c.M, x.C, c.gpos, c.ysrc, c.src_compact, c.ydec, c.mean, c.scale,
                            c.bits});
   }
@@ -265,6 +293,8 @@ PersistArgs persist_args(const pswa_batch* b) {
   P.xcd_tab = b->xcd_tab;
   P.xcd_local = b->xcd_local;
   P.cycle = b->model->x.cycle;
+  P.ct_groups = b->model->x.cg;
+  P.ct_blocks = b->model->x.cL;
   P.attn_staged = b->attn_staged && staged_ok(b->model);
   return P;
 }
@@ -332,7 +362,7 @@ pswa_status apply_groups(pswa_batch* b, int fpg, int bpg, hipStream_t st) {
   std::vector<AttnArgs> at;
   std::vector<SymArgs> stb;
   std::vector<GroupInfo> gi(ng);
-  const int na = attn_phases(x.L), ngm = gemm_phases(x.L);
+  const int na = attn_phases(x.L), ngm = gemm_phases(x.L, ct_phases(x));
   for (int k = 0; k < ng; ++k) {
     const GroupPlan& g = groups[k];
     build_tables(b, g, &gt, &at, &stb);
@@ -417,13 +447,14 @@ pswa_status run(pswa_batch* b, hipStream_t st) {
 void count_work(pswa_batch* b, const std::vector<GemmArgs>& gt,
                 const std::vector<AttnArgs>& at, const std::vector<SymArgs>& stb) {
   const NetDims& x = b->model->x;
-  const int ng = gemm_phases(x.L), na = attn_phases(x.L);
+  // (the spatial network's entries; Channel Transformer entries are not counted)
+  const int ng = gemm_phases(x.L), ngs = gemm_phases(x.L, ct_phases(x)), na = attn_phases(x.L);
   static const Epi epis_head[4] = {EPI_SILU, EPI_HEAD, EPI_STORE, EPI_STORE};
   double by = 0, fl = 0;
   for (size_t t = 0; t < stb.size(); ++t) {
     if (stb[t].M == 0) continue;
     for (int k = 0; k < ng; ++k) {
-      const GemmArgs& a = gt[(size_t)t * ng + k];
+      const GemmArgs& a = gt[(size_t)t * ngs + k];
       Epi e;
       if (k == 0) e = EPI_STORE;
       else if (k == 1) e = EPI_RESID;

@@ -137,6 +137,21 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
+// RMSNorm of one row's K-value slice x (wave per row): lane l sums x[k]^2
+// for k = l, l + 64, ... with fmaf in order, then a fixed xor tree;
+// y[k] = x[k] * rs * gain[k].
+__device__ __forceinline__ void group_rms_row(const float* x, const float* gain, float* y, int K) {
+  const int lane = threadIdx.x & 63;
+  float ss = 0.f;
+  for (int k = lane; k < K; k += 64) {
+    const float v = ldg(x + k);
+    ss = fmaf(v, v, ss);
+  }
+  ss = wave_sum(ss);
+  const float rs = 1.0f / sqrtf(ss / float(K) + kEps);
+  for (int k = lane; k < K; k += 64) stg(y + k, ldg(x + k) * rs * ldg(gain + k));
+}
+
 // Centre and table index of one symbol, one rounding per operation, so the
 // decision equals the documented float32 formula.
 __device__ __forceinline__ void select_table(float mu, float lsig, float ln_smin, float inv_delta,

@@ -92,15 +92,9 @@ __global__ void k_gather_symbols(const int32_t* src, int compact, const int* pos
 // over elements l, l + 64, ... in order, then a fixed xor tree.
 __global__ void __launch_bounds__(256) k_group_rms(const float* X, int ldx, int M, int K, int col0,
                                                    const float* gain, float* Y, int ldy) {
-  const int lane = threadIdx.x & 63;
   const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (m >= M) return;
-  const float* x = X + (size_t)m * ldx + col0;
-  float ss = 0.f;
-  for (int k = lane; k < K; k += 64) ss = fmaf(x[k], x[k], ss);
-  ss = wave_sum(ss);
-  const float rs = 1.0f / sqrtf(ss / float(K) + kEps);
-  for (int k = lane; k < K; k += 64) Y[(size_t)m * ldy + col0 + k] = x[k] * rs * gain[col0 + k];
+  group_rms_row(X + (size_t)m * ldx + col0, gain + col0, Y + (size_t)m * ldy + col0, K);
 }
 
 __global__ void k_symbol_bits(const int* pos, int M, int C, const int32_t* ydec,

@@ -92,7 +92,8 @@ struct PassCtx {
   size_t tkv_stride;
   float *x, *q, *att, *e, *t1, *hmid;  // row activations
   float *ct_c, *ct_u, *ct_h, *ct_t1;   // Channel Transformer rows: stream [M][cd], block
-                                       // inputs [cL][M][cd], SwiGLU [M][cFg], head [M][cdg]
+                                       // inputs [cL][.][cd], SwiGLU [M][cFg], head [M][cdg]
+  size_t ct_u_stride;                  // floats between ct_u's blocks (0: M * cd)
   float *mean, *scale, *bits;          // [HWt][C]
   int32_t* center;
   uint16_t* index;
@@ -265,10 +266,23 @@ __host__ __device__ inline GemmArgs args_ct_latent(const NetDims& x, const DevWe
   a.R = c.ct_c + (size_t)g * x.cdg; a.ldr = x.cd; a.Y = c.ct_c + (size_t)g * x.cdg; a.ldy = x.cd;
   return a;
 }
+// Block b's per-group normalized inputs.
+__host__ __device__ inline float* ct_u_block(const NetDims& x, const PassCtx& c, int b) {
+  return c.ct_u + (size_t)b * (c.ct_u_stride ? c.ct_u_stride : (size_t)c.M * x.cd);
+}
+// Block b's RMSNorm of group g's slice of the stream, as a row description:
+// rows M, slice K = cdg at column col0 (in n), input X, gain, output Y.
+__host__ __device__ inline GemmArgs args_ct_rms(const NetDims& x, const DevWeights& w,
+                                                const PassCtx& c, int b, int g) {
+  GemmArgs a = gemm_base(c.M, x.cdg, x.cdg, R_OTHER);
+  a.X = c.ct_c; a.ldx = x.cd; a.gain = w.ct.g1[b]; a.Y = ct_u_block(x, c, b); a.ldy = x.cd;
+  a.nsplit = g * x.cdg;  // the slice's first column
+  return a;
+}
 __host__ __device__ inline GemmArgs args_ct_mix(const NetDims& x, const DevWeights& w,
                                                 const PassCtx& c, int b, int g) {
   GemmArgs a = gemm_base(c.M, x.cdg, (g + 1) * x.cdg, R_HEAD1);
-  a.X = c.ct_u + (size_t)b * c.M * x.cd; a.ldx = x.cd; a.W = w.ct.m_g[b][g];
+  a.X = ct_u_block(x, c, b); a.ldx = x.cd; a.W = w.ct.m_g[b][g];
   a.R = c.ct_c + (size_t)g * x.cdg; a.ldr = x.cd; a.Y = c.ct_c + (size_t)g * x.cdg; a.ldy = x.cd;
   return a;
 }

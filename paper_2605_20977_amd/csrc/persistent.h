@@ -37,7 +37,7 @@ struct SymArgs {
 // one round of loads; each phase then reads its entry from LDS into scalar
 // registers, so no phase waits on device memory for its arguments.
 struct GroupInfo {
-  const GemmArgs* gtab;    // [T][6 + 4L]
+  const GemmArgs* gtab;    // [T][6 + 4L (+ ct_phases)]
   const AttnArgs* atab;    // [T][1 + L]
   const SymArgs* stab;     // [T]
   int T;                   // steps of the group's frames
@@ -58,6 +58,7 @@ struct PersistArgs {
   int xcd_local;           // allow the one-XCD barrier for groups that qualify
   int args_lds_off;        // byte offset of the step's argument copy in dynamic LDS
   int cycle;               // the model's schedule (0: wavefront)
+  int ct_groups, ct_blocks;  // Channel Transformer (FP32 instances; 0: the plain head)
   int attn_staged;         // wavefront attention from LDS-staged window tiles (else
                            // every key read by its lane from global memory)
 };
@@ -75,8 +76,17 @@ struct PersistArgs {
 #define PSWA_PERSISTENT_NAME_X(P_, D_, R_) PSWA_PERSISTENT_NAME(P_, D_, R_)
 #define PSWA_PERSISTENT_GETTER(P_, D_, R_) const void* PSWA_PERSISTENT_NAME_X(P_, D_, R_)()
 
-__host__ __device__ inline int gemm_phases(int L) { return 6 + 4 * L; }
+// GEMM table entries of a step: the spatial network's 6 + 4L, then for
+// models with channel groups `ct` more (ct_phases).
+__host__ __device__ inline int gemm_phases(int L, int ct = 0) { return 6 + 4 * L + ct; }
 __host__ __device__ inline int attn_phases(int L) { return 1 + L; }
+// Channel Transformer entries of a step (FP32 models): the input map of
+// every group at once, then per group the latent map, per block the
+// per-group RMSNorm (as a row description), mixing, gate/up and down, and
+// the group's head W1 and W2.
+__host__ __device__ inline int ct_phases(const NetDims& x) {
+  return x.cg ? 1 + x.cg * (3 + 4 * x.cL) : 0;
+}
 
 // Dynamic LDS of the kernel: the phases' work area, then the step's
 // argument copy at persistent_args_lds_offset().
@@ -84,10 +94,12 @@ size_t persistent_lds_bytes(const NetDims& x, int prec, int rtile);
 size_t persistent_args_lds_offset(const NetDims& x, int prec, int rtile);
 // Bytes of one step's argument copy, and its parts' offsets within it.
 __host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
-__host__ __device__ inline size_t step_args_gemm_bytes(int L) { return align16(gemm_phases(L) * sizeof(GemmArgs)); }
+__host__ __device__ inline size_t step_args_gemm_bytes(int L, int ct = 0) {
+  return align16(gemm_phases(L, ct) * sizeof(GemmArgs));
+}
 __host__ __device__ inline size_t step_args_attn_bytes(int L) { return align16(attn_phases(L) * sizeof(AttnArgs)); }
-__host__ __device__ inline size_t step_args_bytes(int L) {
-  return step_args_gemm_bytes(L) + step_args_attn_bytes(L) + align16(sizeof(SymArgs));
+__host__ __device__ inline size_t step_args_bytes(int L, int ct = 0) {
+  return step_args_gemm_bytes(L, ct) + step_args_attn_bytes(L) + align16(sizeof(SymArgs));
 }
 // Largest grid whose blocks can all be resident at once (0 on error).
 int persistent_max_grid(const NetDims& x, int prec, int rtile);

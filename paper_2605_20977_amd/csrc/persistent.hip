@@ -38,7 +38,7 @@ size_t persistent_args_lds_offset(const NetDims& x, int prec, int rtile) {
 }
 
 size_t persistent_lds_bytes(const NetDims& x, int prec, int rtile) {
-  return persistent_args_lds_offset(x, prec, rtile) + step_args_bytes(x.L);
+  return persistent_args_lds_offset(x, prec, rtile) + step_args_bytes(x.L, ct_phases(x));
 }
 
 // The instance for a model: projection arithmetic, head size and (for

@@ -179,6 +179,16 @@ __device__ __forceinline__ void attn_phase(const AttnArgs& a, int rank, int nb) 
   }
 }
 
+// Rows of a per-group RMSNorm (a Channel Transformer row description: a.M
+// rows, slice of a.K values at column a.nsplit of X, gain and Y) spread over
+// the group's waves; the row arithmetic is the per-launch kernel's.
+__device__ __forceinline__ void rms_phase(const GemmArgs& a, int rank, int nb) {
+  const int nw = nb * kWaves;
+  for (int m = rank * kWaves + (int)(threadIdx.x >> 6); m < a.M; m += nw)
+    group_rms_row(a.X + (size_t)m * a.ldx + a.nsplit, a.gain + a.nsplit,
+                  a.Y + (size_t)m * a.ldy + a.nsplit, a.K);
+}
+
 // Direct global-to-LDS loads (gfx950): every active lane moves `bytes` from
 // its own global address to lds + lane * bytes (lds: the same in the wave).
 __device__ __forceinline__ void lds_load16(const float* src, float* lds) {
@@ -385,7 +395,10 @@ __global__ void __launch_bounds__(kThreads) k_persistent(PersistArgs P) {
   const GroupInfo G = load_uniform(P.groups + (bm >> 16));
   const int rank = bm & 0xffff, nb = G.nblocks;
   const bool tracer = P.trace && bm == 0 && threadIdx.x == 0;
-  const int L = P.L, ng = 6 + 4 * L, na = 1 + L;
+  const int L = P.L, na = 1 + L;
+  // Channel Transformer entries (FP32 instances only)
+  const int ctp = PREC == PSWA_PREC_F32 && P.ct_groups ? 1 + P.ct_groups * (3 + 4 * P.ct_blocks) : 0;
+  const int ng = gemm_phases(L, ctp);
   // wavefront schedule: attention from LDS-staged window tiles, if chosen
   const bool staged = P.cycle == 0 && P.attn_staged;
   const int t_end = min(P.t_end, G.T);
@@ -418,8 +431,8 @@ __global__ void __launch_bounds__(kThreads) k_persistent(PersistArgs P) {
   // the step's argument copy in LDS, after the phases' work area
   uint8_t* abase = reinterpret_cast<uint8_t*>(smem4) + P.args_lds_off;
   GemmArgs* g = reinterpret_cast<GemmArgs*>(abase);
-  AttnArgs* at = reinterpret_cast<AttnArgs*>(abase + step_args_gemm_bytes(L));
-  SymArgs* ss = reinterpret_cast<SymArgs*>(abase + step_args_gemm_bytes(L) +
+  AttnArgs* at = reinterpret_cast<AttnArgs*>(abase + step_args_gemm_bytes(L, ctp));
+  SymArgs* ss = reinterpret_cast<SymArgs*>(abase + step_args_gemm_bytes(L, ctp) +
                                            step_args_attn_bytes(L));
 
   for (int t = P.t_begin; t < t_end; ++t) {
@@ -462,11 +475,49 @@ __global__ void __launch_bounds__(kThreads) k_persistent(PersistArgs P) {
       gemm_phase<A_FLOAT, false, EPI_RESID, PREC, R>(lds_uniform(g + 5 + 4 * l), smem4, rstd, rank, nb);
       PSWA_SYNC
     }
-    gemm_phase<A_FLOAT, true, EPI_SILU, PREC, R>(lds_uniform(g + 2 + 4 * L), smem4, rstd, rank, nb);
-    PSWA_SYNC
-    // head W2: mean, scale, CDF selection, and the step's symbols and bits
-    gemm_phase<A_FLOAT, false, EPI_HEAD, PREC, R>(lds_uniform(g + 3 + 4 * L), smem4, rstd, rank, nb);
-    PSWA_SYNC
+    bool plain_head = true;
+    if constexpr (PREC == PSWA_PREC_F32) {
+      if (P.ct_groups) {
+        // Channel Transformer: every group's input map, then group by group
+        // the latent map (groups > 0), the blocks and the group's head, whose
+        // epilogue gathers the group's symbols for the next group
+        plain_head = false;
+        const GemmArgs* ct = g + gemm_phases(L);
+        gemm_phase<A_FLOAT, true, EPI_STORE, PREC, R>(lds_uniform(ct), smem4, rstd, rank, nb);
+        PSWA_SYNC
+        int e = 1;
+        for (int gi = 0; gi < P.ct_groups; ++gi) {
+          if (gi > 0) {
+            gemm_phase<A_INT, false, EPI_RESID, PREC, R>(lds_uniform(ct + e), smem4, rstd, rank, nb);
+            PSWA_SYNC
+          }
+          ++e;
+          for (int bl = 0; bl < P.ct_blocks; ++bl) {
+            rms_phase(lds_uniform(ct + e), rank, nb);
+            PSWA_SYNC
+            gemm_phase<A_FLOAT, false, EPI_RESID, PREC, R>(lds_uniform(ct + e + 1), smem4, rstd, rank, nb);
+            PSWA_SYNC
+            gemm_phase<A_FLOAT, true, EPI_SWIGLU, PREC, R>(lds_uniform(ct + e + 2), smem4, rstd, rank, nb);
+            PSWA_SYNC
+            gemm_phase<A_FLOAT, false, EPI_RESID, PREC, R>(lds_uniform(ct + e + 3), smem4, rstd, rank, nb);
+            PSWA_SYNC
+            e += 4;
+          }
+          gemm_phase<A_FLOAT, true, EPI_SILU, PREC, R>(lds_uniform(ct + e), smem4, rstd, rank, nb);
+          PSWA_SYNC
+          gemm_phase<A_FLOAT, false, EPI_HEAD, PREC, R>(lds_uniform(ct + e + 1), smem4, rstd, rank, nb);
+          PSWA_SYNC
+          e += 2;
+        }
+      }
+    }
+    if (plain_head) {
+      gemm_phase<A_FLOAT, true, EPI_SILU, PREC, R>(lds_uniform(g + 2 + 4 * L), smem4, rstd, rank, nb);
+      PSWA_SYNC
+      // head W2: mean, scale, CDF selection, and the step's symbols and bits
+      gemm_phase<A_FLOAT, false, EPI_HEAD, PREC, R>(lds_uniform(g + 3 + 4 * L), smem4, rstd, rank, nb);
+      PSWA_SYNC
+    }
     gemm_phase<A_INT, false, EPI_STORE, PREC, R>(lds_uniform(g + 4 + 4 * L), smem4, rstd, rank, nb);
     PSWA_SYNC
     gemm_phase<A_FLOAT, true, EPI_STORE, PREC, R>(lds_uniform(g + 5 + 4 * L), smem4, rstd, rank, nb);

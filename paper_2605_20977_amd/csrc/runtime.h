@@ -93,8 +93,7 @@ inline void run_ct_group(const pswa_model* m, const PassCtx& c, int g, hipStream
   gemm_run(A_FLOAT, true, EPI_STORE, args_ct_in(x, w, c, g), st);
   if (g > 0) gemm_run(A_INT, false, EPI_RESID, args_ct_latent(x, w, c, g), st);
   for (int b = 0; b < x.cL; ++b) {
-    group_rmsnorm(c.ct_c, x.cd, c.M, x.cdg, g * x.cdg, w.ct.g1[b], c.ct_u + (size_t)b * c.M * x.cd,
-                  x.cd, st);
+    group_rmsnorm(c.ct_c, x.cd, c.M, x.cdg, g * x.cdg, w.ct.g1[b], ct_u_block(x, c, b), x.cd, st);
     gemm_run(A_FLOAT, false, EPI_RESID, args_ct_mix(x, w, c, b, g), st);
     gemm_run(A_FLOAT, true, EPI_SWIGLU, args_ct_gateup(x, w, c, b, g), st);
     gemm_run(A_FLOAT, false, EPI_RESID, args_ct_down(x, w, c, b, g), st);

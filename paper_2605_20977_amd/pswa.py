@@ -486,7 +486,7 @@ class Batch:
         self._frames = arr
         nb = _lib.pswa_batch_workspace_bytes(model.handle, len(frames), arr)
         if nb == 0:
-            raise PswaError(-2, "invalid batch")
+            raise PswaError(-2, "invalid batch: " + _lib.pswa_last_error().decode())
         self.ws = torch.empty(nb, dtype=torch.uint8, device=dev)
         h = C.c_void_p()
         _check(_lib.pswa_batch_create(model.handle, len(frames), arr, grid, _ptr(self.ws), nb,

@@ -10,8 +10,12 @@
   encode;
 * a BF16 model with channel groups (spatial projections on MFMA, the channel
   transformer in FP32): step decode bit-identical to encode, error bounded;
-* what is not built is refused: the batched decode, bitstream decoding and
-  training of models with channel groups.
+* the persistent batched decode of FP32 models with channel groups (the
+  channel groups as extra phases of each step): every frame bit-identical to
+  its step decode, across groupings, I- and P-frames and frames narrower
+  than a window, and at 1080p to the encode form;
+* what is not built is refused: the batched decode of BF16/FP8 models with
+  channel groups, bitstream decoding and training.
 """
 import numpy as np
 import pytest
@@ -99,13 +103,61 @@ def test_bf16_ct_decode_equals_encode(P):
     assert emu <= 0.05 and esg <= 0.02
 
 
+def _frames(cfg, sizes, seed):
+    out = []
+    for k, (H, W, npv) in enumerate(sizes):
+        y, z, prev = synth.frame_inputs(cfg, synth.FrameCfg(H, W, npv), seed + k)
+        out.append({"latents": y, "hyper": z, "prev": prev})
+    return out
+
+
+def test_ct_batch_equals_step_decode(P):
+    cfg = synth.TINY_CT
+    Wt = synth.model_weights(cfg, 25)
+    model = P.Model(cfg, Wt)
+    sizes = [(16, 16, 0), (13, 21, 2), (5, 3, 0), (1, 7, 2), (9, 2, 0), (12, 4, 2)]
+    fr = _frames(cfg, sizes, 300)
+    ref = [P.decode_frame(model, f["latents"].shape[0], f["latents"].shape[1], f["hyper"],
+                          prev=f["prev"], source="device", src=f["latents"]) for f in fr]
+    b = P.Batch(model, fr)
+    for fpg, bpg in ((1, 1), (2, 4), (6, 16), (1, 8)):
+        print(f"case CT batch groups {fpg}x{bpg}", flush=True)
+        b.set_groups(fpg, bpg)
+        b.run()
+        b.check()
+        for k in range(len(fr)):
+            _same(b.outputs(k), ref[k], f"CT batch {fpg}x{bpg} frame {k}")
+    b.capture()
+    for rep in range(2):
+        b.run()
+        b.check()
+        for k in range(len(fr)):
+            _same(b.outputs(k), ref[k], f"CT batch graph replay {rep} frame {k}")
+
+
+def test_ct_batch_1080p_equals_encode(P):
+    cfg = synth.FULL_CT
+    Wt = synth.model_weights(cfg, 26)
+    model = P.Model(cfg, Wt)
+    fr = _frames(cfg, [(68, 120, 0), (68, 120, 2)], 310)
+    ref = [P.pswa_encode_params(model, f["latents"], f["hyper"], f["prev"]) for f in fr]
+    print("case CT batch 1080p I + P", flush=True)
+    b = P.Batch(model, fr)
+    b.set_groups(1, 8)
+    b.run()
+    b.check()
+    for k in range(len(fr)):
+        _same(b.outputs(k), ref[k], f"CT batch 1080p frame {k}")
+
+
 def test_unbuilt_ct_paths_are_refused(P):
     cfg = synth.TINY_CT
     Wt = synth.model_weights(cfg, 24)
     model = P.Model(cfg, Wt)
     y, z, prev = synth.frame_inputs(cfg, synth.FrameCfg(8, 8, 0), 96)
-    with pytest.raises(P.PswaError):
-        P.Batch(model, [{"latents": y, "hyper": z, "prev": None}])
+    with pytest.raises(P.PswaError) as e:
+        P.Batch(P.Model(cfg, Wt, "bf16"), [{"latents": y, "hyper": z, "prev": None}])
+    assert "FP32 models only" in str(e.value)
     with pytest.raises(P.PswaError) as e:
         P.pswa_decode_begin(model, 8, 8, z, source="bitstream", src=b"\x00" * 16)
     assert e.value.name == "E_UNSUPPORTED"
