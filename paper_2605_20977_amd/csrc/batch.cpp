@@ -621,7 +621,9 @@ pswa_status pswa_batch_autotune(pswa_batch* b, const char* cache_path, int reps,
   PSWA_HIP_TRY(hipGetDeviceProperties(&prop, dev));
   std::ostringstream key;
   key << prop.gcnArchName << "|L" << x.L << ".d" << x.d << ".h" << x.heads << ".r" << x.r
-      << ".F" << x.F << ".C" << x.C << ".p" << m->w.prec << ".c" << x.cycle << "|";
+      << ".F" << x.F << ".C" << x.C << ".p" << m->w.prec << ".c" << x.cycle;
+  if (x.cg) key << ".g" << x.cg << "x" << x.cd << "x" << x.cL << "x" << x.cFg;
+  key << "|";
   for (const FrameInfo& f : b->finfo) key << f.H << "x" << f.W << (f.n_prev ? "P" : "I") << ",";
   if (cache_path) {
     std::ifstream in(cache_path);
