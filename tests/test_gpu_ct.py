@@ -121,12 +121,14 @@ def test_ct_batch_equals_step_decode(P):
                           prev=f["prev"], source="device", src=f["latents"]) for f in fr]
     b = P.Batch(model, fr)
     for fpg, bpg in ((1, 1), (2, 4), (6, 16), (1, 8)):
-        print(f"case CT batch groups {fpg}x{bpg}", flush=True)
-        b.set_groups(fpg, bpg)
-        b.run()
-        b.check()
-        for k in range(len(fr)):
-            _same(b.outputs(k), ref[k], f"CT batch {fpg}x{bpg} frame {k}")
+        for staged in (False, True):  # FP32 caches: both attention forms
+            print(f"case CT batch groups {fpg}x{bpg} staged {staged}", flush=True)
+            b.set_groups(fpg, bpg)
+            b.set_attention(staged)
+            b.run()
+            b.check()
+            for k in range(len(fr)):
+                _same(b.outputs(k), ref[k], f"CT batch {fpg}x{bpg} staged {staged} frame {k}")
     b.capture()
     for rep in range(2):
         b.run()
@@ -141,13 +143,17 @@ def test_ct_batch_1080p_equals_encode(P):
     model = P.Model(cfg, Wt)
     fr = _frames(cfg, [(68, 120, 0), (68, 120, 2)], 310)
     ref = [P.pswa_encode_params(model, f["latents"], f["hyper"], f["prev"]) for f in fr]
-    print("case CT batch 1080p I + P", flush=True)
     b = P.Batch(model, fr)
-    b.set_groups(1, 8)
-    b.run()
-    b.check()
-    for k in range(len(fr)):
-        _same(b.outputs(k), ref[k], f"CT batch 1080p frame {k}")
+    # the groupings of the benchmark's 32-frame batch (two frames per group of
+    # 16 blocks, LDS-staged attention) and of one frame per 8 blocks
+    for fpg, bpg, staged in ((2, 16, True), (1, 8, False)):
+        print(f"case CT batch 1080p I + P groups {fpg}x{bpg} staged {staged}", flush=True)
+        b.set_groups(fpg, bpg)
+        b.set_attention(staged)
+        b.run()
+        b.check()
+        for k in range(len(fr)):
+            _same(b.outputs(k), ref[k], f"CT batch 1080p {fpg}x{bpg} frame {k}")
 
 
 def test_unbuilt_ct_paths_are_refused(P):
