@@ -365,11 +365,11 @@ pswa_status pswa_batch_set_xcd_barrier(pswa_batch* batch, int on);
 /* Attention form of the wavefront schedule (an autotuner knob; both give
  * the same bits): staged != 0 stages, per tile of up to four consecutive
  * diagonal rows of a frame, the union of their causal windows (K and V rows
- * of a few heads at a time, the queries and the window biases) in LDS with
- * direct global-to-LDS loads and computes the rows' items from LDS; 0 lets
- * every lane load its key's rows from global memory. The cyclic schedule
- * and models with BF16 key/value caches (BF16, FP8) reject staged != 0
- * (PSWA_E_UNSUPPORTED). Drops a captured graph.
+ * of a few heads at a time, as the caches hold them: FP32, or BF16 for BF16
+ * and FP8 models, the queries and the window biases) in LDS with direct
+ * global-to-LDS loads and computes the rows' items from LDS; 0 lets every
+ * lane load its key's rows from global memory. The cyclic schedule rejects
+ * staged != 0 (PSWA_E_UNSUPPORTED). Drops a captured graph.
  * pswa_batch_attention returns the current form (-1 for a null batch). */
 pswa_status pswa_batch_set_attention(pswa_batch* batch, int staged);
 int pswa_batch_attention(const pswa_batch* batch);

@@ -89,9 +89,9 @@ struct pswa_batch {
 
 namespace {
 
-// LDS-staged window tiles serve the wavefront schedule of models whose
-// key/value caches are FP32.
-bool staged_ok(const pswa_model* m) { return !m->x.cycle && !m->w.kv16; }
+// LDS-staged window tiles serve the wavefront schedule (FP32 or BF16
+// key/value caches).
+bool staged_ok(const pswa_model* m) { return !m->x.cycle; }
 
 // Frame layout of a batch and the worst-case sizes of any grouping: rows of
 // all groups together (at most the sum of each frame's longest diagonal)
@@ -820,7 +820,7 @@ pswa_status pswa_batch_set_attention(pswa_batch* b, int staged) {
   if (!b) return fail(PSWA_E_ARG, "batch is null");
   if (staged && !staged_ok(b->model))
     return fail(PSWA_E_UNSUPPORTED,
-                "LDS-staged window tiles serve the wavefront schedule with FP32 key/value caches");
+                "LDS-staged window tiles serve the wavefront schedule only");
   b->attn_staged = staged ? 1 : 0;
   drop_graph(b);
   return PSWA_OK;

@@ -755,22 +755,26 @@ __host__ __device__ inline size_t attn_lds_bytes(int) { return 0; }
 // query rows lo .. hi whose windows hold ii (windows of neighbouring
 // diagonal rows overlap, s <= 2r + 1), clipped to the frame; cells are
 // numbered image row by image row, and the accumulator's null key and value
-// follow as one more cell. A cell's data starts 16 (cell mod 8) bytes into
-// its slot, so that lanes reading different cells spread over the banks.
+// (the row after the last position of its cache) follow as one more cell. A
+// cell's data starts 16 (cell mod 8) bytes into its slot, so that lanes
+// reading different cells spread over the banks. BF16 caches (kv16) are
+// staged as they are, twice as many heads per slot, and widened on reading.
 constexpr int kStageRows = kWaves;             // query rows of a tile (one per wave)
 constexpr int kStageImgRows = kStageRows + 4;  // image rows of a tile (r <= 4)
 constexpr int kStageCells = 133;               // window cells (at most 132: r = 4, s = 5) + null
 constexpr int kStageCellBytes = 896;           // 56 16-byte slots per cell
 // heads staged together: their K and V rows fill at most 48 of a cell's 56
 // 16-byte slots (the rest is room for the skew of up to 7 slots)
-__host__ __device__ inline constexpr int stage_heads(int dh) { return 96 / dh > 0 ? 96 / dh : 1; }
+__host__ __device__ inline constexpr int stage_heads(int dh, bool kv16 = false) {
+  return (96 / dh > 0 ? 96 / dh : 1) * (kv16 ? 2 : 1);
+}
 // byte offsets of the queries and the biases after the cells
 constexpr size_t kStageQOff = (size_t)kStageCells * kStageCellBytes;
-__host__ __device__ inline constexpr size_t stage_bias_off(int dh) {
-  return kStageQOff + (size_t)kStageRows * stage_heads(dh) * dh * 4;
+__host__ __device__ inline constexpr size_t stage_bias_off(int dh, bool kv16 = false) {
+  return kStageQOff + (size_t)kStageRows * stage_heads(dh, kv16) * dh * 4;
 }
-__host__ __device__ inline size_t attn_stage_lds_bytes(int dh) {
-  return stage_bias_off(dh) + (size_t)stage_heads(dh) * 64 * 4;
+__host__ __device__ inline size_t attn_stage_lds_bytes(int dh, bool kv16 = false) {
+  return stage_bias_off(dh, kv16) + (size_t)stage_heads(dh, kv16) * 64 * 4;
 }
 
 // ------------------------------------------------------------ symbol items

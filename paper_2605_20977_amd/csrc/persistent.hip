@@ -28,7 +28,7 @@ __global__ void k_zero_ints(int* p, int n) {
 }  // namespace
 
 size_t persistent_args_lds_offset(const NetDims& x, int prec, int rtile) {
-  size_t b = x.cycle ? attn_lds_bytes(x.dh) : attn_stage_lds_bytes(x.dh);
+  size_t b = x.cycle ? attn_lds_bytes(x.dh) : attn_stage_lds_bytes(x.dh, prec != 0);
   for (int K : {x.F, x.d, x.C}) {
     size_t g = prec ? qgemm_lds_bytes(K, prec, rtile) : gemm_lds_bytes(K);
     if (prec && rtile == 16 && K <= kWideMaxK) g = std::max(g, qgemm_lds_bytes(K, prec, kMBqWide));

@@ -201,9 +201,10 @@ __device__ __forceinline__ void lds_load4(const float* src, float* lds) {
 }
 
 // Keys of a staged tile: window cells and the null slot from LDS (cell slot
-// of kStageCellBytes, data 16 (cell mod 8) bytes in, head hh's K then V row),
-// temporal keys of P-frames from global memory (FP32 caches).
-template <int DH>
+// of kStageCellBytes, data 16 (cell mod 8) bytes in, head hh's K then V row,
+// FP32 or BF16 as the caches hold them), temporal keys of P-frames from
+// global memory.
+template <int DH, bool KV16>
 struct StagedKeys {
   struct Slot {
     int cell;  // -1: a temporal key, in raw
@@ -235,20 +236,33 @@ struct StagedKeys {
     if (!slot_addr(a, kk, hd, DH, pi, pj, fi, n_sp, 0, s)) return false;
     sl.cell = -1;
     sl.raw.b = ldg(a.bias + s.bias);
-    kv_issue<DH, false>(s.base, s.e, a.d, sl.raw);
+    kv_issue<DH, KV16>(s.base, s.e, a.d, sl.raw);
     return true;
   }
   __device__ __forceinline__ void get(const Slot& sl, float4* kr, float4* vr, float& b) {
     b = sl.raw.b;
     if (sl.cell < 0) {
-      kv_widen<DH, false>(sl.raw, kr, vr);
+      kv_widen<DH, KV16>(sl.raw, kr, vr);
       return;
     }
-    const float* p = smem + sl.cell * (kStageCellBytes / 4) + 4 * (sl.cell & 7) + hh * 2 * DH;
+    const float* p = smem + sl.cell * (kStageCellBytes / 4) + 4 * (sl.cell & 7);
+    if constexpr (KV16) {
+      const int4* q = reinterpret_cast<const int4*>(reinterpret_cast<const uint16_t*>(p) +
+                                                    hh * 2 * DH);
+      KeyRaw<DH> r;
 #pragma unroll
-    for (int e = 0; e < DH / 4; ++e) {
-      kr[e] = *reinterpret_cast<const float4*>(p + 4 * e);
-      vr[e] = *reinterpret_cast<const float4*>(p + DH + 4 * e);
+      for (int c = 0; c < DH / 8; ++c) {
+        r.k[c] = q[c];
+        r.v[c] = q[DH / 8 + c];
+      }
+      kv_widen<DH, true>(r, kr, vr);
+    } else {
+      p += hh * 2 * DH;
+#pragma unroll
+      for (int e = 0; e < DH / 4; ++e) {
+        kr[e] = *reinterpret_cast<const float4*>(p + 4 * e);
+        vr[e] = *reinterpret_cast<const float4*>(p + DH + 4 * e);
+      }
     }
   }
 };
@@ -261,22 +275,24 @@ struct StagedKeys {
 // and the heads' window biases into LDS, then each wave computes its row's
 // items from LDS (temporal keys of P-frames are read from global memory).
 // The arithmetic of every item is attn_core's, as in every other path.
-template <int DH>
+// KV16: the caches hold BF16 (element offsets as for FP32).
+template <int DH, bool KV16>
 __device__ __forceinline__ void attn_phase_staged(const AttnArgs& a, float* smem, int rank,
                                                   int nb) {
-  constexpr int HT = stage_heads(DH);
-  constexpr int QH = DH / 2;                 // 16-byte pieces of one head's K and V rows
+  constexpr int HT = stage_heads(DH, KV16);
+  constexpr int EP = KV16 ? 8 : 4;           // cache elements per 16-byte piece
+  constexpr int QH = 2 * DH / EP;            // 16-byte pieces of one head's K and V rows
   constexpr int CF = kStageCellBytes / 4;    // floats per cell slot
   __shared__ int s_base[kStageImgRows + 1], s_c0[kStageImgRows], s_gpos[kStageCells];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = a.r, s = r + 1, d = a.d;
   const int n_sp = attn_n_sp(a);
   float* qtile = smem + kStageQOff / 4;
-  float* btile = smem + stage_bias_off(DH) / 4;
+  float* btile = smem + stage_bias_off(DH, KV16) / 4;
   // this lane's piece of a cell: head lh of the group, 16 bytes lq of that
-  // head's K (lq < DH/4) or V row
+  // head's K (lq < QH/2) or V row, as an element offset in the position's row
   const int lh = lane / QH, lq = lane % QH;
-  const int lpart = lh * DH + (lq < DH / 4 ? 4 * lq : d - DH + 4 * lq);
+  const int lpart = lh * DH + (lq < QH / 2 ? EP * lq : d - DH + EP * lq);
   const int rpb = (a.M + nb - 1) / nb;
   const int m_lo = min(a.M, rank * rpb), m_hi = min(a.M, m_lo + rpb);
   for (int m0 = m_lo; m0 < m_hi;) {
@@ -344,12 +360,13 @@ __device__ __forceinline__ void attn_phase_staged(const AttnArgs& a, float* smem
     for (int h0 = 0; h0 < a.heads; h0 += HT) {
       const int nh = min(HT, a.heads - h0);
       // K/V rows of the heads: cell c by wave c mod 4, 16 bytes per lane
+      // (the null key and value: the cache's row after its last position)
       if (lane < nh * QH) {
         for (int c = wave; c < ncell; c += kWaves) {
-          const float* src = c < cells
-              ? a.kv + (size_t)s_gpos[c] * 2 * d + h0 * DH + lpart
-              : (lq < DH / 4 ? a.knull + (h0 + lh) * DH + 4 * lq
-                             : a.vnull + (h0 + lh) * DH + 4 * lq - DH);
+          const size_t e = (size_t)(c < cells ? s_gpos[c] : a.HWt) * 2 * d + h0 * DH + lpart;
+          const float* src = KV16 ? reinterpret_cast<const float*>(
+                                        reinterpret_cast<const uint16_t*>(a.kv) + e)
+                                  : a.kv + e;
           lds_load16(src, smem + c * CF + 4 * (c & 7));
         }
       }
@@ -362,8 +379,8 @@ __device__ __forceinline__ void attn_phase_staged(const AttnArgs& a, float* smem
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
       if (live) {
-        // the stage's heads in pairs, one per half-wave (FP32 caches: one key
-        // per round, as in attn_pair_at)
+        // the stage's heads in pairs, one per half-wave (keys per round as in
+        // attn_pair_at: one for FP32 caches, two for BF16)
         for (int hp = 0; hp < nh; hp += 2) {
           const int hs = hp + ((threadIdx.x >> 5) & 1);
           const bool hlive = hs < nh;
@@ -372,9 +389,10 @@ __device__ __forceinline__ void attn_phase_staged(const AttnArgs& a, float* smem
 #pragma unroll
           for (int e = 0; e < DH / 4; ++e)
             q4[e] = *reinterpret_cast<const float4*>(qtile + wave * HT * DH + hh * DH + 4 * e);
-          StagedKeys<DH> src{a, smem, btile, s_base, s_c0, h0 + hh, hh, wave, pi, pj, n_sp, cells,
-                             fi};
-          attn_core<DH, 1>(q4, n_keys, hlive, src, a.out + (size_t)m * a.ldo + (h0 + hh) * DH);
+          StagedKeys<DH, KV16> src{a,  smem, btile, s_base, s_c0, h0 + hh, hh,
+                                   wave, pi, pj, n_sp, cells, fi};
+          attn_core<DH, KV16 ? 2 : 1>(q4, n_keys, hlive, src,
+                                      a.out + (size_t)m * a.ldo + (h0 + hh) * DH);
         }
       }
       __syncthreads();
@@ -454,7 +472,7 @@ __global__ void __launch_bounds__(kThreads) k_persistent(PersistArgs P) {
     // (g0, the accumulator's query projection, depends on the hyperprior
     // tokens only: it runs for every position before the launch)
     if (staged)
-      attn_phase_staged<DH>(lds_uniform(at + 0), smem, rank, nb);
+      attn_phase_staged<DH, PREC != PSWA_PREC_F32>(lds_uniform(at + 0), smem, rank, nb);
     else
       attn_phase<DH, PREC != PSWA_PREC_F32>(lds_uniform(at + 0), rank, nb);
     PSWA_SYNC
@@ -464,7 +482,7 @@ __global__ void __launch_bounds__(kThreads) k_persistent(PersistArgs P) {
       gemm_phase<A_FLOAT, true, EPI_QKV, PREC, R>(lds_uniform(g + 2 + 4 * l), smem4, rstd, rank, nb);
       PSWA_SYNC
       if (staged)
-        attn_phase_staged<DH>(lds_uniform(at + 1 + l), smem, rank, nb);
+        attn_phase_staged<DH, PREC != PSWA_PREC_F32>(lds_uniform(at + 1 + l), smem, rank, nb);
       else
         attn_phase<DH, PREC != PSWA_PREC_F32>(lds_uniform(at + 1 + l), rank, nb);
       PSWA_SYNC

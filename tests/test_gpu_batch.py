@@ -258,8 +258,9 @@ def test_batch_barrier_forms_agree(P, tiny):
 def test_batch_attention_forms_agree(P, tiny):
     """LDS-staged window tiles and per-lane global key loads give the same
     bits, across groupings (tiles cut at frame borders and block runs),
-    I- and P-frames, frames narrower than a window; the cyclic schedule and
-    models with BF16 key/value caches refuse the staged form."""
+    I- and P-frames, frames narrower than a window, FP32 caches and the BF16
+    caches of BF16 and FP8 models; the cyclic schedule refuses the staged
+    form."""
     cfg, Wt, model = tiny
     sizes = [(7, 9, 0), (16, 16, 2), (5, 13, 0), (12, 4, 2), (1, 1, 0), (3, 30, 2), (9, 2, 0)]
     fr = _frames(cfg, sizes, 1700)
@@ -275,11 +276,23 @@ def test_batch_attention_forms_agree(P, tiny):
             b.check()
             for k in range(len(fr)):
                 _assert_same(b.outputs(k), ref[k], f"staged={staged} {fpg}x{bpg} frame {k}")
+    for prec in ("bf16", "fp8"):
+        mq = P.make_model(cfg, Wt, prec, fr[:2])
+        refq = [_per_frame(P, mq, f) for f in fr]
+        bq = P.Batch(mq, fr)
+        for fpg, bpg in ((1, 3), (7, 5)):
+            for staged in (True, False):
+                print(f"case attention {prec} staged={staged} groups {fpg}x{bpg}", flush=True)
+                bq.set_groups(fpg, bpg)
+                bq.set_attention(staged)
+                assert bq.attention_staged == staged
+                bq.run()
+                bq.check()
+                for k in range(len(fr)):
+                    _assert_same(bq.outputs(k), refq[k],
+                                 f"{prec} staged={staged} {fpg}x{bpg} frame {k}")
     cm = P.Model(synth.TINY_CYCLIC, synth.model_weights(synth.TINY_CYCLIC, 1))
     bc = P.Batch(cm, _frames(synth.TINY_CYCLIC, [(8, 8, 0)], 1800))
     with pytest.raises(P.PswaError):
         bc.set_attention(True)
-    bm = P.Batch(P.Model(cfg, Wt, "bf16"), fr[:1])
-    with pytest.raises(P.PswaError):
-        bm.set_attention(True)
-    assert not bm.attention_staged
+    assert not bc.attention_staged

@@ -87,7 +87,8 @@ MIX = [(H, W, npv) for (H, W) in synth.BATCH_MIX for npv in (0, 2)]
 @pytest.mark.parametrize("prec", ["bf16", "fp8"])
 def test_mixed_1080p_batch_every_timed_instance(P, full, prec):
     """One frame of every grid size of the mixed batch, I and P, through the
-    row tiles 16 and 32 and both groupings the benchmark times."""
+    row tiles 16 and 32 and both groupings the benchmark times, and both
+    attention forms (global key loads, LDS-staged window tiles)."""
     cfg, Wt = full
     model = P.make_model(cfg, Wt, prec, synth.calibration_frames(cfg))
     fr = _frames(cfg, MIX, synth.CONFIG_SEEDS["batch"][0])
@@ -103,15 +104,25 @@ def test_mixed_1080p_batch_every_timed_instance(P, full, prec):
             b.check()
             for k in range(len(fr)):
                 _assert_same(b.outputs(k), ref[k], f"{prec} {fpg}x{bpg} rtile {rt} frame {k}")
+    b.set_rtile(16)
+    b.set_attention(True)
+    for fpg, bpg in ((2, 16), (1, 8)):
+        print(f"case mixed 1080p {prec} groups {fpg}x{bpg} rtile 16 staged", flush=True)
+        b.set_groups(fpg, bpg)
+        b.run()
+        b.check()
+        for k in range(len(fr)):
+            _assert_same(b.outputs(k), ref[k], f"{prec} {fpg}x{bpg} staged frame {k}")
     # the 34 x 60 P-frame against the oracle
     _against_oracle(cfg, Wt, fr[3], ref[3], prec, 6, 31, f"mixed {prec} 34x60 P")
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp8"])
 def test_headline_1080p_i_batch(P, full, prec):
-    """1080p-shaped I-frames, row tile 32, replayed from a HIP graph, in the
-    groupings the headline batches use: one frame x 8 workgroups, and four
-    frames sharing 4 workgroups."""
+    """1080p-shaped I-frames, replayed from a HIP graph, in the groupings the
+    headline batches use: one frame x 8 workgroups (row tile 32, global key
+    loads), and four frames sharing 4 workgroups (row tile 16, LDS-staged
+    attention)."""
     cfg, Wt = full
     model = P.make_model(cfg, Wt, prec, synth.calibration_frames(cfg))
     fr = _frames(cfg, [(68, 120, 0)] * 4, synth.CONFIG_SEEDS["1080p_I"][0])
@@ -119,7 +130,8 @@ def test_headline_1080p_i_batch(P, full, prec):
     b = P.Batch(model, fr)
     for fpg, bpg in ((1, 8), (4, 4)):
         b.set_groups(fpg, bpg)
-        b.set_rtile(32)
+        b.set_rtile(32 if fpg == 1 else 16)
+        b.set_attention(fpg == 4)
         b.capture()
         for rep in range(2):
             print(f"case headline 1080p {prec} groups {fpg}x{bpg} replay {rep}", flush=True)
@@ -134,7 +146,7 @@ def test_headline_1080p_i_batch(P, full, prec):
 @pytest.mark.parametrize("rt", [16, 32])
 def test_student_4k_bf16_batch_row_tiles(P, rt):
     """The 4K student (4 heads of 32) in BF16, one frame per group of 32
-    workgroups, at both row tiles."""
+    workgroups, at both row tiles (row tile 16 with LDS-staged attention)."""
     cfg = synth.STUDENT
     Wt = synth.model_weights(cfg, 51)
     model = P.make_model(cfg, Wt, "bf16")
@@ -144,6 +156,7 @@ def test_student_4k_bf16_batch_row_tiles(P, rt):
     b = P.Batch(model, fr)
     b.set_groups(1, 32)
     b.set_rtile(rt)
+    b.set_attention(rt == 16)
     print(f"case student 4K bf16 rtile {rt}", flush=True)
     b.run()
     b.check()
