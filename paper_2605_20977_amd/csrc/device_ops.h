@@ -551,10 +551,15 @@ __device__ __forceinline__ void kv_widen(const KeyRaw<DH>& r, float4* kr, float4
   }
 }
 
-// The arithmetic of one attention item, shared by every path. src.issue(kk,
-// slot) requests key slot kk (false: masked or outside the frame) and
-// src.get(slot, kr, vr, b) delivers its K and V rows and bias; q4 is the
-// lane's head's query, out its output row. live = false idles the half.
+// The arithmetic of one attention item, shared by every path.
+// src.issue(kk, want, slot) requests key slot kk (false: not wanted, masked
+// or outside the frame; the slot then holds harmless data that is never
+// used) and src.get(slot, kr, vr, b) delivers its K and V rows and bias; q4
+// is the lane's head's query, out its output row. live = false idles the
+// half. Every requested slot goes through the same straight-line update and
+// an unused one leaves the lane's state as it was by selection, so no load
+// or update sits behind a per-lane branch (the compiler's wait counters
+// then keep all NK slots' loads in flight together).
 template <int DH, int NK, class Source>
 __device__ __forceinline__ void attn_core(const float4* q4, int n_keys, bool live, Source& src,
                                           float* out) {
@@ -573,11 +578,13 @@ __device__ __forceinline__ void attn_core(const float4* q4, int n_keys, bool liv
 #pragma unroll
     for (int j = 0; j < NK; ++j) {
       const int kk = l32 + kHalf * (u + j);
-      ok[j] = live && kk < n_keys && src.issue(kk, sl[j]);
+      ok[j] = src.issue(kk, live && kk < n_keys, sl[j]);
     }
+    // every slot's loads are issued before the first is used
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int j = 0; j < NK; ++j) {
-      if (!ok[j]) continue;
+      const bool use = ok[j];
       float4 kr[DH / 4], vr[DH / 4];
       float b;
       src.get(sl[j], kr, vr, b);
@@ -588,15 +595,15 @@ __device__ __forceinline__ void attn_core(const float4* q4, int n_keys, bool liv
       const float mn = fmaxf(mx, lg);
       const float c_old = expf(mx - mn);  // 0 for the lane's first key (mx = -inf)
       const float pk = expf(lg - mn);
-      sum = sum * c_old + pk;
+      sum = use ? sum * c_old + pk : sum;
 #pragma unroll
       for (int e = 0; e < DH / 4; ++e) {
-        o[4 * e + 0] = fmaf(pk, vr[e].x, o[4 * e + 0] * c_old);
-        o[4 * e + 1] = fmaf(pk, vr[e].y, o[4 * e + 1] * c_old);
-        o[4 * e + 2] = fmaf(pk, vr[e].z, o[4 * e + 2] * c_old);
-        o[4 * e + 3] = fmaf(pk, vr[e].w, o[4 * e + 3] * c_old);
+        o[4 * e + 0] = use ? fmaf(pk, vr[e].x, o[4 * e + 0] * c_old) : o[4 * e + 0];
+        o[4 * e + 1] = use ? fmaf(pk, vr[e].y, o[4 * e + 1] * c_old) : o[4 * e + 1];
+        o[4 * e + 2] = use ? fmaf(pk, vr[e].z, o[4 * e + 2] * c_old) : o[4 * e + 2];
+        o[4 * e + 3] = use ? fmaf(pk, vr[e].w, o[4 * e + 3] * c_old) : o[4 * e + 3];
       }
-      mx = mn;
+      mx = use ? mn : mx;
     }
   }
 
@@ -640,14 +647,37 @@ __device__ __forceinline__ int attn_n_sp(const AttnArgs& a) {
   return a.cycle ? k1 * k1 : 2 * a.r * (a.r + 1) + (a.include_self ? 1 : 0);
 }
 
-// Where key slot kk of the query at (pi, pj) lives: the cache (kv or tkv)
-// and element offset of its K row for head hd, and its bias index (-1: no
-// bias, the null slot); false when the slot is masked or outside the frame.
+// Where key slot kk of the query at (pi, pj) lives: the cache (temporal:
+// tkv, else kv) and element offset of its K row for head hd, and its bias
+// index (-1: no bias, the null slot); false when the slot is masked or
+// outside the frame.
 struct SlotAddr {
-  const float* base;
+  bool temporal;
   size_t e;
   int bias;
 };
+// The two caches of an item: kv, and tkv as a byte distance from it, both in
+// scalar registers. The per-lane choice of cache is then an add of 0 or the
+// distance; a choice between two pointer fields becomes a choice between
+// their addresses, which keeps the fields in scratch memory, and the wait
+// for that scratch load serialises the key loads in flight.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+struct KvBases {
+  uint64_t kv, dt;
+  __device__ __forceinline__ const float* of(const SlotAddr& s) const {
+    const uint64_t add = s.temporal ? dt : 0;
+    return reinterpret_cast<const float*>(kv + add);
+  }
+};
+__device__ __forceinline__ KvBases kv_bases(const AttnArgs& a) {
+  const uint64_t kv = reinterpret_cast<uint64_t>(a.kv);
+  const uint64_t dt = a.tkv ? reinterpret_cast<uint64_t>(a.tkv) - kv : 0;
+  return KvBases{uniform_u64(kv), uniform_u64(dt)};
+}
 __device__ __forceinline__ bool slot_addr(const AttnArgs& a, int kk, int hd, int dh, int pi,
                                           int pj, const FrameInfo& fi, int n_sp, int step_p,
                                           SlotAddr& s) {
@@ -661,11 +691,11 @@ __device__ __forceinline__ bool slot_addr(const AttnArgs& a, int kk, int hd, int
       const int step_k = (ki + kj) % a.cycle;
       if (a.include_self ? step_k > step_p : step_k >= step_p) return false;
     }
-    s = SlotAddr{a.kv, (size_t)(fi.off + ki * fi.W + kj) * 2 * d + hd * dh, hd * a.nbias + kk};
+    s = SlotAddr{false, (size_t)(fi.off + ki * fi.W + kj) * 2 * d + hd * dh, hd * a.nbias + kk};
     return true;
   }
   if (a.knull && kk == n_sp) {
-    s = SlotAddr{a.kv, (size_t)a.HWt * 2 * d + hd * dh, -1};
+    s = SlotAddr{false, (size_t)a.HWt * 2 * d + hd * dh, -1};
     return true;
   }
   const int r = a.r, k1 = 2 * r + 1;
@@ -673,7 +703,7 @@ __device__ __forceinline__ bool slot_addr(const AttnArgs& a, int kk, int hd, int
   const int tau = t / (k1 * k1), rem = t % (k1 * k1);
   const int ki = pi + rem / k1 - r, kj = pj + rem % k1 - r;
   if (ki < 0 || ki >= fi.H || kj < 0 || kj >= fi.W) return false;
-  s = SlotAddr{a.tkv, ((size_t)tau * a.HWt + (size_t)(fi.off + ki * fi.W + kj)) * 2 * d + hd * dh,
+  s = SlotAddr{true, ((size_t)tau * a.HWt + (size_t)(fi.off + ki * fi.W + kj)) * 2 * d + hd * dh,
                hd * a.nbias + n_sp + t};
   return true;
 }
@@ -690,20 +720,24 @@ template <int DH, bool KV16>
 struct GlobalKeys {
   struct Slot {
     KeyRaw<DH> raw;
+    bool no_bias;  // the null slot: bias 0 (chosen when the slot is used)
   };
   const AttnArgs& a;
+  KvBases kb;
   int hd, pi, pj, n_sp, step_p;
   FrameInfo fi;
-  __device__ __forceinline__ bool issue(int kk, Slot& sl) {
+  __device__ __forceinline__ bool issue(int kk, bool want, Slot& sl) {
     SlotAddr s;
-    if (!slot_addr(a, kk, hd, DH, pi, pj, fi, n_sp, step_p, s)) return false;
-    sl.raw.b = s.bias >= 0 ? ldg(a.bias + s.bias) : 0.f;
-    kv_issue<DH, KV16>(s.base, s.e, a.d, sl.raw);
-    return true;
+    const bool ok = want && slot_addr(a, kk, hd, DH, pi, pj, fi, n_sp, step_p, s);
+    if (!ok) s = SlotAddr{false, 0, 0};  // unused: the first row of kv
+    sl.no_bias = s.bias < 0;
+    sl.raw.b = ldg(a.bias + (s.bias >= 0 ? s.bias : 0));
+    kv_issue<DH, KV16>(kb.of(s), s.e, a.d, sl.raw);
+    return ok;
   }
   __device__ __forceinline__ void get(const Slot& sl, float4* kr, float4* vr, float& b) {
     kv_widen<DH, KV16>(sl.raw, kr, vr);
-    b = sl.raw.b;
+    b = sl.no_bias ? 0.f : sl.raw.b;
   }
 };
 
@@ -721,7 +755,7 @@ __device__ __forceinline__ void attn_pair_at(const AttnArgs& a, int m, int p, in
   float4 q4[DH / 4];
 #pragma unroll
   for (int e = 0; e < DH / 4; ++e) q4[e] = ldg4(qp + 4 * e);
-  GlobalKeys<DH, KV16> src{a, hd, pi, pj, n_sp, a.cycle ? (pi + pj) % a.cycle : 0, fi};
+  GlobalKeys<DH, KV16> src{a, kv_bases(a), hd, pi, pj, n_sp, a.cycle ? (pi + pj) % a.cycle : 0, fi};
   attn_core<DH, KV16 ? 2 : 1>(q4, attn_n_keys(a, fi), live, src,
                               a.out + (size_t)m * a.ldo + hd * DH);
 }

@@ -216,7 +216,10 @@ struct StagedKeys {
   const int *s_base, *s_c0;
   int hd, hh, wave, pi, pj, n_sp, cells;
   FrameInfo fi;
-  __device__ __forceinline__ bool issue(int kk, Slot& sl) {
+  __device__ __forceinline__ bool issue(int kk, bool want, Slot& sl) {
+    sl.cell = 0;  // unused slots read cell 0, which is never used
+    sl.raw.b = 0.f;
+    if (!want) return false;
     if (kk < n_sp) {
       int da, db;
       window_offset(a, kk, da, db);
@@ -236,7 +239,7 @@ struct StagedKeys {
     if (!slot_addr(a, kk, hd, DH, pi, pj, fi, n_sp, 0, s)) return false;
     sl.cell = -1;
     sl.raw.b = ldg(a.bias + s.bias);
-    kv_issue<DH, KV16>(s.base, s.e, a.d, sl.raw);
+    kv_issue<DH, KV16>(a.tkv, s.e, a.d, sl.raw);  // temporal keys only
     return true;
   }
   __device__ __forceinline__ void get(const Slot& sl, float4* kr, float4* vr, float& b) {

@@ -127,7 +127,7 @@ struct AttnArgs {
   int kv16;                    // kv and tkv hold BF16 (element offsets as for FP32)
   const float* bias; int nbias;  // [heads][nbias]
   const float* knull;          // accumulator null slot (null in layer mode): its key and value
-                               // are read from row HWt of kv (the LDS-staged form reads them here)
+                               // are read from row HWt of kv (both attention forms)
   const float* vnull;
   int include_self;            // layer mode: the query's own key
   int cycle;                   // 0: causal half-window; c: full window, masked by
