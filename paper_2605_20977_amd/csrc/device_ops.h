@@ -741,17 +741,17 @@ struct GlobalKeys {
   }
 };
 
-// Item (row m, head pair p) with the row's global position gp and frame fi
-// already known, every key from global memory.
+// Item (row m, head pair p) with the row's global position gp, frame fi and
+// query row qr already known, every key from global memory.
 template <int DH, bool KV16>
 __device__ __forceinline__ void attn_pair_at(const AttnArgs& a, int m, int p, int gp,
-                                             const FrameInfo& fi) {
+                                             const FrameInfo& fi, int qr) {
   const int hd = 2 * p + ((threadIdx.x >> 5) & 1);
   const bool live = hd < a.heads;
   const int lp = gp - fi.off;
   const int pi = lp / fi.W, pj = lp % fi.W;
   const int n_sp = attn_n_sp(a);
-  const float* qp = a.q + (size_t)map_row(a.qrow, m) * a.ldq + min(hd, a.heads - 1) * DH;
+  const float* qp = a.q + (size_t)qr * a.ldq + min(hd, a.heads - 1) * DH;
   float4 q4[DH / 4];
 #pragma unroll
   for (int e = 0; e < DH / 4; ++e) q4[e] = ldg4(qp + 4 * e);
@@ -769,7 +769,7 @@ __device__ __forceinline__ void attn_item(const AttnArgs& a, int item) {
   const int np = attn_pairs(a.heads);
   if (item >= a.M * np) return;
   const int m = item / np, p = item % np;
-  attn_pair_at<DH, KV16>(a, m, p, map_row(a.pos, m), attn_frame(a, m));
+  attn_pair_at<DH, KV16>(a, m, p, map_row(a.pos, m), attn_frame(a, m), map_row(a.qrow, m));
 }
 
 // Attention needs no LDS (the lanes are merged in registers).

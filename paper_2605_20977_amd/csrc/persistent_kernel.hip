@@ -160,13 +160,14 @@ __device__ __forceinline__ void attn_phase(const AttnArgs& a, int rank, int nb) 
       min(items, (rank * kWaves + (int)(threadIdx.x >> 6)) * per));
   const int i1 = min(items, i0 + per);
   for (int b0 = i0; b0 < i1; b0 += PF) {
-    int gp[PF], fr[PF];
+    int gp[PF], fr[PF], qr[PF];
     FrameInfo fi[PF];
 #pragma unroll
     for (int i = 0; i < PF; ++i) {
       const int m = min(b0 + i, i1 - 1) % a.M;
       gp[i] = a.pos ? load_uniform(a.pos + m) : m;
       fr[i] = a.fid ? load_uniform(a.fid + m) : 0;
+      qr[i] = a.qrow ? load_uniform(a.qrow + m) : m;
     }
 #pragma unroll
     for (int i = 0; i < PF; ++i) fi[i] = a.fid ? load_uniform(a.frames + fr[i]) : a.frame0;
@@ -174,7 +175,7 @@ __device__ __forceinline__ void attn_phase(const AttnArgs& a, int rank, int nb) 
     for (int i = 0; i < PF; ++i) {
       const int item = b0 + i;
       if (item >= i1) break;  // uniform across the wave
-      attn_pair_at<DH, KV16>(a, item % a.M, item / a.M, gp[i], fi[i]);
+      attn_pair_at<DH, KV16>(a, item % a.M, item / a.M, gp[i], fi[i], qr[i]);
     }
   }
 }
